@@ -1,0 +1,162 @@
+/*
+ * hubbard.h -- C ABI of the MI355X (gfx950) state-vector engine for the
+ * Hubbard Hamiltonian-variational ansatz.
+ *
+ * The model is the single-band Hubbard Hamiltonian of Eq. (1) of Alvertis et
+ * al., "Classical Benchmarks for Variational Quantum Eigensolver Simulations
+ * of the Hubbard Model", generalised as in Eq. (2), (15) and (16) to a
+ * hopping t_b and an off-site interaction V_b per nearest-neighbour bond and
+ * an on-site energy eps_i per site:
+ *
+ *   H = sum_b sum_sigma (-t_b)(a+_{i sigma} a_{j sigma} + h.c.)
+ *     + U sum_i n_{i up} n_{i dn} + sum_b V_b n_i n_j + sum_i eps_i n_i,
+ *   n_i = n_{i up} + n_{i dn}, every unordered bond b = (i, j) counted once.
+ *
+ * The circuit is Eq. (3) with the Hamiltonian-variational layer of Eq. (7):
+ * each layer applies exp(-i th_0 D) (D = every diagonal term of H: U, V, eps)
+ * and then exp(-i th_g H_hop,g) for each hopping group g in order, where the
+ * groups split the bonds into sets of mutually commuting terms.  Parameters
+ * are layer-major: theta[l * params_per_layer + slot], slot 0 = D.
+ *
+ * Encoding (Sec. 2.2.1): Jordan-Wigner with a_q = (prod_{r<q} Z_r) sigma^-_q;
+ * sites are row-major s = x*ny + y; qubit q = s + nsites*spin (spin 0 = up),
+ * i.e. all spin-up qubits below all spin-down qubits; bit q of an amplitude
+ * index is the occupation of qubit q.  The start state is the checkerboard
+ * product state of Sec. 2.1: site (x, y) holds spin up when x+y is even and
+ * spin down otherwise, amplitude +1.
+ *
+ * State vectors are complex128 (two doubles, real then imaginary) of length
+ * 2^n_qubits in device memory, at most 32 qubits.
+ *
+ * Conventions for every call:
+ *   - Pointers whose name ends in _dev are device pointers (hipMalloc'd or
+ *     from a torch CUDA/HIP tensor); all others are host pointers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device calls are asynchronous on that stream; the status they return
+ *     reports argument and launch errors only, and a kernel fault surfaces at
+ *     the caller's next synchronisation.
+ *   - No call allocates device memory except hubbard_create's lazily
+ *     uploaded tables (a few KiB per handle and device, freed by
+ *     hubbard_destroy).  Vectors and scratch are caller-owned: the caller
+ *     asks hubbard_workspace_size for the byte count and passes a buffer.
+ *   - Every call returns a hubbard_status; on failure hubbard_last_error()
+ *     returns a message (thread-local, valid until the next call on the same
+ *     thread).  No C++ exception crosses this boundary.
+ *   - A handle may be used from one host thread at a time; calls that share
+ *     a workspace on different streams race.
+ */
+#ifndef HUBBARD_H
+#define HUBBARD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HUBBARD_OK = 0,
+    HUBBARD_ERR_ARG = 1,     /* invalid argument (shape, range, aliasing, NULL) */
+    HUBBARD_ERR_SIZE = 2,    /* workspace smaller than hubbard_workspace_size */
+    HUBBARD_ERR_DEVICE = 3,  /* HIP runtime error (launch, copy, attribute) */
+    HUBBARD_ERR_NOMEM = 4,   /* host or device allocation of internal tables failed */
+    HUBBARD_ERR_STATE = 5    /* call not valid for this handle (e.g. destroyed) */
+} hubbard_status;
+
+typedef struct hubbard_model *hubbard_t;
+
+/* Lattice model, Eq. (1)/(2)/(15)/(16).  All pointers are host pointers,
+ * read during hubbard_create only.
+ *   nx, ny          rows and columns (a chain is nx = 1); 1 <= nx*ny <= 16.
+ *   periodic_x/_y   nonzero: wrap bond between the last and first row/column;
+ *                   needs that length >= 3 (and even with default groups).
+ *   t_bond          n_bonds hoppings in canonical bond order (NULL: all 1).
+ *   U               on-site interaction.
+ *   V_bond          n_bonds nearest-neighbour interactions (NULL: all 0).
+ *   eps_site        nx*ny on-site energies (NULL: all 0).
+ *   bond_group      n_bonds group ids >= 0 (NULL: default rule); groups are
+ *                   applied in increasing id, empty ids skipped, and each
+ *                   group must be a matching (no site in two of its bonds).
+ *
+ * Canonical bond order: every horizontal bond (x,y)-(x,y+1) by start site
+ * row-major, the periodic wrap (x,ny-1)-(x,0) right after its row; then every
+ * vertical bond (x,y)-(x+1,y) by start site row-major, wraps (nx-1,y)-(0,y)
+ * last.  Default groups (the commuting split of Eq. (7) into h1, v1, h2, v2):
+ * horizontal bonds by the parity of the start column, vertical bonds by the
+ * parity of the start row; a direction of length 2 whose transverse length is
+ * >= 3 splits by the transverse parity instead. */
+typedef struct {
+    int32_t nx, ny;
+    int32_t periodic_x, periodic_y;
+    const double *t_bond;
+    double U;
+    const double *V_bond;
+    const double *eps_site;
+    const int32_t *bond_group;
+} hubbard_desc;
+
+/* Build a model handle from a lattice description (host only; no GPU work).
+ * Errors: HUBBARD_ERR_ARG for an invalid lattice, a non-matching group, more
+ * than 32 qubits or a non-finite coefficient; HUBBARD_ERR_NOMEM. */
+hubbard_status hubbard_create(const hubbard_desc *desc, hubbard_t *out);
+
+/* Release the handle and its device tables (synchronises nothing; the caller
+ * must not destroy a handle with work still queued on a stream). */
+void hubbard_destroy(hubbard_t h);
+
+/* Host-side description of the handle.  Any out pointer may be NULL. */
+hubbard_status hubbard_query(hubbard_t h, int32_t *n_qubits, int32_t *n_bonds,
+                             int32_t *n_groups, int32_t *params_per_layer,
+                             uint64_t *neel_index);
+
+/* Bond list in canonical order: sites bi[b], bj[b] and the 0-based group slot
+ * (application order) of each bond; each array holds n_bonds entries. */
+hubbard_status hubbard_bonds(hubbard_t h, int32_t *bi, int32_t *bj, int32_t *group);
+
+const char *hubbard_last_error(void);
+
+/* Operations for hubbard_workspace_size. */
+enum {
+    HUBBARD_OP_ENERGY = 0,       /* energy():      psi + reduction partials */
+    HUBBARD_OP_ENERGY_GRAD = 1   /* energy_grad(): psi + lambda + partials */
+};
+
+/* Bytes of device workspace needed by energy()/energy_grad() for n_layers. */
+hubbard_status hubbard_workspace_size(hubbard_t h, int32_t n_layers, int32_t op,
+                                      size_t *bytes);
+
+/* psi_dev <- checkerboard start state |b0> (2^n complex128 written). */
+hubbard_status hubbard_init_neel(hubbard_t h, void *psi_dev, void *stream);
+
+/* Eq. (3)/(7): psi_dev <- U_P(theta_P) ... U_1(theta_1) psi_dev, in place on a
+ * caller-owned vector of 2^n complex128.  theta_dev holds
+ * n_layers * params_per_layer doubles in device memory.  n_layers >= 0. */
+hubbard_status ansatz_apply(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                            void *psi_dev, void *stream);
+
+/* Matrix-free H|psi> (Eq. (4)'s operator): out_dev <- H psi_dev.  Both are
+ * 2^n complex128; out_dev must not overlap psi_dev (HUBBARD_ERR_ARG). */
+hubbard_status hamiltonian_apply(hubbard_t h, const void *psi_dev, void *out_dev,
+                                 void *stream);
+
+/* Eq. (4): E_dev[0] <- <psi(theta)|H|psi(theta)> with psi(theta) prepared
+ * from the start state in the workspace.  ws_dev must hold
+ * hubbard_workspace_size(..., HUBBARD_OP_ENERGY) bytes (HUBBARD_ERR_SIZE). */
+hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                      double *E_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Energy and its gradient by the adjoint recursion of Sec. 2.1:
+ * grad_dev[k] = dE/dtheta_k = 2 Im <lambda_k| G_k |psi_k> for all
+ * P = n_layers * params_per_layer parameters, computed in one reverse sweep
+ * that un-applies the gates to psi and lambda = H psi in the workspace.
+ * ws_dev must hold hubbard_workspace_size(..., HUBBARD_OP_ENERGY_GRAD). */
+hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                           double *E_dev, double *grad_dev, void *ws_dev,
+                           size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HUBBARD_H */

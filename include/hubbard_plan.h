@@ -1,0 +1,49 @@
+/*
+ * hubbard_plan.h -- host-only introspection and tuning of the pass schedule
+ * behind include/hubbard.h.  None of these calls touches a GPU.
+ *
+ * A pass loads tiles of 2^k amplitudes whose index bits are k chosen qubits
+ * (always including the lowest c bits of the amplitude index, for contiguous
+ * loads), applies an ordered list of operations of the Eq. (7) layer (or of
+ * H for the Hamiltonian passes) whose qubits all lie in the tile, and stores
+ * the tiles back.  Operations keep the circuit order of Eq. (3) except where
+ * they commute (hopping terms on disjoint qubit pairs; diagonal terms).
+ */
+#ifndef HUBBARD_PLAN_H
+#define HUBBARD_PLAN_H
+
+#include "hubbard.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Flat dump of a schedule for n_layers.  which: 0 forward passes, 1 H passes
+ * (energy_grad), 2 reverse passes (energy_grad), 3 expectation passes
+ * (energy).  Layout (int32): n_passes, then per pass: k, k tile bit
+ * positions, flags, n_ops, then per op: kind (0 diagonal, 1 hop), param
+ * (-1 for H terms), p, q (hop qubits, -1 for diagonal), umask, emask, n_v,
+ * n_v V-bond indices.  *len receives the length; buf may be NULL to size it;
+ * HUBBARD_ERR_SIZE if cap is too small. */
+hubbard_status hubbard_plan_dump(hubbard_t h, int32_t n_layers, int32_t which, int32_t *buf,
+                                 int64_t cap, int64_t *len);
+
+/* Tile bits of forward and reverse passes (2..13) and the minimum contiguous
+ * low bits c of every tile.  Drops cached device programs of the handle;
+ * call it before queueing work, not while work is in flight. */
+hubbard_status hubbard_set_tiles(hubbard_t h, int32_t fwd_k, int32_t rev_k, int32_t c);
+
+/* Phase timing.  When enabled, every later call records HIP events on its own
+ * stream around its phases: the forward passes, the H (or expectation)
+ * passes and the reverse passes.  hubbard_phase_ms waits for the last
+ * recorded event and returns the phase durations of the most recent call in
+ * milliseconds (-1 for a phase that call did not have).  Not for use under
+ * graph capture. */
+hubbard_status hubbard_set_timing(hubbard_t h, int32_t enable);
+hubbard_status hubbard_phase_ms(hubbard_t h, float *fwd_ms, float *ham_ms, float *rev_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HUBBARD_PLAN_H */

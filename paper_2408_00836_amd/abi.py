@@ -1,0 +1,216 @@
+"""ctypes binding of include/hubbard.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and takes
+plain integers for device pointers and streams.  All computation happens in
+the gfx950 library libhubvqe.so; if it is missing, loading fails loudly --
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhubvqe.so")
+
+HUBBARD_OK = 0
+HUBBARD_ERR_ARG = 1
+HUBBARD_ERR_SIZE = 2
+HUBBARD_ERR_DEVICE = 3
+HUBBARD_ERR_NOMEM = 4
+HUBBARD_ERR_STATE = 5
+HUBBARD_OP_ENERGY = 0
+HUBBARD_OP_ENERGY_GRAD = 1
+
+# Every symbol the headers in include/ declare.
+EXPORTED = [
+    "hubbard_create", "hubbard_destroy", "hubbard_query", "hubbard_bonds",
+    "hubbard_last_error", "hubbard_workspace_size", "hubbard_init_neel",
+    "ansatz_apply", "hamiltonian_apply", "energy", "energy_grad",
+    "hubbard_plan_dump", "hubbard_set_tiles", "hubbard_set_timing", "hubbard_phase_ms",
+]
+
+
+class HubbardError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hubbard status {status}: {msg}")
+        self.status = status
+
+
+class hubbard_desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32),
+        ("t_bond", ctypes.POINTER(ctypes.c_double)),
+        ("U", ctypes.c_double),
+        ("V_bond", ctypes.POINTER(ctypes.c_double)),
+        ("eps_site", ctypes.POINTER(ctypes.c_double)),
+        ("bond_group", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is not built; run `python -m paper_2408_00836_amd.build` "
+                "(hipcc, gfx950). There is no CPU fallback.")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, st, i32, i64, u64 = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int32,
+                                 ctypes.c_int64, ctypes.c_uint64)
+        P = ctypes.POINTER
+        sig = {
+            "hubbard_create": ([P(hubbard_desc), P(vp)], st),
+            "hubbard_destroy": ([vp], None),
+            "hubbard_query": ([vp, P(i32), P(i32), P(i32), P(i32), P(u64)], st),
+            "hubbard_bonds": ([vp, P(i32), P(i32), P(i32)], st),
+            "hubbard_last_error": ([], ctypes.c_char_p),
+            "hubbard_workspace_size": ([vp, i32, i32, P(ctypes.c_size_t)], st),
+            "hubbard_init_neel": ([vp, vp, vp], st),
+            "ansatz_apply": ([vp, vp, i32, vp, vp], st),
+            "hamiltonian_apply": ([vp, vp, vp, vp], st),
+            "energy": ([vp, vp, i32, vp, vp, ctypes.c_size_t, vp], st),
+            "energy_grad": ([vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp], st),
+            "hubbard_plan_dump": ([vp, i32, i32, P(i32), i64, P(i64)], st),
+            "hubbard_set_tiles": ([vp, i32, i32, i32], st),
+            "hubbard_set_timing": ([vp, i32], st),
+            "hubbard_phase_ms": ([vp, P(ctypes.c_float), P(ctypes.c_float),
+                                  P(ctypes.c_float)], st),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != HUBBARD_OK:
+        msg = lib().hubbard_last_error()
+        raise HubbardError(status, msg.decode() if msg else "")
+
+
+def _dptr(arr):
+    if arr is None:
+        return None
+    a = np.ascontiguousarray(arr, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def hubbard_create(nx: int, ny: int, periodic_x: bool = False, periodic_y: bool = False,
+                   t_bond=None, U: float = 0.0, V_bond=None, eps_site=None,
+                   bond_group=None) -> int:
+    """Returns the opaque handle (an int)."""
+    keep = []
+    d = hubbard_desc()
+    d.nx, d.ny = int(nx), int(ny)
+    d.periodic_x, d.periodic_y = int(bool(periodic_x)), int(bool(periodic_y))
+    d.U = float(U)
+    for field, arr in (("t_bond", t_bond), ("V_bond", V_bond), ("eps_site", eps_site)):
+        if arr is not None:
+            a, p = _dptr(arr)
+            keep.append(a)
+            setattr(d, field, p)
+    if bond_group is not None:
+        g = np.ascontiguousarray(bond_group, dtype=np.int32)
+        keep.append(g)
+        d.bond_group = g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    h = ctypes.c_void_p()
+    _check(lib().hubbard_create(ctypes.byref(d), ctypes.byref(h)))
+    return h.value
+
+
+def hubbard_destroy(h: int) -> None:
+    lib().hubbard_destroy(h)
+
+
+def hubbard_query(h: int) -> dict:
+    nq, nb, ng, ppl = (ctypes.c_int32() for _ in range(4))
+    neel = ctypes.c_uint64()
+    _check(lib().hubbard_query(h, ctypes.byref(nq), ctypes.byref(nb), ctypes.byref(ng),
+                               ctypes.byref(ppl), ctypes.byref(neel)))
+    return dict(n_qubits=nq.value, n_bonds=nb.value, n_groups=ng.value,
+                params_per_layer=ppl.value, neel_index=neel.value)
+
+
+def hubbard_bonds(h: int):
+    nb = hubbard_query(h)["n_bonds"]
+    bi, bj, g = (np.zeros(max(nb, 1), dtype=np.int32) for _ in range(3))
+    P = ctypes.POINTER(ctypes.c_int32)
+    _check(lib().hubbard_bonds(h, bi.ctypes.data_as(P), bj.ctypes.data_as(P), g.ctypes.data_as(P)))
+    return bi[:nb], bj[:nb], g[:nb]
+
+
+def hubbard_workspace_size(h: int, n_layers: int, op: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().hubbard_workspace_size(h, int(n_layers), int(op), ctypes.byref(b)))
+    return b.value
+
+
+def hubbard_init_neel(h: int, psi_dev: int, stream: int = 0) -> None:
+    _check(lib().hubbard_init_neel(h, psi_dev, stream))
+
+
+def ansatz_apply(h: int, theta_dev: int, n_layers: int, psi_dev: int, stream: int = 0) -> None:
+    _check(lib().ansatz_apply(h, theta_dev, int(n_layers), psi_dev, stream))
+
+
+def hamiltonian_apply(h: int, psi_dev: int, out_dev: int, stream: int = 0) -> None:
+    _check(lib().hamiltonian_apply(h, psi_dev, out_dev, stream))
+
+
+def energy(h: int, theta_dev: int, n_layers: int, E_dev: int, ws_dev: int, ws_bytes: int,
+           stream: int = 0) -> None:
+    _check(lib().energy(h, theta_dev, int(n_layers), E_dev, ws_dev, int(ws_bytes), stream))
+
+
+def energy_grad(h: int, theta_dev: int, n_layers: int, E_dev: int, grad_dev: int, ws_dev: int,
+                ws_bytes: int, stream: int = 0) -> None:
+    _check(lib().energy_grad(h, theta_dev, int(n_layers), E_dev, grad_dev, ws_dev,
+                             int(ws_bytes), stream))
+
+
+def hubbard_set_tiles(h: int, fwd_k: int, rev_k: int, c: int) -> None:
+    _check(lib().hubbard_set_tiles(h, int(fwd_k), int(rev_k), int(c)))
+
+
+def hubbard_plan_dump(h: int, n_layers: int, which: int):
+    """Parsed schedule: list of passes {tile, flags, ops: [(kind, param, p, q,
+    umask, emask, vbonds)]}."""
+    n = ctypes.c_int64()
+    _check(lib().hubbard_plan_dump(h, int(n_layers), int(which), None, 0, ctypes.byref(n)))
+    buf = np.zeros(n.value, dtype=np.int32)
+    _check(lib().hubbard_plan_dump(h, int(n_layers), int(which),
+                                   buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   n.value, ctypes.byref(n)))
+    it = iter(buf.tolist())
+    passes = []
+    for _ in range(next(it)):
+        k = next(it)
+        tile = [next(it) for _ in range(k)]
+        flags = next(it)
+        ops = []
+        for _ in range(next(it)):
+            kind, param, p, q, um, em, nv = (next(it) for _ in range(7))
+            vb = [next(it) for _ in range(nv)]
+            ops.append((kind, param, p, q, um & 0xffffffff, em & 0xffffffff, vb))
+        passes.append(dict(tile=tile, flags=flags, ops=ops))
+    return passes
+
+
+def hubbard_set_timing(h: int, enable: bool) -> None:
+    _check(lib().hubbard_set_timing(h, int(bool(enable))))
+
+
+def hubbard_phase_ms(h: int):
+    """(forward, H-or-expectation, reverse) milliseconds of the last call."""
+    a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+    _check(lib().hubbard_phase_ms(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value

@@ -1,0 +1,791 @@
+// engine.hip -- host runtime behind include/hubbard.h: device programs built
+// from the pass plans, kernel launches and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hubbard.h"
+#include "../../include/hubbard_plan.h"
+#include "hubvqe.hpp"
+
+namespace hv {
+__global__ void k_forward(DevPass, const DevOp *, const DevVBond *, const double *,
+                          const DevModel *, double2 *);
+__global__ void k_reverse(DevPass, const DevOp *, const DevVBond *, const double *,
+                          const DevModel *, double2 *, double2 *, double *, int);
+__global__ void k_hamiltonian(DevPass, const DevOp *, const DevVBond *, const DevModel *,
+                              const double2 *, double2 *, double *, int);
+__global__ void k_expect(DevPass, const DevOp *, const DevVBond *, const DevModel *,
+                         const double2 *, double *, int);
+__global__ void k_init_basis(double2 *, uint64_t, uint64_t);
+__global__ void k_reduce(const double *, int, const int32_t *, const int32_t *, const int32_t *,
+                         const double *, double *, double *, int);
+}  // namespace hv
+
+using namespace hv;
+
+namespace {
+
+thread_local std::string g_err;
+
+hubbard_status fail(hubbard_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+constexpr int kThreads = 256;
+constexpr int kGridMax = 2048;
+
+enum ProgKind { PROG_ANSATZ = 0, PROG_HAM = 1, PROG_ENERGY = 2, PROG_GRAD = 3 };
+
+// A flattened set of passes of one kind.
+struct PassList {
+    std::vector<DevPass> pass;
+    std::vector<int> grid;
+    std::vector<int> smem;
+};
+
+// Everything one call needs on one device.
+struct Program {
+    int kind = 0;
+    int layers = 0;
+    PassList fwd, ham, rev, exp;
+    // device tables
+    DevOp *d_ops = nullptr;
+    DevVBond *d_vb = nullptr;
+    int32_t *d_row_ptr = nullptr, *d_row_idx = nullptr, *d_row_nblk = nullptr;
+    double *d_scale = nullptr;
+    int n_rows = 0, n_out = 0;
+    size_t partial_bytes = 0;
+    // host copies (introspection)
+    std::vector<HostPass> h_fwd, h_ham, h_rev, h_exp;
+    ~Program()
+    {
+        (void)hipFree(d_ops);
+        (void)hipFree(d_vb);
+        (void)hipFree(d_row_ptr);
+        (void)hipFree(d_row_idx);
+        (void)hipFree(d_row_nblk);
+        (void)hipFree(d_scale);
+    }
+};
+
+struct DeviceState {
+    DevModel *d_model = nullptr;
+    std::map<std::pair<int, int>, std::unique_ptr<Program>> progs;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct hubbard_model {
+    Model m;
+    TileConfig fwd_tc{12, 4};
+    TileConfig rev_tc{12, 4};
+    std::map<int, DeviceState> dev;
+    std::mutex mu;
+    // optional phase timing: events recorded on the call's stream
+    bool timing = false;
+    bool ev_ready = false;
+    hipEvent_t ev[4];
+    int ev_used = 0;
+};
+
+namespace {
+
+// ----------------------------------------------------------- flattening --
+
+struct Builder {
+    const Model &m;
+    std::vector<DevOp> ops;
+    std::vector<DevVBond> vb;
+    std::vector<int> row_param;   // param (or -1 for energy) of each partial row
+    std::vector<int> row_nblk;
+    explicit Builder(const Model &mm) : m(mm) {}
+
+    // rows: 0 none, 1 one row per distinct param (reverse), 2 one energy row
+    PassList add(const std::vector<HostPass> &passes, int rows, bool last_only_energy)
+    {
+        PassList pl;
+        for (size_t pi = 0; pi < passes.size(); ++pi) {
+            const HostPass &hp = passes[pi];
+            DevPass P;
+            std::memset(&P, 0, sizeof(P));
+            const int n = m.nq;
+            P.k = (int)hp.tile.size();
+            int c = 0;
+            while (c < P.k && hp.tile[c] == c)
+                ++c;
+            P.c = c;
+            uint32_t S = 0;
+            for (int j = 0; j < P.k; ++j) {
+                P.tile_pos[j] = (uint8_t)hp.tile[j];
+                S |= 1u << hp.tile[j];
+            }
+            int nf = 0;
+            for (int b = 0; b < n; ++b)
+                if (!(S & (1u << b)))
+                    P.free_pos[nf++] = (uint8_t)b;
+            P.nfree = nf;
+            P.flags = hp.flags;
+            P.op_begin = (int)ops.size();
+            const uint64_t ntiles = (uint64_t)1 << nf;
+            const int grid = (int)std::min<uint64_t>(ntiles, kGridMax);
+            std::map<int, int> red_of;
+            P.red_base = (int)row_param.size();
+            if (rows == 2 && (!last_only_energy || (hp.flags & PF_HAM_LAST))) {
+                red_of[-2] = 0;
+                row_param.push_back(-1);
+                row_nblk.push_back(grid);
+            }
+            int n_diag = 0;
+            for (const HostOp &h : hp.ops) {
+                DevOp o;
+                std::memset(&o, 0, sizeof(o));
+                o.kind = h.kind;
+                o.param = h.param;
+                o.red = -1;
+                o.dtab = -1;
+                o.v_begin = o.v_end = 0;
+                if (rows == 1 && h.param >= 0) {
+                    auto it = red_of.find(h.param);
+                    if (it == red_of.end()) {
+                        int r = (int)red_of.size();
+                        red_of[h.param] = r;
+                        row_param.push_back(h.param);
+                        row_nblk.push_back(grid);
+                        o.red = r;
+                    } else {
+                        o.red = it->second;
+                    }
+                }
+                if (h.kind == OP_HOP) {
+                    int pl = -1, ql = -1;
+                    for (int j = 0; j < P.k; ++j) {
+                        if (hp.tile[j] == h.p)
+                            pl = j;
+                        if (hp.tile[j] == h.q)
+                            ql = j;
+                    }
+                    o.pl = pl;
+                    o.ql = ql;
+                    uint32_t bl = 0, bf = 0;
+                    for (int j = 0; j < P.k; ++j)
+                        if (hp.tile[j] > h.p && hp.tile[j] < h.q)
+                            bl |= 1u << j;
+                    for (int f = 0; f < nf; ++f)
+                        if (P.free_pos[f] > h.p && P.free_pos[f] < h.q)
+                            bf |= 1u << f;
+                    o.bm_local = bl;
+                    o.bm_free = bf;
+                    o.t = h.t;
+                } else {
+                    o.dtab = n_diag++;
+                    o.umask = h.umask;
+                    o.emask = h.emask;
+                    o.v_begin = (int)vb.size();
+                    for (int b : h.vbonds) {
+                        DevVBond v;
+                        std::memset(&v, 0, sizeof(v));
+                        v.q[0] = m.qubit(m.bi[b], 0);
+                        v.q[1] = m.qubit(m.bi[b], 1);
+                        v.q[2] = m.qubit(m.bj[b], 0);
+                        v.q[3] = m.qubit(m.bj[b], 1);
+                        v.V = m.V[b];
+                        vb.push_back(v);
+                    }
+                    o.v_end = (int)vb.size();
+                }
+                ops.push_back(o);
+            }
+            P.n_ops = (int)hp.ops.size();
+            P.n_diag = n_diag;
+            P.n_red = (int)red_of.size();
+            pl.pass.push_back(P);
+            pl.grid.push_back(grid);
+            pl.smem.push_back(0);
+        }
+        return pl;
+    }
+};
+
+int max_smem_per_block()
+{
+    // gfx950 gives a workgroup up to 160 KiB of LDS; ask the device when one
+    // is present so that planning without a GPU gives the same plan.
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 160 * 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 160 * 1024;
+    return v;
+}
+
+void set_smem(PassList &pl, int n_vec, bool force_red1)
+{
+    for (size_t i = 0; i < pl.pass.size(); ++i) {
+        const DevPass &P = pl.pass[i];
+        int nred = force_red1 ? 1 : P.n_red;
+        pl.smem[i] = (int)smem_plan(P.k, P.c, n_vec, P.n_ops, P.n_diag, nred, kThreads).total;
+    }
+}
+
+int max_of(const PassList &pl)
+{
+    int m = 0;
+    for (int s : pl.smem)
+        m = std::max(m, s);
+    return m;
+}
+
+std::vector<HostPass> reversed(std::vector<HostPass> p)
+{
+    std::reverse(p.begin(), p.end());
+    for (HostPass &x : p)
+        std::reverse(x.ops.begin(), x.ops.end());
+    return p;
+}
+
+// Builds host plans only (no device work): used by introspection and upload.
+void plan_program(hubbard_model *h, int kind, int layers, int smem_limit, Program &pr)
+{
+    const Model &m = h->m;
+    pr.kind = kind;
+    pr.layers = layers;
+    if (kind != PROG_HAM)
+        pr.h_fwd = plan_forward(m, layers, h->fwd_tc);
+    TileConfig tc2 = h->rev_tc;
+    for (;;) {
+        if (kind == PROG_HAM || kind == PROG_GRAD)
+            pr.h_ham = plan_hamiltonian(m, tc2);
+        if (kind == PROG_GRAD)
+            pr.h_rev = reversed(plan_forward(m, layers, tc2));
+        // check LDS fit of the two-vector kernels; shrink the tile if needed
+        Builder b(m);
+        PassList ph = b.add(pr.h_ham, 2, true), pv = b.add(pr.h_rev, 1, false);
+        set_smem(ph, 2, false);
+        set_smem(pv, 2, false);
+        if (std::max(max_of(ph), max_of(pv)) <= smem_limit || tc2.k <= 6)
+            break;
+        tc2.k -= 1;
+    }
+    if (kind == PROG_ENERGY)
+        pr.h_exp = plan_hamiltonian(m, h->fwd_tc);
+}
+
+hubbard_status upload_program(hubbard_model *h, DeviceState &ds, Program &pr)
+{
+    const Model &m = h->m;
+    Builder b(m);
+    pr.fwd = b.add(pr.h_fwd, 0, false);
+    pr.ham = b.add(pr.h_ham, pr.kind == PROG_GRAD ? 2 : 0, true);
+    pr.rev = b.add(pr.h_rev, 1, false);
+    pr.exp = b.add(pr.h_exp, 2, false);
+    set_smem(pr.fwd, 1, false);
+    set_smem(pr.ham, 2, false);
+    set_smem(pr.rev, 2, false);
+    set_smem(pr.exp, 1, true);
+    const int P = pr.layers * m.params_per_layer();
+    // reduction map: output 0 = E, outputs 1..P = gradient
+    pr.n_out = (pr.kind == PROG_GRAD) ? 1 + P : 1;
+    std::vector<std::vector<int>> rows_of(pr.n_out);
+    for (size_t r = 0; r < b.row_param.size(); ++r) {
+        int p = b.row_param[r];
+        if (p < 0)
+            rows_of[0].push_back((int)r);
+        else if (pr.kind == PROG_GRAD)
+            rows_of[1 + p].push_back((int)r);
+    }
+    std::vector<int32_t> row_ptr{0}, row_idx;
+    std::vector<double> scale;
+    for (int o = 0; o < pr.n_out; ++o) {
+        for (int r : rows_of[o])
+            row_idx.push_back(r);
+        row_ptr.push_back((int32_t)row_idx.size());
+        scale.push_back(o == 0 ? 1.0 : 2.0);
+    }
+    std::vector<int32_t> nblk(b.row_nblk.begin(), b.row_nblk.end());
+    pr.n_rows = (int)b.row_param.size();
+    pr.partial_bytes = align256((size_t)pr.n_rows * kGridMax * sizeof(double));
+
+    auto up = [](void **dst, const void *src, size_t bytes) -> hipError_t {
+        if (bytes == 0)
+            bytes = 16;
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess)
+            return e;
+        if (src)
+            return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        return hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    e = up((void **)&pr.d_ops, b.ops.data(), b.ops.size() * sizeof(DevOp));
+    if (e == hipSuccess)
+        e = up((void **)&pr.d_vb, b.vb.empty() ? nullptr : b.vb.data(), b.vb.size() * sizeof(DevVBond));
+    if (e == hipSuccess)
+        e = up((void **)&pr.d_row_ptr, row_ptr.data(), row_ptr.size() * sizeof(int32_t));
+    if (e == hipSuccess)
+        e = up((void **)&pr.d_row_idx, row_idx.empty() ? nullptr : row_idx.data(),
+               row_idx.size() * sizeof(int32_t));
+    if (e == hipSuccess)
+        e = up((void **)&pr.d_row_nblk, nblk.empty() ? nullptr : nblk.data(),
+               nblk.size() * sizeof(int32_t));
+    if (e == hipSuccess)
+        e = up((void **)&pr.d_scale, scale.data(), scale.size() * sizeof(double));
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("uploading plan: ") + hipGetErrorString(e));
+    (void)ds;
+    return HUBBARD_OK;
+}
+
+hubbard_status ensure_model(hubbard_model *h, int dev, DeviceState &ds)
+{
+    if (ds.d_model)
+        return HUBBARD_OK;
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        int lim = max_smem_per_block();
+        (void)hipFuncSetAttribute((const void *)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void *)k_reverse, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void *)k_hamiltonian, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void *)k_expect, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    });
+    (void)dev;
+    const Model &m = h->m;
+    DevModel dm;
+    std::memset(&dm, 0, sizeof(dm));
+    dm.n = m.nq;
+    dm.ns = m.ns;
+    dm.general = m.general ? 1 : 0;
+    dm.U = m.U;
+    for (int byte = 0; byte < 4; ++byte)
+        for (int v = 0; v < 256; ++v) {
+            double s = 0.0;
+            for (int j = 0; j < 8; ++j) {
+                int q = byte * 8 + j;
+                if (((v >> j) & 1) && q < m.nq)
+                    s += m.eps[q < m.ns ? q : q - m.ns];
+            }
+            dm.eps_byte[byte][v] = s;
+        }
+    hipError_t e = hipMalloc((void **)&ds.d_model, sizeof(DevModel));
+    if (e == hipSuccess)
+        e = hipMemcpy(ds.d_model, &dm, sizeof(DevModel), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(ds.d_model);
+        ds.d_model = nullptr;
+        return fail(HUBBARD_ERR_DEVICE, std::string("uploading model: ") + hipGetErrorString(e));
+    }
+    return HUBBARD_OK;
+}
+
+hubbard_status get_program(hubbard_model *h, int kind, int layers, Program **out,
+                           DeviceState **dsout)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(h->mu);
+    DeviceState &ds = h->dev[dev];
+    hubbard_status st = ensure_model(h, dev, ds);
+    if (st != HUBBARD_OK)
+        return st;
+    auto key = std::make_pair(kind, layers);
+    auto it = ds.progs.find(key);
+    if (it == ds.progs.end()) {
+        std::unique_ptr<Program> pr(new Program());
+        try {
+            plan_program(h, kind, layers, max_smem_per_block(), *pr);
+        } catch (const std::exception &ex) {
+            return fail(HUBBARD_ERR_NOMEM, std::string("planning: ") + ex.what());
+        }
+        st = upload_program(h, ds, *pr);
+        if (st != HUBBARD_OK)
+            return st;
+        it = ds.progs.emplace(key, std::move(pr)).first;
+    }
+    *out = it->second.get();
+    *dsout = &ds;
+    return HUBBARD_OK;
+}
+
+hubbard_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return HUBBARD_OK;
+}
+
+hubbard_status run_forward(const Program &pr, const DeviceState &ds, const double *theta,
+                           double2 *psi, hipStream_t s)
+{
+    for (size_t i = 0; i < pr.fwd.pass.size(); ++i)
+        hipLaunchKernelGGL(k_forward, dim3(pr.fwd.grid[i]), dim3(kThreads), pr.fwd.smem[i], s,
+                           pr.fwd.pass[i], pr.d_ops, pr.d_vb, theta, ds.d_model, psi);
+    return check_launch("forward pass");
+}
+
+hubbard_status run_ham(const Program &pr, const DeviceState &ds, const double2 *psi, double2 *phi,
+                       double *partial, hipStream_t s)
+{
+    for (size_t i = 0; i < pr.ham.pass.size(); ++i)
+        hipLaunchKernelGGL(k_hamiltonian, dim3(pr.ham.grid[i]), dim3(kThreads), pr.ham.smem[i], s,
+                           pr.ham.pass[i], pr.d_ops, pr.d_vb, ds.d_model, psi, phi, partial,
+                           kGridMax);
+    return check_launch("hamiltonian pass");
+}
+
+hubbard_status run_init(const hubbard_model *h, double2 *psi, hipStream_t s)
+{
+    const uint64_t dim = (uint64_t)1 << h->m.nq;
+    uint64_t blocks = std::min<uint64_t>((dim + kThreads - 1) / kThreads, 8192);
+    hipLaunchKernelGGL(k_init_basis, dim3((unsigned)blocks), dim3(kThreads), 0, s, psi, dim,
+                       (uint64_t)h->m.neel);
+    return check_launch("init");
+}
+
+hubbard_status run_reduce(const Program &pr, const double *partial, double *E, double *grad,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(pr.n_out), dim3(256), 0, s, partial, kGridMax, pr.d_row_ptr,
+                       pr.d_row_idx, pr.d_row_nblk, pr.d_scale, E, grad, 1);
+    return check_launch("reduce");
+}
+
+size_t vec_bytes(const hubbard_model *h) { return ((size_t)1 << h->m.nq) * 16u; }
+
+// Phase marks: 0 before the forward passes, 1 after them, 2 after the H or
+// expectation passes, 3 after the reverse passes.
+void mark(hubbard_model *h, int i, hipStream_t s)
+{
+    if (!h->timing)
+        return;
+    if (!h->ev_ready) {
+        for (int j = 0; j < 4; ++j)
+            if (hipEventCreate(&h->ev[j]) != hipSuccess)
+                return;
+        h->ev_ready = true;
+    }
+    (void)hipEventRecord(h->ev[i], s);
+    h->ev_used |= 1 << i;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char *hubbard_last_error(void) { return g_err.c_str(); }
+
+hubbard_status hubbard_create(const hubbard_desc *d, hubbard_t *out)
+{
+    if (!d || !out)
+        return fail(HUBBARD_ERR_ARG, "desc and out must not be NULL");
+    *out = nullptr;
+    hubbard_model *h = nullptr;
+    try {
+        h = new hubbard_model();
+    } catch (...) {
+        return fail(HUBBARD_ERR_NOMEM, "allocating handle");
+    }
+    std::string err = build_model(d->nx, d->ny, d->periodic_x, d->periodic_y, d->t_bond, d->U,
+                                  d->V_bond, d->eps_site, d->bond_group, h->m);
+    if (!err.empty()) {
+        delete h;
+        return fail(HUBBARD_ERR_ARG, err);
+    }
+    *out = h;
+    return HUBBARD_OK;
+}
+
+void hubbard_destroy(hubbard_t h)
+{
+    if (!h)
+        return;
+    if (h->ev_ready)
+        for (int j = 0; j < 4; ++j)
+            (void)hipEventDestroy(h->ev[j]);
+    for (auto &kv : h->dev) {
+        (void)hipSetDevice(kv.first);
+        kv.second.progs.clear();
+        (void)hipFree(kv.second.d_model);
+    }
+    delete h;
+}
+
+hubbard_status hubbard_query(hubbard_t h, int32_t *n_qubits, int32_t *n_bonds, int32_t *n_groups,
+                             int32_t *params_per_layer, uint64_t *neel_index)
+{
+    if (!h)
+        return fail(HUBBARD_ERR_ARG, "NULL handle");
+    if (n_qubits)
+        *n_qubits = h->m.nq;
+    if (n_bonds)
+        *n_bonds = h->m.nb;
+    if (n_groups)
+        *n_groups = h->m.ngroups;
+    if (params_per_layer)
+        *params_per_layer = h->m.params_per_layer();
+    if (neel_index)
+        *neel_index = h->m.neel;
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_bonds(hubbard_t h, int32_t *bi, int32_t *bj, int32_t *group)
+{
+    if (!h)
+        return fail(HUBBARD_ERR_ARG, "NULL handle");
+    for (int b = 0; b < h->m.nb; ++b) {
+        if (bi)
+            bi[b] = h->m.bi[b];
+        if (bj)
+            bj[b] = h->m.bj[b];
+        if (group)
+            group[b] = h->m.slot[b] - 1;
+    }
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_workspace_size(hubbard_t h, int32_t n_layers, int32_t op, size_t *bytes)
+{
+    if (!h || !bytes || n_layers < 0)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_workspace_size");
+    if (op != HUBBARD_OP_ENERGY && op != HUBBARD_OP_ENERGY_GRAD)
+        return fail(HUBBARD_ERR_ARG, "unknown op");
+    Program pr;
+    try {
+        plan_program(h, op == HUBBARD_OP_ENERGY ? PROG_ENERGY : PROG_GRAD, n_layers,
+                     max_smem_per_block(), pr);
+    } catch (const std::exception &ex) {
+        return fail(HUBBARD_ERR_NOMEM, ex.what());
+    }
+    Builder b(h->m);
+    b.add(pr.h_fwd, 0, false);
+    b.add(pr.h_ham, op == HUBBARD_OP_ENERGY_GRAD ? 2 : 0, true);
+    b.add(pr.h_rev, 1, false);
+    b.add(pr.h_exp, 2, false);
+    size_t partial = align256(b.row_param.size() * (size_t)kGridMax * sizeof(double));
+    size_t nvec = (op == HUBBARD_OP_ENERGY) ? 1 : 2;
+    *bytes = nvec * align256(vec_bytes(h)) + partial;
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_init_neel(hubbard_t h, void *psi_dev, void *stream)
+{
+    if (!h || !psi_dev)
+        return fail(HUBBARD_ERR_ARG, "NULL handle or psi");
+    return run_init(h, (double2 *)psi_dev, (hipStream_t)stream);
+}
+
+hubbard_status ansatz_apply(hubbard_t h, const double *theta_dev, int32_t n_layers, void *psi_dev,
+                            void *stream)
+{
+    if (!h || !psi_dev || n_layers < 0 || (n_layers > 0 && !theta_dev))
+        return fail(HUBBARD_ERR_ARG, "bad arguments to ansatz_apply");
+    if (n_layers == 0)
+        return HUBBARD_OK;
+    Program *pr;
+    DeviceState *ds;
+    hubbard_status st = get_program(h, PROG_ANSATZ, n_layers, &pr, &ds);
+    if (st != HUBBARD_OK)
+        return st;
+    h->ev_used = 0;
+    mark(h, 0, (hipStream_t)stream);
+    st = run_forward(*pr, *ds, theta_dev, (double2 *)psi_dev, (hipStream_t)stream);
+    mark(h, 1, (hipStream_t)stream);
+    return st;
+}
+
+hubbard_status hamiltonian_apply(hubbard_t h, const void *psi_dev, void *out_dev, void *stream)
+{
+    if (!h || !psi_dev || !out_dev)
+        return fail(HUBBARD_ERR_ARG, "NULL argument to hamiltonian_apply");
+    const char *a = (const char *)psi_dev, *b = (const char *)out_dev;
+    const size_t nb = vec_bytes(h);
+    if (a < b + nb && b < a + nb)
+        return fail(HUBBARD_ERR_ARG, "out_dev overlaps psi_dev");
+    Program *pr;
+    DeviceState *ds;
+    hubbard_status st = get_program(h, PROG_HAM, 0, &pr, &ds);
+    if (st != HUBBARD_OK)
+        return st;
+    h->ev_used = 0;
+    mark(h, 1, (hipStream_t)stream);
+    st = run_ham(*pr, *ds, (const double2 *)psi_dev, (double2 *)out_dev, nullptr,
+                 (hipStream_t)stream);
+    mark(h, 2, (hipStream_t)stream);
+    return st;
+}
+
+hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers, double *E_dev,
+                      void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (!h || !E_dev || !ws_dev || n_layers < 0 || (n_layers > 0 && !theta_dev))
+        return fail(HUBBARD_ERR_ARG, "bad arguments to energy");
+    Program *pr;
+    DeviceState *ds;
+    hubbard_status st = get_program(h, PROG_ENERGY, n_layers, &pr, &ds);
+    if (st != HUBBARD_OK)
+        return st;
+    const size_t vb = align256(vec_bytes(h));
+    if (ws_bytes < vb + pr->partial_bytes)
+        return fail(HUBBARD_ERR_SIZE, "workspace too small for energy");
+    hipStream_t s = (hipStream_t)stream;
+    double2 *psi = (double2 *)ws_dev;
+    double *partial = (double *)((char *)ws_dev + vb);
+    if ((st = run_init(h, psi, s)) != HUBBARD_OK)
+        return st;
+    h->ev_used = 0;
+    mark(h, 0, s);
+    if ((st = run_forward(*pr, *ds, theta_dev, psi, s)) != HUBBARD_OK)
+        return st;
+    mark(h, 1, s);
+    for (size_t i = 0; i < pr->exp.pass.size(); ++i)
+        hipLaunchKernelGGL(k_expect, dim3(pr->exp.grid[i]), dim3(kThreads), pr->exp.smem[i], s,
+                           pr->exp.pass[i], pr->d_ops, pr->d_vb, ds->d_model, psi, partial,
+                           kGridMax);
+    if ((st = check_launch("expectation pass")) != HUBBARD_OK)
+        return st;
+    mark(h, 2, s);
+    return run_reduce(*pr, partial, E_dev, nullptr, s);
+}
+
+hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers, double *E_dev,
+                           double *grad_dev, void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (!h || !E_dev || !ws_dev || n_layers < 0 || (n_layers > 0 && (!theta_dev || !grad_dev)))
+        return fail(HUBBARD_ERR_ARG, "bad arguments to energy_grad");
+    Program *pr;
+    DeviceState *ds;
+    hubbard_status st = get_program(h, PROG_GRAD, n_layers, &pr, &ds);
+    if (st != HUBBARD_OK)
+        return st;
+    const size_t vb = align256(vec_bytes(h));
+    if (ws_bytes < 2 * vb + pr->partial_bytes)
+        return fail(HUBBARD_ERR_SIZE, "workspace too small for energy_grad");
+    hipStream_t s = (hipStream_t)stream;
+    double2 *psi = (double2 *)ws_dev;
+    double2 *lam = (double2 *)((char *)ws_dev + vb);
+    double *partial = (double *)((char *)ws_dev + 2 * vb);
+    if ((st = run_init(h, psi, s)) != HUBBARD_OK)
+        return st;
+    h->ev_used = 0;
+    mark(h, 0, s);
+    if ((st = run_forward(*pr, *ds, theta_dev, psi, s)) != HUBBARD_OK)
+        return st;
+    mark(h, 1, s);
+    if ((st = run_ham(*pr, *ds, psi, lam, partial, s)) != HUBBARD_OK)
+        return st;
+    mark(h, 2, s);
+    for (size_t i = 0; i < pr->rev.pass.size(); ++i)
+        hipLaunchKernelGGL(k_reverse, dim3(pr->rev.grid[i]), dim3(kThreads), pr->rev.smem[i], s,
+                           pr->rev.pass[i], pr->d_ops, pr->d_vb, theta_dev, ds->d_model, psi, lam,
+                           partial, kGridMax);
+    if ((st = check_launch("reverse pass")) != HUBBARD_OK)
+        return st;
+    mark(h, 3, s);
+    return run_reduce(*pr, partial, E_dev, grad_dev, s);
+}
+
+// ------------------------------------------------------- introspection --
+
+hubbard_status hubbard_plan_dump(hubbard_t h, int32_t n_layers, int32_t which, int32_t *buf,
+                                 int64_t cap, int64_t *len)
+{
+    if (!h || !len || n_layers < 0 || which < 0 || which > 3)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_plan_dump");
+    Program pr;
+    try {
+        plan_program(h, which == 3 ? PROG_ENERGY : PROG_GRAD, n_layers, max_smem_per_block(), pr);
+    } catch (const std::exception &ex) {
+        return fail(HUBBARD_ERR_NOMEM, ex.what());
+    }
+    const std::vector<HostPass> &ps =
+        which == 0 ? pr.h_fwd : which == 1 ? pr.h_ham : which == 2 ? pr.h_rev : pr.h_exp;
+    std::vector<int32_t> out;
+    out.push_back((int32_t)ps.size());
+    for (const HostPass &p : ps) {
+        out.push_back((int32_t)p.tile.size());
+        for (int b : p.tile)
+            out.push_back(b);
+        out.push_back(p.flags);
+        out.push_back((int32_t)p.ops.size());
+        for (const HostOp &o : p.ops) {
+            out.push_back(o.kind);
+            out.push_back(o.param);
+            out.push_back(o.p);
+            out.push_back(o.q);
+            out.push_back((int32_t)o.umask);
+            out.push_back((int32_t)o.emask);
+            out.push_back((int32_t)o.vbonds.size());
+            for (int b : o.vbonds)
+                out.push_back(b);
+        }
+    }
+    *len = (int64_t)out.size();
+    if (buf && cap >= (int64_t)out.size())
+        std::memcpy(buf, out.data(), out.size() * sizeof(int32_t));
+    else if (buf)
+        return fail(HUBBARD_ERR_SIZE, "buffer too small for plan dump");
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_set_tiles(hubbard_t h, int32_t fwd_k, int32_t rev_k, int32_t c)
+{
+    if (!h || fwd_k < 2 || fwd_k > kMaxTileBits || rev_k < 2 || rev_k > kMaxTileBits || c < 0 ||
+        c > fwd_k || c > rev_k)
+        return fail(HUBBARD_ERR_ARG, "tile bits must be in [2, 13] and c <= k");
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->fwd_tc = TileConfig{fwd_k, c};
+    h->rev_tc = TileConfig{rev_k, c};
+    for (auto &kv : h->dev)
+        kv.second.progs.clear();
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_set_timing(hubbard_t h, int32_t enable)
+{
+    if (!h)
+        return fail(HUBBARD_ERR_ARG, "NULL handle");
+    h->timing = enable != 0;
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_phase_ms(hubbard_t h, float *fwd_ms, float *ham_ms, float *rev_ms)
+{
+    if (!h || !fwd_ms || !ham_ms || !rev_ms)
+        return fail(HUBBARD_ERR_ARG, "NULL argument to hubbard_phase_ms");
+    *fwd_ms = *ham_ms = *rev_ms = -1.0f;
+    if (!h->ev_ready)
+        return fail(HUBBARD_ERR_STATE, "timing was not enabled before the last call");
+    auto span = [&](int a, int b, float *out) -> hubbard_status {
+        if ((h->ev_used & (1 << a)) && (h->ev_used & (1 << b))) {
+            hipError_t e = hipEventSynchronize(h->ev[b]);
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(out, h->ev[a], h->ev[b]);
+            if (e != hipSuccess)
+                return fail(HUBBARD_ERR_DEVICE, std::string("event timing: ") + hipGetErrorString(e));
+        }
+        return HUBBARD_OK;
+    };
+    hubbard_status st = span(0, 1, fwd_ms);
+    if (st == HUBBARD_OK)
+        st = span(1, 2, ham_ms);
+    if (st == HUBBARD_OK)
+        st = span(2, 3, rev_ms);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// hubvqe.hpp -- internal structures shared by the host runtime (model.cpp,
+// plan.cpp, engine.hip) and the gfx950 kernels.  Not part of the public ABI
+// (include/hubbard.h is).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#if !defined(__HIPCC__)
+#define __host__
+#define __device__
+#endif
+
+namespace hv {
+
+constexpr int kMaxSites = 16;
+constexpr int kMaxQubits = 32;
+constexpr int kMaxBonds = 64;
+constexpr int kMaxTileBits = 13;
+constexpr int kMaxOpsPerPass = 96;
+constexpr int kMaxDiagPerPass = 32;
+constexpr int kMaxRedPerPass = 12;
+constexpr int kDiagTab = kMaxSites + 1;   // U-count phase table entries
+
+enum OpKind : int32_t {
+    OP_DIAG = 0,   // diagonal sub-term: U and eps of a set of sites, V of a set of bonds
+    OP_HOP = 1     // one hopping term (a+_p a_q + h.c.) of one bond and spin
+};
+
+enum PassFlags : int32_t {
+    PF_HAM_FIRST = 1,   // H pass: phi <- D psi + terms (else phi += terms)
+    PF_HAM_LAST = 2,    // H pass: also reduce Re <psi|phi> into row 0
+};
+
+// One device operation inside a pass (64 bytes).
+struct DevOp {
+    int32_t kind;
+    int32_t param;      // theta index (-1 for Hamiltonian terms)
+    int32_t red;        // reduction row within the pass (-1: none)
+    int32_t dtab;       // DIAG: index of its phase table within the pass
+    int32_t pl, ql;     // HOP: tile-local bit positions of the two qubits
+    uint32_t bm_local;  // HOP: Jordan-Wigner between-mask over tile-local bits
+    uint32_t bm_free;   // HOP: between-mask over the free (tile-index) bits
+    uint32_t umask;     // DIAG: spin-up qubits of the sites whose U term it carries
+    uint32_t emask;     // DIAG: qubits whose eps term it carries
+    int32_t v_begin;    // DIAG: V bonds [v_begin, v_end) of the plan's V table
+    int32_t v_end;
+    double t;           // HOP: bond hopping t_b
+    double pad;
+};
+static_assert(sizeof(DevOp) == 64, "DevOp layout");
+
+// A V bond as the device reads it: qubits (i up, i dn, j up, j dn) and V_b.
+struct DevVBond {
+    int32_t q[4];
+    double V;
+    double pad;
+};
+
+// Pass descriptor, passed by value as a kernel argument.
+struct DevPass {
+    int32_t k;          // tile bits
+    int32_t c;          // tile bits 0..c-1 are global bits 0..c-1 (coalesced run)
+    int32_t nfree;      // n - k
+    int32_t op_begin;   // first op in the plan's op array
+    int32_t n_ops;
+    int32_t n_diag;     // DIAG ops (phase tables) in this pass
+    int32_t red_base;   // first partial row of this pass
+    int32_t n_red;      // partial rows written by this pass
+    int32_t flags;
+    int32_t pad;
+    uint8_t tile_pos[16];   // global bit of tile bit j
+    uint8_t free_pos[32];   // global bit of free bit f
+};
+
+// Model constants in device memory.
+struct DevModel {
+    int32_t n, ns;
+    int32_t general;        // 0: D = U * (#doubly occupied sites) only
+    int32_t pad;
+    double U;
+    double eps_byte[4][256];  // sum of eps over set qubits of each index byte
+};
+
+// LDS carve-up shared by host (launch size) and device.
+struct SmemPlan {
+    uint32_t tiles, offs, opc, dtab, red, total;
+};
+
+__host__ __device__ inline SmemPlan smem_plan(int k, int c, int n_vec, int n_ops, int n_diag,
+                                              int n_red, int threads)
+{
+    SmemPlan s;
+    uint32_t at = 0;
+    s.tiles = at;
+    at += (uint32_t)n_vec * (1u << k) * 16u;
+    s.offs = at;
+    at += ((1u << (k - c)) * 4u + 15u) & ~15u;
+    s.opc = at;
+    at += (uint32_t)n_ops * 16u;
+    s.dtab = at;
+    at += (uint32_t)n_diag * kDiagTab * 16u;
+    s.red = at;
+    at += (uint32_t)n_red * (uint32_t)threads * 8u;
+    s.total = at;
+    return s;
+}
+
+// ------------------------------------------------------------------ host --
+
+struct Model {
+    int nx = 0, ny = 0, px = 0, py = 0;
+    int ns = 0, nq = 0, nb = 0, ngroups = 0;
+    std::vector<int> bi, bj, slot;   // slot: 1..ngroups (application order)
+    std::vector<double> t, V, eps;
+    double U = 0.0;
+    uint64_t neel = 0;
+    bool general = false;            // any eps or V nonzero
+    int qubit(int site, int spin) const { return site + ns * spin; }
+    int params_per_layer() const { return 1 + ngroups; }
+};
+
+// Build and validate a model; returns an empty string or an error message.
+std::string build_model(int nx, int ny, int px, int py, const double *t, double U,
+                        const double *V, const double *eps, const int32_t *groups, Model &m);
+
+// One elementary operation of the forward circuit or of H.
+struct HostOp {
+    int kind = OP_DIAG;
+    int param = -1;
+    uint32_t qmask = 0;     // qubits it touches (ordering constraints)
+    int p = -1, q = -1;     // HOP qubits, p < q
+    double t = 0.0;
+    uint32_t umask = 0, emask = 0;
+    std::vector<int> vbonds;
+};
+
+struct HostPass {
+    std::vector<int> tile;        // sorted global bit positions
+    std::vector<HostOp> ops;      // application order
+    int flags = 0;
+};
+
+struct TileConfig {
+    int k = 12;     // tile bits
+    int c = 4;      // minimum contiguous low bits in every tile
+};
+
+// Forward circuit (layers of Eq. (7)) as elementary ops, then fused passes.
+std::vector<HostOp> circuit_ops(const Model &m, int layers);
+std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig &tc);
+// Passes that together apply H (terms split over tiles, D in the first).
+std::vector<HostPass> plan_hamiltonian(const Model &m, const TileConfig &tc);
+
+}  // namespace hv

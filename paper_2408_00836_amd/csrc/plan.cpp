@@ -1,0 +1,363 @@
+// plan.cpp -- turns the circuit of Eq. (3)/(7) and the operator H into
+// fused tile passes over the state vector.  Host only.
+//
+// A pass loads tiles of 2^k amplitudes whose index bits are a chosen set S of
+// k qubits (always containing the c lowest bits, so every load is a run of
+// 2^c contiguous amplitudes), applies a sequence of operations whose qubits
+// all lie in S, and writes the tiles back.  Diagonal operations act
+// element-wise and fit any tile.
+//
+// Ordering rule: two operations must keep their relative order iff they share
+// a qubit and are not both diagonal.  Hopping terms on disjoint qubit pairs are
+// fermion-parity-even bilinears on disjoint modes and commute; diagonal terms
+// commute with each other.  The diagonal of a layer is split into one
+// sub-term per site (U n_up n_dn + eps n) and one per V bond, so a spin-up
+// gate only waits for the sub-terms on its own sites.
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "hubvqe.hpp"
+
+namespace hv {
+
+namespace {
+
+inline uint32_t qbit(int q) { return 1u << q; }
+
+bool conflicts(const HostOp &a, const HostOp &b)
+{
+    if (a.kind == OP_DIAG && b.kind == OP_DIAG)
+        return false;
+    return (a.qmask & b.qmask) != 0;
+}
+
+struct Closure {
+    uint32_t S = 0;
+    std::vector<int> inc;
+    int hops = 0;
+};
+
+// Grow a tile set from `seed`, repeatedly taking the ready hop that adds the
+// fewest new qubits, and return the ops that this tile can apply in order.
+Closure grow(const std::vector<HostOp> &ops, const std::vector<int> &active,
+             const std::vector<char> &done, uint32_t seed, int k)
+{
+    (void)done;
+    Closure cl;
+    cl.S = seed;
+    if (__builtin_popcount(cl.S) > k)
+        return cl;
+    std::vector<char> in(ops.size(), 0);
+    for (;;) {
+        uint32_t bg = 0, bd = 0;   // qubits of blocked hops / blocked diagonals
+        int best = -1, best_new = 99;
+        for (int i : active) {
+            if (in[i])
+                continue;
+            const HostOp &o = ops[i];
+            if (o.kind == OP_DIAG) {
+                if (o.qmask & bg)
+                    bd |= o.qmask;
+                else
+                    in[i] = 1;
+                continue;
+            }
+            if ((o.qmask & bg) || (o.qmask & bd)) {
+                bg |= o.qmask;
+                continue;
+            }
+            uint32_t u = cl.S | o.qmask;
+            int nw = __builtin_popcount(u) - __builtin_popcount(cl.S);
+            if (__builtin_popcount(u) <= k && nw < best_new) {
+                best_new = nw;
+                best = i;
+            }
+            bg |= o.qmask;   // until included, later ops must wait for it
+        }
+        if (best < 0)
+            break;
+        in[best] = 1;
+        cl.S |= ops[best].qmask;
+    }
+    // Final in-order check: an op is applied only if no earlier op it must
+    // follow is left for a later pass.
+    uint32_t bg = 0, bd = 0;
+    for (int i : active) {
+        const HostOp &o = ops[i];
+        bool ok = in[i] && !(o.qmask & bg) && (o.kind == OP_DIAG || !(o.qmask & bd));
+        if (ok) {
+            cl.inc.push_back(i);
+            if (o.kind == OP_HOP)
+                ++cl.hops;
+        } else if (o.kind == OP_DIAG) {
+            bd |= o.qmask;
+        } else {
+            bg |= o.qmask;
+        }
+    }
+    return cl;
+}
+
+// Fill a tile set up to k bits, lowest free bits first (longer contiguous run).
+std::vector<int> finish_tile(uint32_t S, int n, int k)
+{
+    for (int b = 0; b < n && __builtin_popcount(S) < k; ++b)
+        S |= qbit(b);
+    std::vector<int> tile;
+    for (int b = 0; b < n; ++b)
+        if (S & qbit(b))
+            tile.push_back(b);
+    return tile;
+}
+
+// Merge diagonal sub-terms of the same parameter inside a pass when no
+// conflicting op sits between them, so each tile multiplies once per run.
+void merge_diagonals(std::vector<HostOp> &ops)
+{
+    std::vector<HostOp> out;
+    for (const HostOp &o : ops) {
+        if (o.kind == OP_DIAG) {
+            int target = -1;
+            for (int j = (int)out.size() - 1; j >= 0; --j) {
+                if (out[j].kind == OP_DIAG && out[j].param == o.param) {
+                    target = j;
+                    break;
+                }
+                if (conflicts(out[j], o))
+                    break;
+            }
+            if (target >= 0) {
+                HostOp &d = out[target];
+                // Moving o back to `target` is valid: everything between
+                // commutes with it.  Everything between also commutes with the
+                // merged op's other part, which was already there.
+                d.qmask |= o.qmask;
+                d.umask |= o.umask;
+                d.emask |= o.emask;
+                d.vbonds.insert(d.vbonds.end(), o.vbonds.begin(), o.vbonds.end());
+                continue;
+            }
+        }
+        out.push_back(o);
+    }
+    ops.swap(out);
+}
+
+}  // namespace
+
+std::vector<HostOp> circuit_ops(const Model &m, int layers)
+{
+    std::vector<HostOp> ops;
+    const int per = m.params_per_layer();
+    for (int l = 0; l < layers; ++l) {
+        const int p0 = l * per;
+        for (int i = 0; i < m.ns; ++i) {
+            HostOp d;
+            d.kind = OP_DIAG;
+            d.param = p0;
+            uint32_t both = qbit(m.qubit(i, 0)) | qbit(m.qubit(i, 1));
+            d.qmask = both;
+            if (m.U != 0.0)
+                d.umask = qbit(m.qubit(i, 0));
+            if (m.eps[i] != 0.0)
+                d.emask = both;
+            if (d.umask || d.emask)
+                ops.push_back(d);
+        }
+        for (int b = 0; b < m.nb; ++b) {
+            if (m.V[b] == 0.0)
+                continue;
+            HostOp d;
+            d.kind = OP_DIAG;
+            d.param = p0;
+            d.qmask = qbit(m.qubit(m.bi[b], 0)) | qbit(m.qubit(m.bi[b], 1)) |
+                      qbit(m.qubit(m.bj[b], 0)) | qbit(m.qubit(m.bj[b], 1));
+            d.vbonds.push_back(b);
+            ops.push_back(d);
+        }
+        for (int s = 1; s < per; ++s) {
+            for (int b = 0; b < m.nb; ++b) {
+                if (m.slot[b] != s)
+                    continue;
+                for (int spin = 0; spin < 2; ++spin) {
+                    HostOp h;
+                    h.kind = OP_HOP;
+                    h.param = p0 + s;
+                    int a = m.qubit(m.bi[b], spin), c = m.qubit(m.bj[b], spin);
+                    h.p = std::min(a, c);
+                    h.q = std::max(a, c);
+                    h.qmask = qbit(a) | qbit(c);
+                    h.t = m.t[b];
+                    ops.push_back(h);
+                }
+            }
+        }
+    }
+    return ops;
+}
+
+std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig &tc)
+{
+    std::vector<HostOp> ops = circuit_ops(m, layers);
+    std::vector<HostPass> passes;
+    if (ops.empty())
+        return passes;
+    const int n = m.nq;
+    const int k = std::min(tc.k, n);
+    const int c = std::min(tc.c, k);
+    if (n <= k) {
+        HostPass p;
+        p.tile = finish_tile(0, n, n);
+        p.ops = ops;
+        merge_diagonals(p.ops);
+        passes.push_back(p);
+        return passes;
+    }
+    uint32_t C = 0;
+    for (int b = 0; b < c; ++b)
+        C |= qbit(b);
+    std::vector<char> done(ops.size(), 0);
+    size_t first = 0;
+    const size_t window = 480;
+    while (first < ops.size()) {
+        std::vector<int> active;
+        for (size_t i = first; i < ops.size() && active.size() < window; ++i)
+            if (!done[i])
+                active.push_back((int)i);
+        // Seeds: no seed, and the qubits of each ready hop.
+        std::vector<uint32_t> seeds{0u};
+        {
+            uint32_t bg = 0, bd = 0;
+            for (int i : active) {
+                const HostOp &o = ops[i];
+                if (o.kind == OP_DIAG) {
+                    if (o.qmask & bg)
+                        bd |= o.qmask;
+                    continue;
+                }
+                if (!((o.qmask & bg) || (o.qmask & bd)))
+                    seeds.push_back(o.qmask);
+                bg |= o.qmask;
+                if (seeds.size() > 48)
+                    break;
+            }
+        }
+        Closure best;
+        best.hops = -1;
+        for (uint32_t sd : seeds) {
+            Closure cl = grow(ops, active, done, C | sd, k);
+            if (cl.inc.empty())
+                continue;
+            if (cl.hops > best.hops || (cl.hops == best.hops && cl.inc.size() > best.inc.size()))
+                best = cl;
+        }
+        HostPass p;
+        p.tile = finish_tile(best.S, n, k);
+        for (int i : best.inc) {
+            p.ops.push_back(ops[i]);
+            done[i] = 1;
+        }
+        merge_diagonals(p.ops);
+        passes.push_back(p);
+        while (first < ops.size() && done[first])
+            ++first;
+    }
+    return passes;
+}
+
+std::vector<HostPass> plan_hamiltonian(const Model &m, const TileConfig &tc)
+{
+    const int n = m.nq;
+    const int k = std::min(tc.k, n);
+    const int c = std::min(tc.c, k);
+    HostOp diag;
+    diag.kind = OP_DIAG;
+    diag.param = -1;
+    for (int i = 0; i < m.ns; ++i) {
+        diag.umask |= qbit(m.qubit(i, 0));
+        if (m.eps[i] != 0.0)
+            diag.emask |= qbit(m.qubit(i, 0)) | qbit(m.qubit(i, 1));
+    }
+    diag.qmask = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
+    for (int b = 0; b < m.nb; ++b)
+        if (m.V[b] != 0.0)
+            diag.vbonds.push_back(b);
+    std::vector<HostOp> terms;
+    for (int b = 0; b < m.nb; ++b)
+        for (int spin = 0; spin < 2; ++spin) {
+            HostOp h;
+            h.kind = OP_HOP;
+            int a = m.qubit(m.bi[b], spin), cq = m.qubit(m.bj[b], spin);
+            h.p = std::min(a, cq);
+            h.q = std::max(a, cq);
+            h.qmask = qbit(a) | qbit(cq);
+            h.t = m.t[b];
+            terms.push_back(h);
+        }
+    std::vector<HostPass> passes;
+    uint32_t C = 0;
+    for (int b = 0; b < c; ++b)
+        C |= qbit(b);
+    std::vector<char> used(terms.size(), 0);
+    size_t left = terms.size();
+    bool first = true;
+    while (left > 0 || first) {
+        uint32_t bestS = C;
+        int bestCount = -1;
+        std::vector<uint32_t> seeds{0u};
+        for (size_t i = 0; i < terms.size(); ++i)
+            if (!used[i])
+                seeds.push_back(terms[i].qmask);
+        for (uint32_t sd : seeds) {
+            uint32_t S = C | sd;
+            if (__builtin_popcount(S) > k)
+                continue;
+            std::vector<char> take(terms.size(), 0);
+            for (;;) {
+                int bi = -1, bn = 99;
+                for (size_t i = 0; i < terms.size(); ++i) {
+                    if (used[i] || take[i])
+                        continue;
+                    uint32_t u = S | terms[i].qmask;
+                    int nw = __builtin_popcount(u) - __builtin_popcount(S);
+                    if (__builtin_popcount(u) <= k && nw < bn) {
+                        bn = nw;
+                        bi = (int)i;
+                    }
+                }
+                if (bi < 0)
+                    break;
+                take[bi] = 1;
+                S |= terms[bi].qmask;
+            }
+            int cnt = 0;
+            for (size_t i = 0; i < terms.size(); ++i)
+                cnt += (!used[i] && (terms[i].qmask & ~S) == 0);
+            if (cnt > bestCount) {
+                bestCount = cnt;
+                bestS = S;
+            }
+        }
+        HostPass p;
+        p.tile = finish_tile(bestS, n, k);
+        uint32_t Sf = 0;
+        for (int b : p.tile)
+            Sf |= qbit(b);
+        if (first)
+            p.ops.push_back(diag);
+        for (size_t i = 0; i < terms.size(); ++i)
+            if (!used[i] && (terms[i].qmask & ~Sf) == 0) {
+                used[i] = 1;
+                --left;
+                p.ops.push_back(terms[i]);
+            }
+        p.flags = first ? PF_HAM_FIRST : 0;
+        first = false;
+        passes.push_back(p);
+    }
+    passes.back().flags |= PF_HAM_LAST;
+    return passes;
+}
+
+}  // namespace hv

@@ -1,0 +1,148 @@
+"""PyTorch-facing wrapper of the gfx950 library: device memory and streams
+come from torch, every step of the path runs in the library's kernels.
+
+    m = Hubbard(nx=2, ny=2, U=4.0)
+    E = m.energy(theta)                 # theta: float64 CUDA/HIP tensor
+    E, g = m.energy_grad(theta)
+    E = EnergyGrad.apply(theta, m)      # differentiable, adjoint backward
+"""
+from __future__ import annotations
+
+import torch
+
+from . import abi
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _require_gpu(t: torch.Tensor, name: str, dtype=None):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (the library has no CPU path)")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Hubbard:
+    """One Hubbard model instance (Eq. (1)/(2)/(15)/(16)) and its HVA circuit."""
+
+    def __init__(self, nx: int, ny: int, *, periodic_x: bool = False, periodic_y: bool = False,
+                 t=None, U: float = 0.0, V=None, eps=None, groups=None):
+        self.handle = abi.hubbard_create(nx, ny, periodic_x, periodic_y, t, U, V, eps, groups)
+        q = abi.hubbard_query(self.handle)
+        self.n_qubits = q["n_qubits"]
+        self.n_bonds = q["n_bonds"]
+        self.n_groups = q["n_groups"]
+        self.params_per_layer = q["params_per_layer"]
+        self.neel_index = q["neel_index"]
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                torch.cuda.synchronize()
+            except Exception:
+                pass
+            abi.hubbard_destroy(h)
+            self.handle = None
+
+    @property
+    def dim(self) -> int:
+        return 1 << self.n_qubits
+
+    def n_params(self, layers: int) -> int:
+        return layers * self.params_per_layer
+
+    def bonds(self):
+        return abi.hubbard_bonds(self.handle)
+
+    def set_tiles(self, fwd_k: int, rev_k: int, c: int) -> None:
+        abi.hubbard_set_tiles(self.handle, fwd_k, rev_k, c)
+        self._ws.clear()
+
+    def workspace(self, layers: int, op: int, device=None) -> torch.Tensor:
+        """Device workspace of at least hubbard_workspace_size bytes; an existing
+        larger buffer of this model is reused (psi sits at its start)."""
+        nbytes = abi.hubbard_workspace_size(self.handle, layers, op)
+        dev = torch.device(device or "cuda")
+        for key, ws in self._ws.items():
+            if ws.numel() >= nbytes and ws.device == dev and (key[1] == op or
+                                                              op == abi.HUBBARD_OP_ENERGY):
+                return ws
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self._ws[(layers, op, str(dev))] = ws
+        return ws
+
+    def _layers(self, theta: torch.Tensor) -> int:
+        _require_gpu(theta, "theta", torch.float64)
+        if theta.numel() % self.params_per_layer:
+            raise ValueError("theta length must be a multiple of params_per_layer")
+        return theta.numel() // self.params_per_layer
+
+    def new_state(self, device="cuda") -> torch.Tensor:
+        psi = torch.empty(self.dim, dtype=torch.complex128, device=device)
+        abi.hubbard_init_neel(self.handle, psi.data_ptr(), _stream())
+        return psi
+
+    def ansatz(self, theta: torch.Tensor, psi: torch.Tensor | None = None) -> torch.Tensor:
+        L = self._layers(theta)
+        if psi is None:
+            psi = self.new_state(theta.device)
+        _require_gpu(psi, "psi", torch.complex128)
+        abi.ansatz_apply(self.handle, theta.data_ptr(), L, psi.data_ptr(), _stream())
+        return psi
+
+    def apply_h(self, psi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _require_gpu(psi, "psi", torch.complex128)
+        if out is None:
+            out = torch.empty_like(psi)
+        abi.hamiltonian_apply(self.handle, psi.data_ptr(), out.data_ptr(), _stream())
+        return out
+
+    def energy(self, theta: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        L = self._layers(theta)
+        ws = self.workspace(L, abi.HUBBARD_OP_ENERGY, theta.device)
+        E = out if out is not None else torch.empty(1, dtype=torch.float64, device=theta.device)
+        abi.energy(self.handle, theta.data_ptr(), L, E.data_ptr(), ws.data_ptr(), ws.numel(),
+                   _stream())
+        return E
+
+    def energy_grad(self, theta: torch.Tensor, E: torch.Tensor | None = None,
+                    grad: torch.Tensor | None = None):
+        L = self._layers(theta)
+        ws = self.workspace(L, abi.HUBBARD_OP_ENERGY_GRAD, theta.device)
+        if E is None:
+            E = torch.empty(1, dtype=torch.float64, device=theta.device)
+        if grad is None:
+            grad = torch.empty(theta.numel(), dtype=torch.float64, device=theta.device)
+        abi.energy_grad(self.handle, theta.data_ptr(), L, E.data_ptr(), grad.data_ptr(),
+                        ws.data_ptr(), ws.numel(), _stream())
+        return E, grad
+
+    def workspace_views(self, layers: int):
+        """(psi, lambda) views into the energy_grad workspace after a call."""
+        ws = self.workspace(layers, abi.HUBBARD_OP_ENERGY_GRAD, "cuda")
+        vb = ((self.dim * 16 + 255) // 256) * 256
+        psi = ws[: self.dim * 16].view(torch.complex128)
+        lam = ws[vb: vb + self.dim * 16].view(torch.complex128)
+        return psi, lam
+
+
+class EnergyGrad(torch.autograd.Function):
+    """E(theta) whose backward is the adjoint gradient computed by the forward
+    call's single reverse sweep (Sec. 2.1)."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, model: Hubbard):
+        E, g = model.energy_grad(theta.detach().contiguous())
+        ctx.save_for_backward(g)
+        return E.reshape(())
+
+    @staticmethod
+    def backward(ctx, gE):
+        (g,) = ctx.saved_tensors
+        return gE * g, None

@@ -97,7 +97,7 @@ BATCH_KINDS = [(1, 4), (1, 5), (1, 6), (1, 7), (1, 8), (1, 9), (1, 10),
                (2, 2), (2, 3), (2, 4), (3, 3)]
 # Parameters per layer the configuration states for each kind: a chain and
 # the 2x2 lattice have [U, two hopping groups]; the others [U, h1, v1, h2, v2].
-BATCH_PER_LAYER = {(1, L): 3 for L in range(2, 17)}
+BATCH_PER_LAYER = {(1, L): 3 for L in range(3, 17)}
 BATCH_PER_LAYER.update({(2, 2): 3, (2, 3): 5, (2, 4): 5, (3, 3): 5})
 
 
