@@ -21,6 +21,10 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # keep SimplifyCFG from merging the per-register-pair code of the
+           # pass kernels into one block with phi'd addresses, which would
+           # force the register tiles into scratch memory
+           "-mllvm", "-simplifycfg-sink-common=false",
            "-Wall", "-Wno-unused-parameter", "-x", "hip"]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
     cmd += ["-o", tmp]

@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <stdexcept>
 #include <vector>
 
 #include "../../include/hubbard.h"
@@ -16,14 +17,9 @@
 #include "hubvqe.hpp"
 
 namespace hv {
-__global__ void k_forward(DevPass, const DevOp *, const DevVBond *, const double *,
-                          const DevModel *, double2 *);
-__global__ void k_reverse(DevPass, const DevOp *, const DevVBond *, const double *,
-                          const DevModel *, double2 *, double2 *, double *, int);
-__global__ void k_hamiltonian(DevPass, const DevOp *, const DevVBond *, const DevModel *,
-                              const double2 *, double2 *, double *, int);
-__global__ void k_expect(DevPass, const DevOp *, const DevVBond *, const DevModel *,
-                         const double2 *, double *, int);
+template <int MODE, bool GEN>
+__global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,
+                       const DevModel *, double2 *, double2 *, double *, int);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t);
 __global__ void k_reduce(const double *, int, const int32_t *, const int32_t *, const int32_t *,
                          const double *, double *, double *, int);
@@ -41,8 +37,8 @@ hubbard_status fail(hubbard_status s, const std::string &msg)
     return s;
 }
 
-constexpr int kThreads = 256;
 constexpr int kGridMax = 2048;
+enum { M_FWD = 0, M_REV = 1, M_HAM = 2, M_EXP = 3 };
 
 enum ProgKind { PROG_ANSATZ = 0, PROG_HAM = 1, PROG_ENERGY = 2, PROG_GRAD = 3 };
 
@@ -51,15 +47,18 @@ struct PassList {
     std::vector<DevPass> pass;
     std::vector<int> grid;
     std::vector<int> smem;
+    std::vector<int> threads;
 };
 
 // Everything one call needs on one device.
 struct Program {
     int kind = 0;
     int layers = 0;
+    bool general = false;   // diagonal has eps or V terms
     PassList fwd, ham, rev, exp;
     // device tables
     DevOp *d_ops = nullptr;
+    DevPhase *d_phases = nullptr;
     DevVBond *d_vb = nullptr;
     int32_t *d_row_ptr = nullptr, *d_row_idx = nullptr, *d_row_nblk = nullptr;
     double *d_scale = nullptr;
@@ -70,6 +69,7 @@ struct Program {
     ~Program()
     {
         (void)hipFree(d_ops);
+        (void)hipFree(d_phases);
         (void)hipFree(d_vb);
         (void)hipFree(d_row_ptr);
         (void)hipFree(d_row_idx);
@@ -107,6 +107,7 @@ namespace {
 struct Builder {
     const Model &m;
     std::vector<DevOp> ops;
+    std::vector<DevPhase> phases;
     std::vector<DevVBond> vb;
     std::vector<int> row_param;   // param (or -1 for energy) of each partial row
     std::vector<int> row_nblk;
@@ -128,13 +129,18 @@ struct Builder {
             P.c = c;
             uint32_t S = 0;
             for (int j = 0; j < P.k; ++j) {
-                P.tile_pos[j] = (uint8_t)hp.tile[j];
                 S |= 1u << hp.tile[j];
+                if (j >= c)
+                    P.hi_mask |= 1u << hp.tile[j];
             }
             int nf = 0;
+            std::vector<int> free_pos;
             for (int b = 0; b < n; ++b)
-                if (!(S & (1u << b)))
-                    P.free_pos[nf++] = (uint8_t)b;
+                if (!(S & (1u << b))) {
+                    P.free_mask |= 1u << b;
+                    free_pos.push_back(b);
+                    ++nf;
+                }
             P.nfree = nf;
             P.flags = hp.flags;
             P.op_begin = (int)ops.size();
@@ -148,6 +154,7 @@ struct Builder {
                 row_nblk.push_back(grid);
             }
             int n_diag = 0;
+            std::vector<int> op_pl, op_ql;   // tile-local bits of each op's qubits
             for (const HostOp &h : hp.ops) {
                 DevOp o;
                 std::memset(&o, 0, sizeof(o));
@@ -176,19 +183,21 @@ struct Builder {
                         if (hp.tile[j] == h.q)
                             ql = j;
                     }
-                    o.pl = pl;
-                    o.ql = ql;
+                    op_pl.push_back(pl);
+                    op_ql.push_back(ql);
                     uint32_t bl = 0, bf = 0;
                     for (int j = 0; j < P.k; ++j)
                         if (hp.tile[j] > h.p && hp.tile[j] < h.q)
                             bl |= 1u << j;
                     for (int f = 0; f < nf; ++f)
-                        if (P.free_pos[f] > h.p && P.free_pos[f] < h.q)
+                        if (free_pos[f] > h.p && free_pos[f] < h.q)
                             bf |= 1u << f;
                     o.bm_local = bl;
                     o.bm_free = bf;
                     o.t = h.t;
                 } else {
+                    op_pl.push_back(-1);
+                    op_ql.push_back(-1);
                     o.dtab = n_diag++;
                     o.umask = h.umask;
                     o.emask = h.emask;
@@ -210,9 +219,67 @@ struct Builder {
             P.n_ops = (int)hp.ops.size();
             P.n_diag = n_diag;
             P.n_red = (int)red_of.size();
+            // register layouts
+            const int rbits = std::min(P.k, kRegBits);
+            P.tbits = P.k - rbits;
+            P.phase_begin = (int)phases.size();
+            P.n_phases = (int)hp.phases.size();
+            for (const HostPhase &hph : hp.phases) {
+                DevPhase D;
+                std::memset(&D, 0, sizeof(D));
+                D.op_begin = hph.op_begin;
+                D.op_end = hph.op_end;
+                uint32_t regmask = 0;
+                for (int b : hph.regs)
+                    regmask |= 1u << b;
+                D.tmask = 0;
+                for (int b = 0; b < P.k; ++b)
+                    if (!((regmask >> b) & 1u))
+                        D.tmask |= 1u << b;
+                D.valid = 0;
+                for (int j = 0; j < kRegs; ++j) {
+                    uint32_t lo = 0, go = 0;
+                    bool ok = true;
+                    for (int i = 0; i < kRegBits; ++i) {
+                        if (!((j >> i) & 1))
+                            continue;
+                        if (i >= (int)hph.regs.size()) {
+                            ok = false;   // phantom register bit of a tile < 16
+                            continue;
+                        }
+                        lo |= 1u << hph.regs[i];
+                        go |= 1u << hp.tile[hph.regs[i]];
+                    }
+                    D.roff[j] = lo;
+                    D.goff[j] = go;
+                    if (ok)
+                        D.valid |= 1u << j;
+                }
+                // pair index of each hop of the phase
+                for (int o = hph.op_begin; o < hph.op_end; ++o) {
+                    DevOp &op = ops[P.op_begin + o];
+                    if (op.kind != OP_HOP)
+                        continue;
+                    int ra = -1, rb = -1;
+                    for (size_t i = 0; i < hph.regs.size(); ++i) {
+                        if (hph.regs[i] == op_pl[o])
+                            ra = (int)i;
+                        if (hph.regs[i] == op_ql[o])
+                            rb = (int)i;
+                    }
+                    if (ra < 0 || rb < 0)
+                        throw std::runtime_error("hop outside its phase's register bits");
+                    int a = std::min(ra, rb), b = std::max(ra, rb);
+                    static const int pair_of[4][4] = {
+                        {-1, 0, 1, 2}, {0, -1, 3, 4}, {1, 3, -1, 5}, {2, 4, 5, -1}};
+                    op.pair = pair_of[a][b];
+                }
+                phases.push_back(D);
+            }
             pl.pass.push_back(P);
             pl.grid.push_back(grid);
             pl.smem.push_back(0);
+            pl.threads.push_back(1 << P.tbits);
         }
         return pl;
     }
@@ -230,12 +297,12 @@ int max_smem_per_block()
     return v;
 }
 
-void set_smem(PassList &pl, int n_vec, bool force_red1)
+void set_smem(PassList &pl, bool force_red1)
 {
     for (size_t i = 0; i < pl.pass.size(); ++i) {
         const DevPass &P = pl.pass[i];
         int nred = force_red1 ? 1 : P.n_red;
-        pl.smem[i] = (int)smem_plan(P.k, P.c, n_vec, P.n_ops, P.n_diag, nred, kThreads).total;
+        pl.smem[i] = (int)smem_plan(P.k, P.c, P.n_ops, P.n_diag, nred, pl.threads[i]).total;
     }
 }
 
@@ -247,20 +314,13 @@ int max_of(const PassList &pl)
     return m;
 }
 
-std::vector<HostPass> reversed(std::vector<HostPass> p)
-{
-    std::reverse(p.begin(), p.end());
-    for (HostPass &x : p)
-        std::reverse(x.ops.begin(), x.ops.end());
-    return p;
-}
-
 // Builds host plans only (no device work): used by introspection and upload.
 void plan_program(hubbard_model *h, int kind, int layers, int smem_limit, Program &pr)
 {
     const Model &m = h->m;
     pr.kind = kind;
     pr.layers = layers;
+    pr.general = m.general;
     if (kind != PROG_HAM)
         pr.h_fwd = plan_forward(m, layers, h->fwd_tc);
     TileConfig tc2 = h->rev_tc;
@@ -268,12 +328,12 @@ void plan_program(hubbard_model *h, int kind, int layers, int smem_limit, Progra
         if (kind == PROG_HAM || kind == PROG_GRAD)
             pr.h_ham = plan_hamiltonian(m, tc2);
         if (kind == PROG_GRAD)
-            pr.h_rev = reversed(plan_forward(m, layers, tc2));
+            pr.h_rev = reversed_passes(plan_forward(m, layers, tc2));
         // check LDS fit of the two-vector kernels; shrink the tile if needed
         Builder b(m);
         PassList ph = b.add(pr.h_ham, 2, true), pv = b.add(pr.h_rev, 1, false);
-        set_smem(ph, 2, false);
-        set_smem(pv, 2, false);
+        set_smem(ph, false);
+        set_smem(pv, false);
         if (std::max(max_of(ph), max_of(pv)) <= smem_limit || tc2.k <= 6)
             break;
         tc2.k -= 1;
@@ -290,10 +350,15 @@ hubbard_status upload_program(hubbard_model *h, DeviceState &ds, Program &pr)
     pr.ham = b.add(pr.h_ham, pr.kind == PROG_GRAD ? 2 : 0, true);
     pr.rev = b.add(pr.h_rev, 1, false);
     pr.exp = b.add(pr.h_exp, 2, false);
-    set_smem(pr.fwd, 1, false);
-    set_smem(pr.ham, 2, false);
-    set_smem(pr.rev, 2, false);
-    set_smem(pr.exp, 1, true);
+    set_smem(pr.fwd, false);
+    set_smem(pr.ham, false);
+    set_smem(pr.rev, false);
+    set_smem(pr.exp, true);
+    int lim = max_smem_per_block();
+    for (const PassList *l : {&pr.fwd, &pr.ham, &pr.rev, &pr.exp})
+        if (max_of(*l) > lim)
+            return fail(HUBBARD_ERR_ARG, "a pass needs more LDS than a workgroup may use; "
+                                         "choose smaller tiles");
     const int P = pr.layers * m.params_per_layer();
     // reduction map: output 0 = E, outputs 1..P = gradient
     pr.n_out = (pr.kind == PROG_GRAD) ? 1 + P : 1;
@@ -330,6 +395,9 @@ hubbard_status upload_program(hubbard_model *h, DeviceState &ds, Program &pr)
     hipError_t e = hipSuccess;
     e = up((void **)&pr.d_ops, b.ops.data(), b.ops.size() * sizeof(DevOp));
     if (e == hipSuccess)
+        e = up((void **)&pr.d_phases, b.phases.empty() ? nullptr : b.phases.data(),
+               b.phases.size() * sizeof(DevPhase));
+    if (e == hipSuccess)
         e = up((void **)&pr.d_vb, b.vb.empty() ? nullptr : b.vb.data(), b.vb.size() * sizeof(DevVBond));
     if (e == hipSuccess)
         e = up((void **)&pr.d_row_ptr, row_ptr.data(), row_ptr.size() * sizeof(int32_t));
@@ -354,10 +422,13 @@ hubbard_status ensure_model(hubbard_model *h, int dev, DeviceState &ds)
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
         int lim = max_smem_per_block();
-        (void)hipFuncSetAttribute((const void *)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        (void)hipFuncSetAttribute((const void *)k_reverse, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        (void)hipFuncSetAttribute((const void *)k_hamiltonian, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        (void)hipFuncSetAttribute((const void *)k_expect, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        const void *fns[] = {
+            (const void *)k_pass<M_FWD, false>, (const void *)k_pass<M_REV, false>,
+            (const void *)k_pass<M_HAM, false>, (const void *)k_pass<M_EXP, false>,
+            (const void *)k_pass<M_FWD, true>,  (const void *)k_pass<M_REV, true>,
+            (const void *)k_pass<M_HAM, true>,  (const void *)k_pass<M_EXP, true>};
+        for (const void *f : fns)
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     });
     (void)dev;
     const Model &m = h->m;
@@ -427,30 +498,41 @@ hubbard_status check_launch(const char *what)
     return HUBBARD_OK;
 }
 
+template <int MODE>
+void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, const double *theta,
+                 const double2 *a, const double2 *b, double *partial, hipStream_t s)
+{
+    for (size_t i = 0; i < pl.pass.size(); ++i) {
+        if (pr.general)
+            hipLaunchKernelGGL((k_pass<MODE, true>), dim3(pl.grid[i]), dim3(pl.threads[i]),
+                               pl.smem[i], s, pl.pass[i], pr.d_phases, pr.d_ops, pr.d_vb, theta,
+                               ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax);
+        else
+            hipLaunchKernelGGL((k_pass<MODE, false>), dim3(pl.grid[i]), dim3(pl.threads[i]),
+                               pl.smem[i], s, pl.pass[i], pr.d_phases, pr.d_ops, pr.d_vb, theta,
+                               ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax);
+    }
+}
+
 hubbard_status run_forward(const Program &pr, const DeviceState &ds, const double *theta,
                            double2 *psi, hipStream_t s)
 {
-    for (size_t i = 0; i < pr.fwd.pass.size(); ++i)
-        hipLaunchKernelGGL(k_forward, dim3(pr.fwd.grid[i]), dim3(kThreads), pr.fwd.smem[i], s,
-                           pr.fwd.pass[i], pr.d_ops, pr.d_vb, theta, ds.d_model, psi);
+    launch_list<M_FWD>(pr, ds, pr.fwd, theta, psi, nullptr, nullptr, s);
     return check_launch("forward pass");
 }
 
 hubbard_status run_ham(const Program &pr, const DeviceState &ds, const double2 *psi, double2 *phi,
                        double *partial, hipStream_t s)
 {
-    for (size_t i = 0; i < pr.ham.pass.size(); ++i)
-        hipLaunchKernelGGL(k_hamiltonian, dim3(pr.ham.grid[i]), dim3(kThreads), pr.ham.smem[i], s,
-                           pr.ham.pass[i], pr.d_ops, pr.d_vb, ds.d_model, psi, phi, partial,
-                           kGridMax);
+    launch_list<M_HAM>(pr, ds, pr.ham, nullptr, psi, phi, partial, s);
     return check_launch("hamiltonian pass");
 }
 
 hubbard_status run_init(const hubbard_model *h, double2 *psi, hipStream_t s)
 {
     const uint64_t dim = (uint64_t)1 << h->m.nq;
-    uint64_t blocks = std::min<uint64_t>((dim + kThreads - 1) / kThreads, 8192);
-    hipLaunchKernelGGL(k_init_basis, dim3((unsigned)blocks), dim3(kThreads), 0, s, psi, dim,
+    uint64_t blocks = std::min<uint64_t>((dim + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_init_basis, dim3((unsigned)blocks), dim3(256), 0, s, psi, dim,
                        (uint64_t)h->m.neel);
     return check_launch("init");
 }
@@ -652,10 +734,7 @@ hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers, do
     if ((st = run_forward(*pr, *ds, theta_dev, psi, s)) != HUBBARD_OK)
         return st;
     mark(h, 1, s);
-    for (size_t i = 0; i < pr->exp.pass.size(); ++i)
-        hipLaunchKernelGGL(k_expect, dim3(pr->exp.grid[i]), dim3(kThreads), pr->exp.smem[i], s,
-                           pr->exp.pass[i], pr->d_ops, pr->d_vb, ds->d_model, psi, partial,
-                           kGridMax);
+    launch_list<M_EXP>(*pr, *ds, pr->exp, nullptr, psi, nullptr, partial, s);
     if ((st = check_launch("expectation pass")) != HUBBARD_OK)
         return st;
     mark(h, 2, s);
@@ -689,10 +768,7 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
     if ((st = run_ham(*pr, *ds, psi, lam, partial, s)) != HUBBARD_OK)
         return st;
     mark(h, 2, s);
-    for (size_t i = 0; i < pr->rev.pass.size(); ++i)
-        hipLaunchKernelGGL(k_reverse, dim3(pr->rev.grid[i]), dim3(kThreads), pr->rev.smem[i], s,
-                           pr->rev.pass[i], pr->d_ops, pr->d_vb, theta_dev, ds->d_model, psi, lam,
-                           partial, kGridMax);
+    launch_list<M_REV>(*pr, *ds, pr->rev, theta_dev, psi, lam, partial, s);
     if ((st = check_launch("reverse pass")) != HUBBARD_OK)
         return st;
     mark(h, 3, s);

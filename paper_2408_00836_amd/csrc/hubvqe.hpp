@@ -40,7 +40,8 @@ struct DevOp {
     int32_t param;      // theta index (-1 for Hamiltonian terms)
     int32_t red;        // reduction row within the pass (-1: none)
     int32_t dtab;       // DIAG: index of its phase table within the pass
-    int32_t pl, ql;     // HOP: tile-local bit positions of the two qubits
+    int32_t pair;       // HOP: register-bit pair (0..5: 01 02 03 12 13 23) in its phase
+    int32_t pad0;
     uint32_t bm_local;  // HOP: Jordan-Wigner between-mask over tile-local bits
     uint32_t bm_free;   // HOP: between-mask over the free (tile-index) bits
     uint32_t umask;     // DIAG: spin-up qubits of the sites whose U term it carries
@@ -51,6 +52,22 @@ struct DevOp {
     double pad;
 };
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
+
+// Register layout of one phase of a pass.  Each thread holds 16 amplitudes of
+// the tile in registers: register j holds tile-local index tloc | roff[j],
+// where tloc deposits the thread id over the local bits in tmask and roff[j]
+// deposits j over the phase's four register bits.  Gates of the phase act on
+// register bits only; between phases the tile is re-laid out through LDS.
+constexpr int kRegs = 16;
+constexpr int kRegBits = 4;
+struct DevPhase {
+    int32_t op_begin, op_end;   // ops of this phase (absolute indices)
+    uint32_t roff[kRegs];       // tile-local bits of register j
+    uint32_t goff[kRegs];       // global index bits of register j
+    uint32_t tmask;             // tile-local bits that carry the thread id (ascending)
+    uint32_t valid;             // bit j: register j holds an amplitude (tiles < 16)
+    uint32_t pad[2];
+};
 
 // A V bond as the device reads it: qubits (i up, i dn, j up, j dn) and V_b.
 struct DevVBond {
@@ -70,9 +87,12 @@ struct DevPass {
     int32_t red_base;   // first partial row of this pass
     int32_t n_red;      // partial rows written by this pass
     int32_t flags;
-    int32_t pad;
-    uint8_t tile_pos[16];   // global bit of tile bit j
-    uint8_t free_pos[32];   // global bit of free bit f
+    int32_t phase_begin;   // first phase in the plan's phase array
+    int32_t n_phases;      // phases (the first and last are the load/store layouts)
+    int32_t tbits;         // thread-id bits: a workgroup has 2^tbits threads
+    uint32_t hi_mask;      // global bits of tile bits c..k-1 (tile bits 0..c-1 = global 0..c-1)
+    uint32_t free_mask;    // global bits not in the tile (the tile id is deposited here)
+    int32_t pad2[2];
 };
 
 // Model constants in device memory.
@@ -84,18 +104,20 @@ struct DevModel {
     double eps_byte[4][256];  // sum of eps over set qubits of each index byte
 };
 
-// LDS carve-up shared by host (launch size) and device.
+// LDS carve-up shared by host (launch size) and device: one tile-sized
+// exchange buffer, the tile's global-offset table, per-op rotation
+// coefficients, diagonal phase tables and per-thread reduction rows.
 struct SmemPlan {
-    uint32_t tiles, offs, opc, dtab, red, total;
+    uint32_t xbuf, offs, opc, dtab, red, total;
 };
 
-__host__ __device__ inline SmemPlan smem_plan(int k, int c, int n_vec, int n_ops, int n_diag,
-                                              int n_red, int threads)
+__host__ __device__ inline SmemPlan smem_plan(int k, int c, int n_ops, int n_diag, int n_red,
+                                              int threads)
 {
     SmemPlan s;
     uint32_t at = 0;
-    s.tiles = at;
-    at += (uint32_t)n_vec * (1u << k) * 16u;
+    s.xbuf = at;
+    at += (1u << k) * 16u;
     s.offs = at;
     at += ((1u << (k - c)) * 4u + 15u) & ~15u;
     s.opc = at;
@@ -137,9 +159,17 @@ struct HostOp {
     std::vector<int> vbonds;
 };
 
+// Ops [op_begin, op_end) of a pass whose hopping terms all act on the
+// phase's register bits `regs` (tile-local bit indices, at most four).
+struct HostPhase {
+    std::vector<int> regs;
+    int op_begin = 0, op_end = 0;
+};
+
 struct HostPass {
-    std::vector<int> tile;        // sorted global bit positions
-    std::vector<HostOp> ops;      // application order
+    std::vector<int> tile;          // sorted global bit positions
+    std::vector<HostOp> ops;        // application order (grouped by phase)
+    std::vector<HostPhase> phases;  // register layouts, in order
     int flags = 0;
 };
 
@@ -153,5 +183,10 @@ std::vector<HostOp> circuit_ops(const Model &m, int layers);
 std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig &tc);
 // Passes that together apply H (terms split over tiles, D in the first).
 std::vector<HostPass> plan_hamiltonian(const Model &m, const TileConfig &tc);
+// Split a pass's ops into register phases (reorders ops within the pass only
+// where they commute) and add load/store layouts.
+void plan_phases(HostPass &p);
+// The same passes un-applied: pass order, phase order and op order reversed.
+std::vector<HostPass> reversed_passes(std::vector<HostPass> p);
 
 }  // namespace hv

@@ -1,17 +1,25 @@
 // kernels.hip -- gfx950 kernels of the Hubbard state-vector engine.
 //
-// Every kernel streams the complex128 state vector through LDS in tiles of
-// 2^k amplitudes.  The tile's index bits are the pass's chosen qubits; the
-// other n-k bits (the tile id) are spread over the grid with a grid-stride
-// loop.  Tile bits 0..c-1 are the low c bits of the amplitude index, so every
-// global access is a run of 2^c contiguous 16-byte amplitudes.
+// A pass streams the complex128 state vector (and, for the adjoint and H
+// passes, a second vector) through registers in tiles of 2^k amplitudes.
+// The tile's index bits are the pass's chosen qubits; the other n-k bits (the
+// tile id) are spread over the grid with a grid-stride loop.  Tile bits
+// 0..c-1 are the low bits of the amplitude index, and the load/store layout
+// puts them on lanes 0..15, so every global access is a run of >= 256
+// contiguous bytes.
+//
+// Inside a tile each thread holds 16 amplitudes in registers (four
+// "register bits" of the tile index).  A pass is a sequence of phases; every
+// hopping term of a phase acts on two of its register bits, so it runs
+// entirely in registers.  Between phases the tile is re-laid out through one
+// LDS exchange (XOR-swizzled slots against bank conflicts).
 //
 // Operations (see hubvqe.hpp):
 //   OP_HOP   exp(-i th (-t)(a+_p a_q + h.c.)) on the pairs x <-> x^(2^p+2^q)
 //            with exactly one of p, q occupied.  On such a pair the term is
 //            s * [[0,1],[1,0]] with the Jordan-Wigner sign
 //            s = (-1)^popcount(x & between(p,q)), so the gate is the rotation
-//            (cos(th t), i s sin(th t)) -- no other amplitude changes.
+//            (cos(th t), i s sin(th t)); no other amplitude changes.
 //   OP_DIAG  exp(-i th D_sub) with D_sub = U * #{doubly occupied sites in the
 //            op's set} + sum eps over its qubits + sum V_b n_i n_j over its bonds.
 // No MFMA: nothing here is a dense contraction; the bound is HBM bandwidth.
@@ -21,29 +29,52 @@
 
 namespace hv {
 
-__device__ __forceinline__ uint32_t insert_zero(uint32_t x, int pos)
+enum Mode { M_FWD = 0, M_REV = 1, M_HAM = 2, M_EXP = 3 };
+
+// Bit deposit: the low bits of x go, in order, to the set bits of mask.  x and
+// mask are wave-uniform wherever this is called, so it runs on the scalar unit.
+__device__ __forceinline__ uint32_t pdep32(uint32_t x, uint32_t mask)
 {
-    uint32_t lo = x & ((1u << pos) - 1u);
-    return ((x >> pos) << (pos + 1)) | lo;
+    uint32_t r = 0;
+    for (uint32_t m = mask; m; m &= m - 1u) {
+        if (x & 1u)
+            r |= m & (0u - m);
+        x >>= 1;
+    }
+    return r;
 }
 
-// Global index bits contributed by the tile id (deposit over the free bits).
-__device__ __forceinline__ uint32_t tile_base(uint64_t tile, const DevPass &P)
+// LDS slot of tile-local index l: the low four bits are XORed with a fold of
+// the higher bits so that lanes whose indices differ only in high bits land
+// in different banks.  A bijection on [0, 2^k).
+__device__ __forceinline__ uint32_t slot(uint32_t l)
 {
-    uint32_t g = 0;
-    for (int f = 0; f < P.nfree; ++f)
-        g |= (uint32_t)((tile >> f) & 1u) << P.free_pos[f];
-    return g;
+    return l ^ (((l >> 4) ^ (l >> 8)) & 15u);
 }
 
-// Diagonal sub-term value D_sub(g) for the general model.
+// Deposit the thread id over the local bits of tmask (lowest id bit into the
+// lowest set bit).  tmask is uniform, so the loop is scalar control flow.
+__device__ __forceinline__ uint32_t thread_local_index(uint32_t tmask, int tid)
+{
+    uint32_t t = 0;
+    for (int i = 0; tmask; ++i) {
+        const uint32_t low = tmask & (0u - tmask);
+        if ((tid >> i) & 1)
+            t |= low;
+        tmask ^= low;
+    }
+    return t;
+}
+
+// Diagonal sub-term value D_sub(g); GEN: the model has eps or V terms.
+template <bool GEN>
 __device__ __forceinline__ double diag_value(const DevOp &op, uint32_t g, const DevModel *M,
                                              const DevVBond *vb)
 {
     uint32_t up = g & op.umask;
     uint32_t dn = (uint32_t)((uint64_t)g >> M->ns) & op.umask;
     double d = M->U * (double)__popc(up & dn);
-    if (M->general) {
+    if constexpr (GEN) {
         uint32_t e = g & op.emask;
         d += M->eps_byte[0][e & 255u] + M->eps_byte[1][(e >> 8) & 255u] +
              M->eps_byte[2][(e >> 16) & 255u] + M->eps_byte[3][(e >> 24) & 255u];
@@ -62,129 +93,108 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Per-WG set-up shared by all pass kernels: tile offset table, per-op
-// rotation coefficients and (U-count models) diagonal phase tables.
-// sign = +1 applies the gates, -1 un-applies them.
-__device__ void pass_setup(const DevPass &P, const DevOp *ops, const double *theta,
-                           const DevModel *M, double sign, char *smem, const SmemPlan &sp)
-{
-    const int T = blockDim.x, tid = threadIdx.x;
-    uint32_t *offs = (uint32_t *)(smem + sp.offs);
-    double2 *opc = (double2 *)(smem + sp.opc);
-    double2 *dtab = (double2 *)(smem + sp.dtab);
-    const int nhi = P.k - P.c;
-    for (int i = tid; i < (1 << nhi); i += T) {
-        uint32_t o = 0;
-        for (int j = 0; j < nhi; ++j)
-            if ((i >> j) & 1)
-                o |= 1u << P.tile_pos[P.c + j];
-        offs[i] = o;
-    }
-    for (int o = tid; o < P.n_ops; o += T) {
-        const DevOp op = ops[P.op_begin + o];
-        if (op.kind == OP_HOP && op.param >= 0) {
-            double s, c;
-            sincos(theta[op.param] * op.t, &s, &c);
-            opc[o] = make_double2(c, sign * s);
-        }
-    }
-    if (!M->general) {
-        for (int o = 0; o < P.n_ops; ++o) {
-            const DevOp op = ops[P.op_begin + o];
-            if (op.kind != OP_DIAG || op.param < 0)
-                continue;
-            for (int mcount = tid; mcount < kDiagTab; mcount += T) {
-                double s, c;
-                sincos(theta[op.param] * (M->U * (double)mcount), &s, &c);
-                dtab[op.dtab * kDiagTab + mcount] = make_double2(c, -sign * s);
-            }
-        }
-    }
-}
-
-// exp(-i sign th D_sub) for amplitude index g.
-__device__ __forceinline__ double2 diag_phase(const DevOp &op, uint32_t g, const DevModel *M,
-                                              const DevVBond *vb, const double *theta,
-                                              double sign, const double2 *dtab)
-{
-    if (!M->general) {
-        uint32_t up = g & op.umask;
-        uint32_t dn = (uint32_t)((uint64_t)g >> M->ns) & op.umask;
-        return dtab[op.dtab * kDiagTab + __popc(up & dn)];
-    }
-    double s, c;
-    sincos(theta[op.param] * diag_value(op, g, M, vb), &s, &c);
-    return make_double2(c, -sign * s);
-}
-
-// ------------------------------------------------------------ forward pass --
-
-__global__ void __launch_bounds__(256)
-k_forward(DevPass P, const DevOp *__restrict__ ops, const DevVBond *__restrict__ vb,
-          const double *__restrict__ theta, const DevModel *__restrict__ M,
-          double2 *__restrict__ psi)
-{
-    extern __shared__ __align__(16) char smem[];
-    const int T = blockDim.x, tid = threadIdx.x;
-    const SmemPlan sp = smem_plan(P.k, P.c, 1, P.n_ops, P.n_diag, 0, T);
-    double2 *tile = (double2 *)(smem + sp.tiles);
-    const uint32_t *offs = (const uint32_t *)(smem + sp.offs);
-    const double2 *opc = (const double2 *)(smem + sp.opc);
-    const double2 *dtab = (const double2 *)(smem + sp.dtab);
-    pass_setup(P, ops, theta, M, 1.0, smem, sp);
-    __syncthreads();
-
-    const int k = P.k, c = P.c;
-    const uint32_t cmask = (1u << c) - 1u;
-    const uint32_t tsize = 1u << k;
-    const uint64_t ntiles = (uint64_t)1 << P.nfree;
-    for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
-        const uint32_t base = tile_base(tl, P);
-        for (uint32_t l = tid; l < tsize; l += T)
-            tile[l] = psi[(uint64_t)(base | offs[l >> c] | (l & cmask))];
-        __syncthreads();
-        for (int o = 0; o < P.n_ops; ++o) {
-            const DevOp op = ops[P.op_begin + o];
-            if (op.kind == OP_DIAG) {
-                for (uint32_t l = tid; l < tsize; l += T) {
-                    uint32_t g = base | offs[l >> c] | (l & cmask);
-                    tile[l] = cmul(tile[l], diag_phase(op, g, M, vb, theta, 1.0, dtab));
-                }
-            } else {
-                const double cs = opc[o].x, sn = opc[o].y;
-                const uint32_t par0 = __popc((uint32_t)tl & op.bm_free) & 1u;
-                const int lo = min(op.pl, op.ql), hi = max(op.pl, op.ql);
-                const uint32_t flip = (1u << op.pl) | (1u << op.ql);
-                for (uint32_t j = tid; j < (tsize >> 2); j += T) {
-                    uint32_t x = insert_zero(insert_zero(j, lo), hi) | (1u << op.pl);
-                    uint32_t y = x ^ flip;
-                    uint32_t par = (__popc(x & op.bm_local) + par0) & 1u;
-                    double ss = par ? -sn : sn;
-                    double2 a = tile[x], b = tile[y];
-                    tile[x] = make_double2(cs * a.x - ss * b.y, cs * a.y + ss * b.x);
-                    tile[y] = make_double2(cs * b.x - ss * a.y, cs * b.y + ss * a.x);
-                }
-            }
-            __syncthreads();
-        }
-        for (uint32_t l = tid; l < tsize; l += T)
-            psi[(uint64_t)(base | offs[l >> c] | (l & cmask))] = tile[l];
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------ reverse pass --
-// Un-applies the pass's ops (listed in un-application order; angle -th) to psi
-// and lambda and
-// accumulates, per op, Im <lambda| G |psi> into the op's reduction row:
-//   HOP : (-t) s (conj(lam_x) psi_y + conj(lam_y) psi_x) over the pairs
-//   DIAG: D_sub(b) conj(lam_b) psi_b
-// (the generator commutes with its own gate, so evaluating before the
-// un-application is exact).  Row sums land in partial[row * stride + block].
-
 __device__ __forceinline__ double im_conj_mul(double2 a, double2 b)
 {
     return a.x * b.y - a.y * b.x;   // Im(conj(a) b)
+}
+
+__device__ __forceinline__ double re_conj_mul(double2 a, double2 b)
+{
+    return a.x * b.x + a.y * b.y;   // Re(conj(a) b)
+}
+
+// (x, y) <- (c x + i s y, i s x + c y)
+__device__ __forceinline__ void rotate(double2 &x, double2 &y, double c, double s)
+{
+    double2 a = x, b = y;
+    x = make_double2(c * a.x - s * b.y, c * a.y + s * b.x);
+    y = make_double2(c * b.x - s * a.y, c * b.y + s * a.x);
+}
+
+// Per-op context of a hopping term applied in registers.
+struct PairCtx {
+    double cs, sn, t;      // rotation (cos, sin) and bond hopping
+    uint32_t par0, bm;     // sign parity from thread/tile bits; between-mask
+    const uint32_t *roff;  // tile-local bits of each register (uniform)
+    double acc;            // reduction of the op
+};
+
+// The pair (J, JJ) of registers that the term couples; J has the term's
+// first register bit set and the second clear.  All register indices are
+// compile-time constants, so the register arrays never go to scratch.
+template <int MODE, int NV, int J, int JJ>
+__device__ __forceinline__ void pair_op(double2 (&v)[NV][kRegs], PairCtx &x)
+{
+    const uint32_t par = (x.par0 + __popc(x.roff[J] & x.bm)) & 1u;
+    if constexpr (MODE == 0) {            // forward gate
+        rotate(v[0][J], v[0][JJ], x.cs, par ? -x.sn : x.sn);
+    } else if constexpr (MODE == 1) {     // reverse: reduce, then un-apply
+        double w = im_conj_mul(v[NV - 1][J], v[0][JJ]) + im_conj_mul(v[NV - 1][JJ], v[0][J]);
+        x.acc += par ? -w : w;
+        const double ss = par ? -x.sn : x.sn;
+        rotate(v[0][J], v[0][JJ], x.cs, ss);
+        rotate(v[NV - 1][J], v[NV - 1][JJ], x.cs, ss);
+    } else if constexpr (MODE == 2) {     // phi += (-t) s (swap) psi
+        const double w = par ? x.t : -x.t;
+        v[NV - 1][J].x += w * v[0][JJ].x;
+        v[NV - 1][J].y += w * v[0][JJ].y;
+        v[NV - 1][JJ].x += w * v[0][J].x;
+        v[NV - 1][JJ].y += w * v[0][J].y;
+    } else {                              // expectation
+        const double r = re_conj_mul(v[0][J], v[0][JJ]);
+        x.acc += par ? -r : r;
+    }
+}
+
+template <int MODE, int NV, int A, int B, int X>
+__device__ __forceinline__ void pair_at(double2 (&v)[NV][kRegs], PairCtx &x)
+{
+    constexpr int C = (A != 0 && B != 0) ? 0 : ((A != 1 && B != 1) ? 1 : 2);
+    constexpr int D = 6 - A - B - C;   // the fourth register bit
+    constexpr int J = (1 << A) | ((X & 1) << C) | (((X >> 1) & 1) << D);
+    pair_op<MODE, NV, J, J ^ ((1 << A) | (1 << B))>(v, x);
+}
+
+template <int MODE, int NV, int A, int B>
+__device__ __forceinline__ void pairs4(double2 (&v)[NV][kRegs], PairCtx &x)
+{
+    pair_at<MODE, NV, A, B, 0>(v, x);
+    pair_at<MODE, NV, A, B, 1>(v, x);
+    pair_at<MODE, NV, A, B, 2>(v, x);
+    pair_at<MODE, NV, A, B, 3>(v, x);
+}
+
+template <int MODE, int NV>
+__device__ __forceinline__ void hop_regs(int pair, double2 (&v)[NV][kRegs], PairCtx &x)
+{
+    switch (pair) {
+    case 0: pairs4<MODE, NV, 0, 1>(v, x); break;
+    case 1: pairs4<MODE, NV, 0, 2>(v, x); break;
+    case 2: pairs4<MODE, NV, 0, 3>(v, x); break;
+    case 3: pairs4<MODE, NV, 1, 2>(v, x); break;
+    case 4: pairs4<MODE, NV, 1, 3>(v, x); break;
+    default: pairs4<MODE, NV, 2, 3>(v, x); break;
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void relayout(double2 (&v)[NV][kRegs], double2 *xbuf, uint32_t tl_from,
+                                         const DevPhase &from, uint32_t tl_to,
+                                         const DevPhase &to, uint32_t valid)
+{
+#pragma unroll
+    for (int w = 0; w < NV; ++w) {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j)
+            if ((valid >> j) & 1u)
+                xbuf[slot(tl_from | from.roff[j])] = v[w][j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j)
+            if ((valid >> j) & 1u)
+                v[w][j] = xbuf[slot(tl_to | to.roff[j])];
+        __syncthreads();
+    }
 }
 
 __device__ void block_reduce_rows(double *red, int n_red, double *partial, int red_base,
@@ -204,234 +214,195 @@ __device__ void block_reduce_rows(double *red, int n_red, double *partial, int r
     }
 }
 
-__global__ void __launch_bounds__(256)
-k_reverse(DevPass P, const DevOp *__restrict__ ops, const DevVBond *__restrict__ vb,
-          const double *__restrict__ theta, const DevModel *__restrict__ M,
-          double2 *__restrict__ psi, double2 *__restrict__ lam, double *__restrict__ partial,
-          int stride)
+// One pass of MODE over every tile.
+//   M_FWD: v0 = psi; apply the pass's gates.
+//   M_REV: v0 = psi, v1 = lambda; ops are listed in un-application order;
+//          for each op accumulate Im <lambda|G|psi> into its reduction row
+//          (the generator commutes with its own gate, so evaluating before the
+//          un-application is exact), then un-apply it to both vectors.
+//   M_HAM: v0 = psi (read), v1 = phi: phi <- D psi + terms (first pass) or
+//          phi += terms; the last pass also reduces Re <psi|phi> (energy).
+//   M_EXP: v0 = psi (read only): reduce <psi|term|psi> for the pass's terms.
+template <int MODE, bool GEN>
+__global__ void __launch_bounds__(512)
+k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__ ops,
+       const DevVBond *__restrict__ vb, const double *__restrict__ theta,
+       const DevModel *__restrict__ M, double2 *__restrict__ v0, double2 *__restrict__ v1,
+       double *__restrict__ partial, int stride)
 {
+    constexpr int NV = (MODE == M_FWD || MODE == M_EXP) ? 1 : 2;
     extern __shared__ __align__(16) char smem[];
     const int T = blockDim.x, tid = threadIdx.x;
-    const SmemPlan sp = smem_plan(P.k, P.c, 2, P.n_ops, P.n_diag, P.n_red, T);
-    double2 *tp = (double2 *)(smem + sp.tiles);
-    double2 *tq = tp + (1u << P.k);
-    const uint32_t *offs = (const uint32_t *)(smem + sp.offs);
-    const double2 *opc = (const double2 *)(smem + sp.opc);
-    const double2 *dtab = (const double2 *)(smem + sp.dtab);
-    double *red = (double *)(smem + sp.red);
-    pass_setup(P, ops, theta, M, -1.0, smem, sp);
-    for (int r = 0; r < P.n_red; ++r)
-        red[r * T + tid] = 0.0;
-    __syncthreads();
-
-    const int k = P.k, c = P.c;
-    const uint32_t cmask = (1u << c) - 1u;
-    const uint32_t tsize = 1u << k;
-    const uint64_t ntiles = (uint64_t)1 << P.nfree;
-    for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
-        const uint32_t base = tile_base(tl, P);
-        for (uint32_t l = tid; l < tsize; l += T) {
-            uint64_t g = base | offs[l >> c] | (l & cmask);
-            tp[l] = psi[g];
-            tq[l] = lam[g];
-        }
-        __syncthreads();
-        // the reverse plan stores each pass's ops in un-application order
-        for (int o = 0; o < P.n_ops; ++o) {
-            const DevOp op = ops[P.op_begin + o];
-            double acc = 0.0;
-            if (op.kind == OP_DIAG) {
-                for (uint32_t l = tid; l < tsize; l += T) {
-                    uint32_t g = base | offs[l >> c] | (l & cmask);
-                    double2 a = tp[l], b = tq[l];
-                    acc += diag_value(op, g, M, vb) * im_conj_mul(b, a);
-                    double2 ph = diag_phase(op, g, M, vb, theta, -1.0, dtab);
-                    tp[l] = cmul(a, ph);
-                    tq[l] = cmul(b, ph);
-                }
-            } else {
-                const double cs = opc[o].x, sn = opc[o].y;
-                const uint32_t par0 = __popc((uint32_t)tl & op.bm_free) & 1u;
-                const int lo = min(op.pl, op.ql), hi = max(op.pl, op.ql);
-                const uint32_t flip = (1u << op.pl) | (1u << op.ql);
-                for (uint32_t j = tid; j < (tsize >> 2); j += T) {
-                    uint32_t x = insert_zero(insert_zero(j, lo), hi) | (1u << op.pl);
-                    uint32_t y = x ^ flip;
-                    uint32_t par = (__popc(x & op.bm_local) + par0) & 1u;
-                    double ss = par ? -sn : sn;
-                    double sg = par ? -1.0 : 1.0;
-                    double2 a = tp[x], b = tp[y];
-                    double2 la = tq[x], lb = tq[y];
-                    acc += sg * (im_conj_mul(la, b) + im_conj_mul(lb, a));
-                    tp[x] = make_double2(cs * a.x - ss * b.y, cs * a.y + ss * b.x);
-                    tp[y] = make_double2(cs * b.x - ss * a.y, cs * b.y + ss * a.x);
-                    tq[x] = make_double2(cs * la.x - ss * lb.y, cs * la.y + ss * lb.x);
-                    tq[y] = make_double2(cs * lb.x - ss * la.y, cs * lb.y + ss * la.x);
-                }
-                acc *= -op.t;
-            }
-            if (op.red >= 0)
-                red[op.red * T + tid] += acc;
-            __syncthreads();
-        }
-        for (uint32_t l = tid; l < tsize; l += T) {
-            uint64_t g = base | offs[l >> c] | (l & cmask);
-            psi[g] = tp[l];
-            lam[g] = tq[l];
-        }
-        __syncthreads();
-    }
-    block_reduce_rows(red, P.n_red, partial, P.red_base, stride);
-}
-
-// ---------------------------------------------------------------- H passes --
-// phi <- D psi + sum of the pass's terms (first pass), phi += terms (others);
-// the last pass also reduces Re <psi|phi> into its row 0.
-
-__global__ void __launch_bounds__(256)
-k_hamiltonian(DevPass P, const DevOp *__restrict__ ops, const DevVBond *__restrict__ vb,
-              const DevModel *__restrict__ M, const double2 *__restrict__ psi,
-              double2 *__restrict__ phi, double *__restrict__ partial, int stride)
-{
-    extern __shared__ __align__(16) char smem[];
-    const int T = blockDim.x, tid = threadIdx.x;
-    const SmemPlan sp = smem_plan(P.k, P.c, 2, P.n_ops, P.n_diag, P.n_red, T);
-    double2 *tp = (double2 *)(smem + sp.tiles);
-    double2 *tf = tp + (1u << P.k);
-    double *red = (double *)(smem + sp.red);
+    const bool ham_first = (MODE == M_HAM) && (P.flags & PF_HAM_FIRST);
+    const bool ham_last = (MODE == M_HAM) && (P.flags & PF_HAM_LAST);
+    const int n_red = (MODE == M_REV) ? P.n_red : (MODE == M_EXP) ? 1 : P.n_red;
+    const SmemPlan sp = smem_plan(P.k, P.c, P.n_ops, P.n_diag, n_red, T);
+    double2 *xbuf = (double2 *)(smem + sp.xbuf);
     uint32_t *offs = (uint32_t *)(smem + sp.offs);
+    double2 *opc = (double2 *)(smem + sp.opc);
+    double2 *dtab = (double2 *)(smem + sp.dtab);
+    double *red = (double *)(smem + sp.red);
+
+    // ---- per-workgroup set-up
+    const double sign = (MODE == M_REV) ? -1.0 : 1.0;
     {
         const int nhi = P.k - P.c;
-        for (int i = tid; i < (1 << nhi); i += T) {
-            uint32_t o = 0;
-            for (int j = 0; j < nhi; ++j)
-                if ((i >> j) & 1)
-                    o |= 1u << P.tile_pos[P.c + j];
-            offs[i] = o;
-        }
-    }
-    double eacc = 0.0;
-    __syncthreads();
-    const int k = P.k, c = P.c;
-    const uint32_t cmask = (1u << c) - 1u;
-    const uint32_t tsize = 1u << k;
-    const uint64_t ntiles = (uint64_t)1 << P.nfree;
-    const bool first = (P.flags & PF_HAM_FIRST) != 0;
-    const bool last = (P.flags & PF_HAM_LAST) != 0;
-    for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
-        const uint32_t base = tile_base(tl, P);
-        for (uint32_t l = tid; l < tsize; l += T) {
-            uint64_t g = base | offs[l >> c] | (l & cmask);
-            tp[l] = psi[g];
-            tf[l] = first ? make_double2(0.0, 0.0) : phi[g];
-        }
-        __syncthreads();
-        for (int o = 0; o < P.n_ops; ++o) {
-            const DevOp op = ops[P.op_begin + o];
-            if (op.kind == OP_DIAG) {
-                for (uint32_t l = tid; l < tsize; l += T) {
-                    uint32_t g = base | offs[l >> c] | (l & cmask);
-                    double d = diag_value(op, g, M, vb);
-                    tf[l].x += d * tp[l].x;
-                    tf[l].y += d * tp[l].y;
-                }
-            } else {
-                const uint32_t par0 = __popc((uint32_t)tl & op.bm_free) & 1u;
-                const int lo = min(op.pl, op.ql), hi = max(op.pl, op.ql);
-                const uint32_t flip = (1u << op.pl) | (1u << op.ql);
-                for (uint32_t j = tid; j < (tsize >> 2); j += T) {
-                    uint32_t x = insert_zero(insert_zero(j, lo), hi) | (1u << op.pl);
-                    uint32_t y = x ^ flip;
-                    uint32_t par = (__popc(x & op.bm_local) + par0) & 1u;
-                    double w = par ? op.t : -op.t;   // (-t) * s
-                    tf[x].x += w * tp[y].x;
-                    tf[x].y += w * tp[y].y;
-                    tf[y].x += w * tp[x].x;
-                    tf[y].y += w * tp[x].y;
+        for (int i = tid; i < (1 << nhi); i += T)
+            offs[i] = pdep32((uint32_t)i, P.hi_mask);
+        if constexpr (MODE == M_FWD || MODE == M_REV) {
+            for (int o = tid; o < P.n_ops; o += T) {
+                const DevOp op = ops[P.op_begin + o];
+                if (op.kind == OP_HOP) {
+                    double s, c;
+                    sincos(theta[op.param] * op.t, &s, &c);
+                    opc[o] = make_double2(c, sign * s);
                 }
             }
-            __syncthreads();
+            if constexpr (!GEN) {
+                for (int o = 0; o < P.n_ops; ++o) {
+                    const DevOp op = ops[P.op_begin + o];
+                    if (op.kind != OP_DIAG)
+                        continue;
+                    for (int m = tid; m < kDiagTab; m += T) {
+                        double s, c;
+                        sincos(theta[op.param] * (M->U * (double)m), &s, &c);
+                        dtab[op.dtab * kDiagTab + m] = make_double2(c, -sign * s);
+                    }
+                }
+            }
         }
-        for (uint32_t l = tid; l < tsize; l += T) {
-            uint64_t g = base | offs[l >> c] | (l & cmask);
-            double2 f = tf[l];
-            if (last)
-                eacc += tp[l].x * f.x + tp[l].y * f.y;
-            phi[g] = f;
-        }
-        __syncthreads();
+        for (int r = 0; r < n_red; ++r)
+            red[r * T + tid] = 0.0;
     }
-    if (P.n_red > 0) {
+    __syncthreads();
+
+    const uint32_t cmask = (1u << P.c) - 1u;
+    const uint64_t ntiles = (uint64_t)1 << P.nfree;
+    const DevPhase *ph = phases + P.phase_begin;
+    const uint32_t valid = ph[0].valid;
+    double eacc = 0.0;
+    double2 v[NV][kRegs];
+
+    for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+        const uint32_t base = pdep32((uint32_t)tl, P.free_mask);
+        uint32_t tloc = thread_local_index(ph[0].tmask, tid);
+        uint32_t gthr = base | offs[tloc >> P.c] | (tloc & cmask);
+        // ---- load in the first phase's layout
+        // (registers of a tile smaller than 16 amplitudes that hold nothing
+        // are zero, so they add nothing to any reduction)
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            v[0][j] = make_double2(0.0, 0.0);
+            if constexpr (NV == 2)
+                v[NV - 1][j] = make_double2(0.0, 0.0);
+            if ((valid >> j) & 1u) {
+                const uint64_t g = gthr | ph[0].goff[j];
+                v[0][j] = v0[g];
+                if constexpr (NV == 2)
+                    if (!ham_first)
+                        v[NV - 1][j] = v1[g];
+            }
+        }
+        for (int q = 0; q < P.n_phases; ++q) {
+            if (q > 0) {
+                const uint32_t tnew = thread_local_index(ph[q].tmask, tid);
+                relayout<NV>(v, xbuf, tloc, ph[q - 1], tnew, ph[q], valid);
+                tloc = tnew;
+                gthr = base | offs[tloc >> P.c] | (tloc & cmask);
+            }
+            for (int o = ph[q].op_begin; o < ph[q].op_end; ++o) {
+                const DevOp op = ops[P.op_begin + o];
+                if (op.kind == OP_DIAG) {
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) {
+                        if (!((valid >> j) & 1u))
+                            continue;
+                        const uint32_t g = gthr | ph[q].goff[j];
+                        if constexpr (MODE == M_FWD || MODE == M_REV) {
+                            double2 phs;
+                            if constexpr (!GEN) {
+                                uint32_t up = g & op.umask;
+                                uint32_t dn = (uint32_t)((uint64_t)g >> M->ns) & op.umask;
+                                phs = dtab[op.dtab * kDiagTab + __popc(up & dn)];
+                            } else {
+                                double s, c;
+                                sincos(theta[op.param] * diag_value<GEN>(op, g, M, vb), &s, &c);
+                                phs = make_double2(c, -sign * s);
+                            }
+                            if constexpr (MODE == M_REV) {
+                                double d = diag_value<GEN>(op, g, M, vb);
+                                red[op.red * T + tid] += d * im_conj_mul(v[NV - 1][j], v[0][j]);
+                                v[NV - 1][j] = cmul(v[NV - 1][j], phs);
+                            }
+                            v[0][j] = cmul(v[0][j], phs);
+                        } else if constexpr (MODE == M_HAM) {
+                            double d = diag_value<GEN>(op, g, M, vb);
+                            v[NV - 1][j].x += d * v[0][j].x;
+                            v[NV - 1][j].y += d * v[0][j].y;
+                        } else {
+                            double2 a = v[0][j];
+                            eacc += diag_value<GEN>(op, g, M, vb) * (a.x * a.x + a.y * a.y);
+                        }
+                    }
+                } else {
+                    PairCtx x;
+                    x.par0 = (__popc(tloc & op.bm_local) + __popc((uint32_t)tl & op.bm_free)) & 1u;
+                    x.bm = op.bm_local;
+                    x.roff = ph[q].roff;
+                    x.t = op.t;
+                    x.acc = 0.0;
+                    if constexpr (MODE == M_FWD || MODE == M_REV) {
+                        x.cs = opc[o].x;
+                        x.sn = opc[o].y;
+                    } else {
+                        x.cs = x.sn = 0.0;
+                    }
+                    hop_regs<MODE, NV>(op.pair, v, x);
+                    if constexpr (MODE == M_REV)
+                        red[op.red * T + tid] += -op.t * x.acc;
+                    if constexpr (MODE == M_EXP)
+                        eacc += -2.0 * op.t * x.acc;
+                }
+            }
+        }
+        // ---- store from the last phase's layout
+        const DevPhase &pl = ph[P.n_phases - 1];
+        if constexpr (MODE != M_EXP) {
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                if ((valid >> j) & 1u) {
+                    const uint64_t g = gthr | pl.goff[j];
+                    if constexpr (MODE == M_FWD || MODE == M_REV)
+                        v0[g] = v[0][j];
+                    if constexpr (NV == 2)
+                        v1[g] = v[NV - 1][j];
+                    if (MODE == M_HAM && ham_last)
+                        eacc += re_conj_mul(v[0][j], v[NV - 1][j]);
+                }
+            }
+        }
+    }
+    if (MODE == M_EXP || (MODE == M_HAM && n_red > 0)) {
+        __syncthreads();
         red[tid] = eacc;
-        block_reduce_rows(red, 1, partial, P.red_base, stride);
     }
+    block_reduce_rows(red, n_red, partial, P.red_base, stride);
 }
 
-// ------------------------------------------------------- expectation pass --
-// Read-only energy: sum over its terms of <psi|term|psi>, and D if present:
-//   DIAG: D(b) |psi_b|^2;  HOP: 2 (-t) s Re(conj(psi_x) psi_y) per pair.
-
-__global__ void __launch_bounds__(256)
-k_expect(DevPass P, const DevOp *__restrict__ ops, const DevVBond *__restrict__ vb,
-         const DevModel *__restrict__ M, const double2 *__restrict__ psi,
-         double *__restrict__ partial, int stride)
-{
-    extern __shared__ __align__(16) char smem[];
-    const int T = blockDim.x, tid = threadIdx.x;
-    const SmemPlan sp = smem_plan(P.k, P.c, 1, P.n_ops, P.n_diag, 1, T);
-    double2 *tp = (double2 *)(smem + sp.tiles);
-    double *red = (double *)(smem + sp.red);
-    uint32_t *offs = (uint32_t *)(smem + sp.offs);
-    {
-        const int nhi = P.k - P.c;
-        for (int i = tid; i < (1 << nhi); i += T) {
-            uint32_t o = 0;
-            for (int j = 0; j < nhi; ++j)
-                if ((i >> j) & 1)
-                    o |= 1u << P.tile_pos[P.c + j];
-            offs[i] = o;
-        }
-    }
-    double eacc = 0.0;
-    __syncthreads();
-    const int k = P.k, c = P.c;
-    const uint32_t cmask = (1u << c) - 1u;
-    const uint32_t tsize = 1u << k;
-    const uint64_t ntiles = (uint64_t)1 << P.nfree;
-    for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
-        const uint32_t base = tile_base(tl, P);
-        for (uint32_t l = tid; l < tsize; l += T)
-            tp[l] = psi[(uint64_t)(base | offs[l >> c] | (l & cmask))];
-        __syncthreads();
-        for (int o = 0; o < P.n_ops; ++o) {
-            const DevOp op = ops[P.op_begin + o];
-            if (op.kind == OP_DIAG) {
-                for (uint32_t l = tid; l < tsize; l += T) {
-                    uint32_t g = base | offs[l >> c] | (l & cmask);
-                    double2 a = tp[l];
-                    eacc += diag_value(op, g, M, vb) * (a.x * a.x + a.y * a.y);
-                }
-            } else {
-                const uint32_t par0 = __popc((uint32_t)tl & op.bm_free) & 1u;
-                const int lo = min(op.pl, op.ql), hi = max(op.pl, op.ql);
-                const uint32_t flip = (1u << op.pl) | (1u << op.ql);
-                double acc = 0.0;
-                for (uint32_t j = tid; j < (tsize >> 2); j += T) {
-                    uint32_t x = insert_zero(insert_zero(j, lo), hi) | (1u << op.pl);
-                    uint32_t y = x ^ flip;
-                    uint32_t par = (__popc(x & op.bm_local) + par0) & 1u;
-                    double2 a = tp[x], b = tp[y];
-                    double re = a.x * b.x + a.y * b.y;
-                    acc += par ? -re : re;
-                }
-                eacc += -2.0 * op.t * acc;
-            }
-        }
-        __syncthreads();
-    }
-    red[tid] = eacc;
-    block_reduce_rows(red, 1, partial, P.red_base, stride);
-}
+#define HV_INSTANTIATE(MODE, GEN)                                                          \
+    template __global__ void k_pass<MODE, GEN>(DevPass, const DevPhase *, const DevOp *,   \
+                                               const DevVBond *, const double *,           \
+                                               const DevModel *, double2 *, double2 *,     \
+                                               double *, int);
+HV_INSTANTIATE(M_FWD, false)
+HV_INSTANTIATE(M_REV, false)
+HV_INSTANTIATE(M_HAM, false)
+HV_INSTANTIATE(M_EXP, false)
+HV_INSTANTIATE(M_FWD, true)
+HV_INSTANTIATE(M_REV, true)
+HV_INSTANTIATE(M_HAM, true)
+HV_INSTANTIATE(M_EXP, true)
+#undef HV_INSTANTIATE
 
 // ------------------------------------------------------------ misc kernels --
 

@@ -211,6 +211,7 @@ std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig 
         p.tile = finish_tile(0, n, n);
         p.ops = ops;
         merge_diagonals(p.ops);
+        plan_phases(p);
         passes.push_back(p);
         return passes;
     }
@@ -259,6 +260,7 @@ std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig 
             done[i] = 1;
         }
         merge_diagonals(p.ops);
+        plan_phases(p);
         passes.push_back(p);
         while (first < ops.size() && done[first])
             ++first;
@@ -354,10 +356,141 @@ std::vector<HostPass> plan_hamiltonian(const Model &m, const TileConfig &tc)
             }
         p.flags = first ? PF_HAM_FIRST : 0;
         first = false;
+        plan_phases(p);
         passes.push_back(p);
     }
     passes.back().flags |= PF_HAM_LAST;
     return passes;
+}
+
+void plan_phases(HostPass &p)
+{
+    const int k = (int)p.tile.size();
+    const int rbits = std::min(k, kRegBits);
+    int loc[kMaxQubits];
+    for (int b = 0; b < kMaxQubits; ++b)
+        loc[b] = -1;
+    for (int j = 0; j < k; ++j)
+        loc[p.tile[j]] = j;
+    // the same ops with tile-local qubit masks (ordering only needs tile bits:
+    // every hopping term of the pass lies in the tile)
+    std::vector<HostOp> lops = p.ops;
+    for (HostOp &o : lops) {
+        uint32_t m = 0;
+        for (int b = 0; b < kMaxQubits; ++b)
+            if ((o.qmask >> b) & 1u)
+                if (loc[b] >= 0)
+                    m |= 1u << loc[b];
+        o.qmask = m;
+    }
+    // low local bits that the load/store layout keeps on lanes 0..15
+    uint32_t io_forbid = 0;
+    for (int b = 0; b < std::min(4, k - kRegBits); ++b)
+        io_forbid |= 1u << b;
+    auto pad = [&](uint32_t S) {
+        std::vector<int> regs;
+        for (int b = 0; b < k; ++b)
+            if ((S >> b) & 1u)
+                regs.push_back(b);
+        for (int b = k - 1; b >= 0 && (int)regs.size() < rbits; --b)
+            if (!((S >> b) & 1u) && !((io_forbid >> b) & 1u))
+                regs.push_back(b), S |= 1u << b;
+        for (int b = k - 1; b >= 0 && (int)regs.size() < rbits; --b)
+            if (!((S >> b) & 1u))
+                regs.push_back(b), S |= 1u << b;
+        std::sort(regs.begin(), regs.end());
+        return regs;
+    };
+    auto io_regs = [&]() {
+        std::vector<int> regs;
+        for (int b = k - rbits; b < k; ++b)
+            regs.push_back(b);
+        return regs;
+    };
+    auto io_ok = [&](const std::vector<int> &regs) {
+        for (int b : regs)
+            if ((io_forbid >> b) & 1u)
+                return false;
+        return true;
+    };
+
+    std::vector<HostPhase> phases;
+    std::vector<HostOp> ordered;
+    std::vector<char> done(lops.size(), 0);
+    size_t left = lops.size();
+    while (left > 0) {
+        std::vector<int> active;
+        for (size_t i = 0; i < lops.size(); ++i)
+            if (!done[i])
+                active.push_back((int)i);
+        std::vector<uint32_t> seeds{0u};
+        {
+            uint32_t bg = 0, bd = 0;
+            for (int i : active) {
+                const HostOp &o = lops[i];
+                if (o.kind == OP_DIAG) {
+                    if (o.qmask & bg)
+                        bd |= o.qmask;
+                    continue;
+                }
+                if (!((o.qmask & bg) || (o.qmask & bd)))
+                    seeds.push_back(o.qmask);
+                bg |= o.qmask;
+            }
+        }
+        Closure best;
+        best.hops = -1;
+        for (uint32_t sd : seeds) {
+            Closure cl = grow(lops, active, done, sd, rbits);
+            if (cl.inc.empty())
+                continue;
+            if (cl.hops > best.hops || (cl.hops == best.hops && cl.inc.size() > best.inc.size()))
+                best = cl;
+        }
+        HostPhase ph;
+        ph.regs = pad(best.S);
+        ph.op_begin = (int)ordered.size();
+        for (int i : best.inc) {
+            ordered.push_back(p.ops[i]);
+            done[i] = 1;
+            --left;
+        }
+        ph.op_end = (int)ordered.size();
+        // a phase whose register set equals the previous one's extends it
+        if (!phases.empty() && phases.back().regs == ph.regs)
+            phases.back().op_end = ph.op_end;
+        else
+            phases.push_back(ph);
+    }
+    if (phases.empty() || !io_ok(phases.front().regs)) {
+        HostPhase io;
+        io.regs = io_regs();
+        phases.insert(phases.begin(), io);
+    }
+    if (!io_ok(phases.back().regs)) {
+        HostPhase io;
+        io.regs = io_regs();
+        io.op_begin = io.op_end = (int)ordered.size();
+        phases.push_back(io);
+    }
+    p.ops.swap(ordered);
+    p.phases.swap(phases);
+}
+
+std::vector<HostPass> reversed_passes(std::vector<HostPass> ps)
+{
+    std::reverse(ps.begin(), ps.end());
+    for (HostPass &p : ps) {
+        const int n = (int)p.ops.size();
+        std::reverse(p.ops.begin(), p.ops.end());
+        std::reverse(p.phases.begin(), p.phases.end());
+        for (HostPhase &ph : p.phases) {
+            int b = n - ph.op_end, e = n - ph.op_begin;
+            ph.op_begin = b;
+            ph.op_end = e;
+        }
+    }
+    return ps;
 }
 
 }  // namespace hv
