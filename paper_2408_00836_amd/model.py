@@ -69,6 +69,8 @@ class Hubbard:
         larger buffer of this model is reused (psi sits at its start)."""
         nbytes = abi.hubbard_workspace_size(self.handle, layers, op)
         dev = torch.device(device or "cuda")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
         for key, ws in self._ws.items():
             if ws.numel() >= nbytes and ws.device == dev and (key[1] == op or
                                                               op == abi.HUBBARD_OP_ENERGY):

@@ -1,0 +1,182 @@
+"""Parity at the full 32-qubit size (4x4 periodic, U=8, 16 layers, 80 params),
+in the launch configuration bench.py times.
+
+A dense oracle run at 32 qubits needs three 64 GiB vectors and hours of CPU,
+so the full-size checks use exact special cases that the oracle side computes
+independently of any 32-qubit state vector, plus properties that hold at any
+size:
+  * free-fermion case (diagonal angles zero after layer 0): sampled amplitudes
+    from Slater determinants, E from Wick's theorem, every hopping gradient
+    exactly (oracle.freefermion, 16 x 16 matrices);
+  * row-factorised case (all vertical angles zero): the state is a product of
+    four 4-site ring states, each from the 8-qubit oracle; E and the U/h
+    gradients are sums over rows;
+  * at the benchmark's own theta: E(th) = E(-th), grad odd, norm 1, adjoint vs
+    central finite differences of the GPU energy.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import core as oc
+from oracle import freefermion as ff
+from oracle.model import make_model
+from paper_2408_00836_amd import abi, workloads as W
+from paper_2408_00836_amd.model import Hubbard
+
+pytestmark = pytest.mark.gpu
+
+AMP_TOL = 1e-10
+GRAD_TOL = 1e-8
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def c5(gpu):
+    w = W.config5()
+    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    om = make_model(w.nx, w.ny, **w.kwargs())
+    yield w, m, om
+    del m
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def state_in_workspace(m, th):
+    """psi(theta) prepared in the energy_grad workspace's psi buffer."""
+    L = th.numel() // m.params_per_layer
+    psi, _ = m.workspace_views(L)
+    abi.hubbard_init_neel(m.handle, psi.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    m.ansatz(th, psi)
+    torch.cuda.synchronize()
+    return psi
+
+
+def sector_samples(rng, n):
+    """Random basis indices with 8 up and 8 down electrons (spin-blocked)."""
+    out = []
+    for _ in range(n):
+        up = rng.choice(16, 8, replace=False)
+        dn = rng.choice(16, 8, replace=False)
+        out.append(int(sum(1 << int(s) for s in up) + sum(1 << (16 + int(s)) for s in dn)))
+    return out
+
+
+def test_free_fermion_32q(c5):
+    w, m, om = c5
+    th = w.theta.copy()
+    per = w.params_per_layer
+    for l in range(1, w.layers):
+        th[l * per] = 0.0
+    tdev = torch.tensor(th, dtype=torch.float64, device="cuda")
+    say("[32q] free-fermion case: energy_grad")
+    E, g = m.energy_grad(tdev)
+    E, g = E.item(), g.cpu().numpy()
+    E_ref = ff.energy(om, th, w.layers)
+    assert abs(E - E_ref) <= 1e-12 * max(1, abs(E_ref)), (E, E_ref)
+    for k, v in ff.hop_gradients(om, th, w.layers).items():
+        assert abs(g[k] - v) <= GRAD_TOL, (k, g[k], v)
+    assert abs(g[0]) < 1e-12   # first diagonal angle is a global phase
+    say("[32q] free-fermion case: amplitudes")
+    psi = state_in_workspace(m, tdev)
+    C = ff.orbitals(om, th, w.layers)
+    ph = ff.start_phase(om, th, w.layers)
+    rng = np.random.default_rng(5)
+    idx = sector_samples(rng, 300) + [om.neel_index()]
+    got = psi[torch.tensor(idx, device="cuda")].cpu().numpy()
+    want = np.array([ff.amplitude(om, C, b, ph) for b in idx])
+    assert np.max(np.abs(got - want)) <= AMP_TOL
+    assert np.max(np.abs(want)) > 1e-4   # the samples are not all trivial
+    # outside the (8, 8) sector every amplitude is exactly zero
+    out = [int(b) for b in rng.integers(0, 1 << 32, 300, dtype=np.uint64)]
+    out = [b for b in out if bin(b & 0xFFFF).count("1") != 8 or bin(b >> 16).count("1") != 8]
+    vals = psi[torch.tensor(out, device="cuda")].cpu().numpy()
+    assert np.all(vals == 0.0)
+
+
+def ring_models(om):
+    ring = make_model(1, 4, periodic_y=True, U=om.U)
+    b0s = []
+    for r in range(4):
+        b0 = 0
+        for y in range(4):
+            b0 |= 1 << ring.qubit(y, (r + y) % 2)
+        b0s.append(b0)
+    return ring, b0s
+
+
+def test_row_factorised_32q(c5):
+    w, m, om = c5
+    th = w.theta.copy()
+    per = w.params_per_layer
+    th[2::per] = 0.0   # v1
+    th[4::per] = 0.0   # v2
+    tdev = torch.tensor(th, dtype=torch.float64, device="cuda")
+    ring, b0s = ring_models(om)
+    thr = np.stack([th[0::per], th[1::per], th[3::per]], axis=1).ravel()
+    Es, gs, states = 0.0, np.zeros_like(th), []
+    for r in range(4):
+        Er, gr = oc.energy_grad(ring, thr, w.layers, b0s[r])
+        Es += Er
+        gs[0::per] += gr[0::3]
+        gs[1::per] += gr[1::3]
+        gs[3::per] += gr[2::3]
+        states.append(oc.ansatz(ring, thr, w.layers, b0s[r]))
+    say("[32q] row-factorised case: energy_grad")
+    E, g = m.energy_grad(tdev)
+    E, g = E.item(), g.cpu().numpy()
+    assert abs(E - Es) <= 1e-12 * max(1, abs(Es)), (E, Es)
+    for k in range(len(th)):
+        if k % per in (0, 1, 3):
+            assert abs(g[k] - gs[k]) <= GRAD_TOL, (k, g[k], gs[k])
+    say("[32q] row-factorised case: amplitudes")
+    psi = state_in_workspace(m, tdev)
+    rng = np.random.default_rng(6)
+    # in-sector samples with each row holding one ring sector (2 up, 2 down)
+    idx = []
+    for _ in range(300):
+        b = 0
+        for r in range(4):
+            nz = np.nonzero(np.abs(states[r]) > 1e-6)[0]
+            s = int(rng.choice(nz))
+            b |= (s & 0xF) << (4 * r)
+            b |= ((s >> 4) & 0xF) << (16 + 4 * r)
+        idx.append(b)
+    got = psi[torch.tensor(idx, device="cuda")].cpu().numpy()
+    want = []
+    for b in idx:
+        a = 1.0 + 0j
+        for r in range(4):
+            a *= states[r][((b >> (4 * r)) & 0xF) | (((b >> (16 + 4 * r)) & 0xF) << 4)]
+        want.append(a)
+    assert np.max(np.abs(got - np.array(want))) <= AMP_TOL
+
+
+def test_symmetry_norm_and_fd_32q(c5):
+    w, m, om = c5
+    tdev = torch.tensor(w.theta, dtype=torch.float64, device="cuda")
+    say("[32q] bench theta: energy_grad(+theta), energy_grad(-theta)")
+    E1, g1 = m.energy_grad(tdev)
+    E1, g1 = E1.item(), g1.cpu().numpy()
+    E2, g2 = m.energy_grad(-tdev)
+    E2, g2 = E2.item(), g2.cpu().numpy()
+    assert abs(E1 - E2) <= 1e-12 * max(1, abs(E1))
+    assert np.max(np.abs(g1 + g2)) <= GRAD_TOL
+    assert abs(g1[0]) < 1e-12
+    say("[32q] norm of psi(theta)")
+    psi = state_in_workspace(m, tdev)
+    nrm = sum(torch.vdot(c, c).real.item() for c in psi.split(1 << 28))
+    assert abs(nrm - 1.0) < 1e-12
+    say("[32q] central finite differences for two parameters")
+    h = 1e-5
+    for k in (1, 77):
+        tp, tm = tdev.clone(), tdev.clone()
+        tp[k] += h
+        tm[k] -= h
+        fd = (m.energy(tp).item() - m.energy(tm).item()) / (2 * h)
+        assert abs(fd - g1[k]) < GRAD_TOL, (k, fd, g1[k])
