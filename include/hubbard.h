@@ -35,10 +35,13 @@
  *     Device calls are asynchronous on that stream; the status they return
  *     reports argument and launch errors only, and a kernel fault surfaces at
  *     the caller's next synchronisation.
- *   - No call allocates device memory except hubbard_create's lazily
- *     uploaded tables (a few KiB per handle and device, freed by
- *     hubbard_destroy).  Vectors and scratch are caller-owned: the caller
- *     asks hubbard_workspace_size for the byte count and passes a buffer.
+ *   - Vectors and scratch are caller-owned: the caller asks
+ *     hubbard_workspace_size (or hubbard_batch_workspace_size) for the byte
+ *     count and passes a buffer.  The only device memory the library
+ *     allocates itself is small read-only tables (model constants and pass
+ *     plans, KiB per handle, layer count and device; batch tables per
+ *     distinct batch), uploaded on first use and kept until
+ *     hubbard_destroy (batch tables: until the process ends).
  *   - Every call returns a hubbard_status; on failure hubbard_last_error()
  *     returns a message (thread-local, valid until the next call on the same
  *     thread).  No C++ exception crosses this boundary.
@@ -154,6 +157,30 @@ hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers,
 hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,
                            double *E_dev, double *grad_dev, void *ws_dev,
                            size_t ws_bytes, void *stream);
+
+/* Batched energy and gradient of many independent instances (different
+ * lattices, sizes, U, disorder, V and layer counts; each its own parameters)
+ * in one persistent launch: every workgroup claims whole instances, largest
+ * first, and runs the instance's circuit, H|psi> and adjoint sweep itself.
+ *   hs[i]           instance handles (n >= 1)
+ *   theta_dev       all parameters, instance i's n_layers[i]*params_per_layer
+ *                   values starting at theta_dev + theta_off[i] (device)
+ *   theta_off, n_layers  host arrays of n entries
+ *   E_dev[i]        energy of instance i (device, n doubles)
+ *   grad_dev        gradient of instance i at grad_dev + theta_off[i] (device)
+ *   ws_dev          hubbard_batch_workspace_size bytes (device): a work counter
+ *                   and each instance's psi and lambda
+ * The first call with a given set of pointers and sizes plans the batch and
+ * uploads its tables (it must not be under graph capture); later calls only
+ * launch two kernels (a counter reset and the batch kernel) and may be
+ * captured into a graph and replayed with new theta values in place.
+ * Errors: HUBBARD_ERR_ARG, HUBBARD_ERR_SIZE (workspace), HUBBARD_ERR_STATE
+ * (first call under capture), HUBBARD_ERR_DEVICE. */
+hubbard_status hubbard_batch_workspace_size(const hubbard_t *hs, int32_t n, size_t *bytes);
+hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *theta_dev,
+                                 const int64_t *theta_off, const int32_t *n_layers,
+                                 double *E_dev, double *grad_dev, void *ws_dev, size_t ws_bytes,
+                                 void *stream);
 
 #ifdef __cplusplus
 }

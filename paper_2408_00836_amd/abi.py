@@ -30,6 +30,7 @@ EXPORTED = [
     "hubbard_last_error", "hubbard_workspace_size", "hubbard_init_neel",
     "ansatz_apply", "hamiltonian_apply", "energy", "energy_grad",
     "hubbard_plan_dump", "hubbard_set_tiles", "hubbard_set_timing", "hubbard_phase_ms",
+    "hubbard_batch_workspace_size", "energy_grad_batch",
 ]
 
 
@@ -80,6 +81,9 @@ def lib() -> ctypes.CDLL:
             "hubbard_plan_dump": ([vp, i32, i32, P(i32), i64, P(i64)], st),
             "hubbard_set_tiles": ([vp, i32, i32, i32], st),
             "hubbard_set_timing": ([vp, i32], st),
+            "hubbard_batch_workspace_size": ([P(vp), i32, P(ctypes.c_size_t)], st),
+            "energy_grad_batch": ([P(vp), i32, vp, P(i64), P(i32), vp, vp, vp, ctypes.c_size_t,
+                                   vp], st),
             "hubbard_phase_ms": ([vp, P(ctypes.c_float), P(ctypes.c_float),
                                   P(ctypes.c_float)], st),
         }
@@ -214,3 +218,24 @@ def hubbard_phase_ms(h: int):
     a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
     _check(lib().hubbard_phase_ms(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+def _handles(hs):
+    arr = (ctypes.c_void_p * len(hs))(*hs)
+    return arr
+
+
+def hubbard_batch_workspace_size(hs) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().hubbard_batch_workspace_size(_handles(hs), len(hs), ctypes.byref(b)))
+    return b.value
+
+
+def energy_grad_batch(hs, theta_dev: int, theta_off, n_layers, E_dev: int, grad_dev: int,
+                      ws_dev: int, ws_bytes: int, stream: int = 0) -> None:
+    off = np.ascontiguousarray(theta_off, dtype=np.int64)
+    lay = np.ascontiguousarray(n_layers, dtype=np.int32)
+    _check(lib().energy_grad_batch(_handles(hs), len(hs), theta_dev,
+                                   off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   lay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   E_dev, grad_dev, ws_dev, int(ws_bytes), stream))

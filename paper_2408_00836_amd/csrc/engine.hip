@@ -21,6 +21,8 @@ template <int MODE, bool GEN>
 __global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,
                        const DevModel *, double2 *, double2 *, double *, int);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t);
+__global__ void k_batch(const DevInstance *, const DevPass *, int, unsigned int *);
+__global__ void k_fill_u32(unsigned int *, unsigned int, int);
 __global__ void k_reduce(const double *, int, const int32_t *, const int32_t *, const int32_t *,
                          const double *, double *, double *, int);
 }  // namespace hv
@@ -61,6 +63,7 @@ struct Program {
     DevPhase *d_phases = nullptr;
     DevVBond *d_vb = nullptr;
     int32_t *d_row_ptr = nullptr, *d_row_idx = nullptr, *d_row_nblk = nullptr;
+    int32_t *d_row_param = nullptr;
     double *d_scale = nullptr;
     int n_rows = 0, n_out = 0;
     size_t partial_bytes = 0;
@@ -74,6 +77,7 @@ struct Program {
         (void)hipFree(d_row_ptr);
         (void)hipFree(d_row_idx);
         (void)hipFree(d_row_nblk);
+        (void)hipFree(d_row_param);
         (void)hipFree(d_scale);
     }
 };
@@ -302,7 +306,9 @@ void set_smem(PassList &pl, bool force_red1)
     for (size_t i = 0; i < pl.pass.size(); ++i) {
         const DevPass &P = pl.pass[i];
         int nred = force_red1 ? 1 : P.n_red;
-        pl.smem[i] = (int)smem_plan(P.k, P.c, P.n_ops, P.n_diag, nred, pl.threads[i]).total;
+        pl.smem[i] = (int)smem_plan(P.k, P.c, P.n_ops, P.n_diag, nred, pl.threads[i],
+                                    P.nfree == 0)
+                         .total;
     }
 }
 
@@ -409,6 +415,11 @@ hubbard_status upload_program(hubbard_model *h, DeviceState &ds, Program &pr)
                nblk.size() * sizeof(int32_t));
     if (e == hipSuccess)
         e = up((void **)&pr.d_scale, scale.data(), scale.size() * sizeof(double));
+    if (e == hipSuccess) {
+        std::vector<int32_t> rp(b.row_param.begin(), b.row_param.end());
+        e = up((void **)&pr.d_row_param, rp.empty() ? nullptr : rp.data(),
+               rp.size() * sizeof(int32_t));
+    }
     if (e != hipSuccess)
         return fail(HUBBARD_ERR_DEVICE, std::string("uploading plan: ") + hipGetErrorString(e));
     (void)ds;
@@ -564,6 +575,147 @@ void mark(hubbard_model *h, int i, hipStream_t s)
 }
 
 }  // namespace
+
+// ================================================================ batch
+
+struct BatchProgram {
+    std::vector<std::unique_ptr<Program>> progs;
+    DevInstance *d_inst = nullptr;
+    DevPass *d_passes = nullptr;
+    int n = 0, grid = 1, threads = 64, smem = 0;
+    size_t ws_need = 0;
+    ~BatchProgram()
+    {
+        (void)hipFree(d_inst);
+        (void)hipFree(d_passes);
+    }
+};
+
+std::mutex g_batch_mu;
+std::map<std::string, std::unique_ptr<BatchProgram>> g_batches;
+
+size_t batch_ws_bytes(const hubbard_t *hs, int n)
+{
+    size_t need = 256;   // work counter
+    for (int i = 0; i < n; ++i)
+        need += 2 * align256(vec_bytes(hs[i]));
+    return need;
+}
+
+hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, const int64_t *toff,
+                           const int32_t *layers, double *E, double *grad, char *ws,
+                           BatchProgram &bp)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, "no current device");
+    const int lim = max_smem_per_block();
+    bp.n = n;
+    bp.ws_need = batch_ws_bytes(hs, n);
+    std::vector<DevInstance> insts(n);
+    std::vector<DevPass> allp;
+    std::vector<double> cost(n);
+    // per-instance vectors in the workspace, in argument order
+    std::vector<size_t> voff(n);
+    size_t at = 256;
+    for (int i = 0; i < n; ++i) {
+        voff[i] = at;
+        at += 2 * align256(vec_bytes(hs[i]));
+    }
+    int threads = 64;
+    for (int i = 0; i < n; ++i) {
+        hubbard_model *h = hs[i];
+        std::unique_ptr<Program> pr(new Program());
+        {
+            std::lock_guard<std::mutex> lk(h->mu);
+            DeviceState &ds = h->dev[dev];
+            hubbard_status st = ensure_model(h, dev, ds);
+            if (st != HUBBARD_OK)
+                return st;
+            try {
+                plan_program(h, PROG_GRAD, layers[i], lim, *pr);
+            } catch (const std::exception &ex) {
+                return fail(HUBBARD_ERR_NOMEM, std::string("planning: ") + ex.what());
+            }
+            st = upload_program(h, ds, *pr);
+            if (st != HUBBARD_OK)
+                return st;
+            DevInstance &I = insts[i];
+            std::memset(&I, 0, sizeof(I));
+            I.model = ds.d_model;
+        }
+        DevInstance &I = insts[i];
+        I.n_fwd = (int)pr->fwd.pass.size();
+        I.n_ham = (int)pr->ham.pass.size();
+        I.n_rev = (int)pr->rev.pass.size();
+        I.general = pr->general ? 1 : 0;
+        I.n_params = layers[i] * h->m.params_per_layer();
+        I.dim = (uint64_t)1 << h->m.nq;
+        I.neel = h->m.neel;
+        I.phases = pr->d_phases;
+        I.ops = pr->d_ops;
+        I.vb = pr->d_vb;
+        I.row_param = pr->d_row_param;
+        I.theta = theta + toff[i];
+        I.grad = grad + toff[i];
+        I.E = E + i;
+        I.psi = ws + voff[i];
+        I.lam = ws + voff[i] + align256(vec_bytes(h));
+        I.pass_begin = (int)allp.size();
+        int tb = 0;
+        for (const PassList *l : {&pr->fwd, &pr->ham, &pr->rev})
+            for (const DevPass &P : l->pass) {
+                allp.push_back(P);
+                tb = std::max(tb, P.tbits);
+            }
+        I.tbits = tb;
+        threads = std::max(threads, 1 << tb);
+        cost[i] = (double)I.dim * (I.n_fwd + I.n_ham + 2.0 * I.n_rev) + 1.0;
+        bp.progs.push_back(std::move(pr));
+    }
+    // LDS: the widest pass of any instance, with this launch's block size
+    int smem = 0;
+    for (const DevPass &P : allp) {
+        const int nred = P.n_red > 0 ? P.n_red : 1;
+        smem = std::max(smem, (int)smem_plan(P.k, P.c, P.n_ops, P.n_diag, nred, threads,
+                                             P.nfree == 0)
+                                  .total);
+    }
+    smem += 16;   // the batch kernel's work-claim word
+    if (smem > lim)
+        return fail(HUBBARD_ERR_ARG, "a batch instance needs more LDS than a workgroup may use");
+    bp.threads = threads;
+    bp.smem = smem;
+    // largest instances first: they are claimed first from the work counter
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<DevInstance> sorted(n);
+    for (int i = 0; i < n; ++i)
+        sorted[i] = insts[order[i]];
+    int cus = 0, per_cu = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim) != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, "setting the batch kernel's LDS limit");
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch, threads,
+                                                     smem) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    bp.grid = std::max(1, std::min(n, std::max(cus, 1) * per_cu));
+    hipError_t e = hipMalloc((void **)&bp.d_inst, std::max<size_t>(16, n * sizeof(DevInstance)));
+    if (e == hipSuccess)
+        e = hipMemcpy(bp.d_inst, sorted.data(), n * sizeof(DevInstance), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&bp.d_passes, std::max<size_t>(16, allp.size() * sizeof(DevPass)));
+    if (e == hipSuccess && !allp.empty())
+        e = hipMemcpy(bp.d_passes, allp.data(), allp.size() * sizeof(DevPass),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("uploading batch: ") + hipGetErrorString(e));
+    return HUBBARD_OK;
+}
 
 // ===================================================================== ABI
 
@@ -773,6 +925,64 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
         return st;
     mark(h, 3, s);
     return run_reduce(*pr, partial, E_dev, grad_dev, s);
+}
+
+hubbard_status hubbard_batch_workspace_size(const hubbard_t *hs, int32_t n, size_t *bytes)
+{
+    if (!hs || n < 1 || !bytes)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_batch_workspace_size");
+    for (int i = 0; i < n; ++i)
+        if (!hs[i])
+            return fail(HUBBARD_ERR_ARG, "NULL handle in batch");
+    *bytes = batch_ws_bytes(hs, n);
+    return HUBBARD_OK;
+}
+
+hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *theta_dev,
+                                 const int64_t *theta_off, const int32_t *n_layers,
+                                 double *E_dev, double *grad_dev, void *ws_dev, size_t ws_bytes,
+                                 void *stream)
+{
+    if (!hs || n < 1 || !theta_dev || !theta_off || !n_layers || !E_dev || !grad_dev || !ws_dev)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to energy_grad_batch");
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i] || n_layers[i] < 0 || theta_off[i] < 0)
+            return fail(HUBBARD_ERR_ARG, "bad instance " + std::to_string(i) + " in batch");
+    }
+    if (ws_bytes < batch_ws_bytes(hs, n))
+        return fail(HUBBARD_ERR_SIZE, "workspace too small for energy_grad_batch");
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::string key = std::to_string(dev) + ":" + std::to_string((uintptr_t)theta_dev) + ":" +
+                      std::to_string((uintptr_t)E_dev) + ":" + std::to_string((uintptr_t)grad_dev) +
+                      ":" + std::to_string((uintptr_t)ws_dev);
+    for (int i = 0; i < n; ++i)
+        key += ":" + std::to_string((uintptr_t)hs[i]) + "/" + std::to_string(n_layers[i]) + "/" +
+               std::to_string(theta_off[i]);
+    hipStream_t s = (hipStream_t)stream;
+    BatchProgram *bp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        auto it = g_batches.find(key);
+        if (it == g_batches.end()) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+                return fail(HUBBARD_ERR_STATE, "first call of a batch must happen outside graph "
+                                               "capture (it uploads the batch tables)");
+            std::unique_ptr<BatchProgram> nb(new BatchProgram());
+            hubbard_status st = build_batch(hs, n, theta_dev, theta_off, n_layers, E_dev,
+                                            grad_dev, (char *)ws_dev, *nb);
+            if (st != HUBBARD_OK)
+                return st;
+            it = g_batches.emplace(key, std::move(nb)).first;
+        }
+        bp = it->second.get();
+    }
+    unsigned int *counter = (unsigned int *)ws_dev;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 0u, 1);
+    hipLaunchKernelGGL(k_batch, dim3(bp->grid), dim3(bp->threads), bp->smem, s, bp->d_inst,
+                       bp->d_passes, bp->n, counter);
+    return check_launch("batch");
 }
 
 // ------------------------------------------------------- introspection --

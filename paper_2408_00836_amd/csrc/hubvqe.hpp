@@ -95,6 +95,25 @@ struct DevPass {
     int32_t pad2[2];
 };
 
+// One instance of a batched energy+gradient launch: its passes (forward, H,
+// reverse) live at pass_begin in the batch's pass array; every pointer is a
+// device pointer.  row_param maps the instance's reduction rows to outputs
+// (-1: the energy, p >= 0: gradient entry p).
+struct DevInstance {
+    int32_t n_fwd, n_ham, n_rev, general;
+    int32_t pass_begin, n_params;
+    int32_t tbits, pad;
+    uint64_t dim, neel;
+    const struct DevPhase *phases;
+    const struct DevOp *ops;
+    const struct DevVBond *vb;
+    const struct DevModel *model;
+    const int32_t *row_param;
+    const double *theta;
+    void *psi, *lam;
+    double *E, *grad;
+};
+
 // Model constants in device memory.
 struct DevModel {
     int32_t n, ns;
@@ -106,13 +125,15 @@ struct DevModel {
 
 // LDS carve-up shared by host (launch size) and device: one tile-sized
 // exchange buffer, the tile's global-offset table, per-op rotation
-// coefficients, diagonal phase tables and per-thread reduction rows.
+// coefficients, diagonal phase tables and reduction rows.
 struct SmemPlan {
     uint32_t xbuf, offs, opc, dtab, red, total;
 };
 
+// Reduction rows: a pass over many tiles keeps one accumulator per thread
+// and row; a single-tile pass reduces every op at once into one value per row.
 __host__ __device__ inline SmemPlan smem_plan(int k, int c, int n_ops, int n_diag, int n_red,
-                                              int threads)
+                                              int threads, bool single_tile)
 {
     SmemPlan s;
     uint32_t at = 0;
@@ -125,7 +146,8 @@ __host__ __device__ inline SmemPlan smem_plan(int k, int c, int n_ops, int n_dia
     s.dtab = at;
     at += (uint32_t)n_diag * kDiagTab * 16u;
     s.red = at;
-    at += (uint32_t)n_red * (uint32_t)threads * 8u;
+    at += (uint32_t)n_red * (single_tile ? 1u : (uint32_t)threads) * 8u;
+    at += 16u * 8u;   // per-wave partial sums
     s.total = at;
     return s;
 }

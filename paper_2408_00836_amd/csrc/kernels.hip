@@ -197,23 +197,6 @@ __device__ __forceinline__ void relayout(double2 (&v)[NV][kRegs], double2 *xbuf,
     }
 }
 
-__device__ void block_reduce_rows(double *red, int n_red, double *partial, int red_base,
-                                  int stride)
-{
-    const int T = blockDim.x, tid = threadIdx.x;
-    for (int r = 0; r < n_red; ++r) {
-        double *row = red + r * T;
-        for (int s = T >> 1; s > 0; s >>= 1) {
-            __syncthreads();
-            if (tid < s)
-                row[tid] += row[tid + s];
-        }
-        __syncthreads();
-        if (tid == 0)
-            partial[(size_t)(red_base + r) * stride + blockIdx.x] = row[0];
-    }
-}
-
 // One pass of MODE over every tile.
 //   M_FWD: v0 = psi; apply the pass's gates.
 //   M_REV: v0 = psi, v1 = lambda; ops are listed in un-application order;
@@ -223,20 +206,53 @@ __device__ void block_reduce_rows(double *red, int n_red, double *partial, int r
 //   M_HAM: v0 = psi (read), v1 = phi: phi <- D psi + terms (first pass) or
 //          phi += terms; the last pass also reduces Re <psi|phi> (energy).
 //   M_EXP: v0 = psi (read only): reduce <psi|term|psi> for the pass's terms.
+// Where a pass's reduction rows go: the partial array of the two-stage
+// reduction (row r, block b at partial[(red_base + r) * stride + b]), or, for
+// a batched instance, straight into its outputs (row_param != nullptr).
+struct Sink {
+    double *partial;
+    int stride, block;
+    const int32_t *row_param;
+    double *E, *grad;
+};
+
+// Sum of x over the workgroup, valid in thread 0 (fixed shuffle tree, then
+// the waves in order).  All threads must call it.
+__device__ __forceinline__ double block_sum(double x, double *wsum)
+{
+    const int T = blockDim.x, tid = threadIdx.x;
+    for (int off = (T < 64 ? T : 64) >> 1; off > 0; off >>= 1)
+        x += __shfl_xor(x, off);
+    if ((tid & 63) == 0)
+        wsum[tid >> 6] = x;
+    __syncthreads();
+    double tot = 0.0;
+    if (tid == 0)
+        for (int w = 0; w < (T + 63) / 64; ++w)
+            tot += wsum[w];
+    __syncthreads();
+    return tot;
+}
+
 template <int MODE, bool GEN>
-__global__ void __launch_bounds__(512)
-k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__ ops,
-       const DevVBond *__restrict__ vb, const double *__restrict__ theta,
-       const DevModel *__restrict__ M, double2 *__restrict__ v0, double2 *__restrict__ v1,
-       double *__restrict__ partial, int stride)
+__device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__restrict__ phases,
+                                         const DevOp *__restrict__ ops,
+                                         const DevVBond *__restrict__ vb,
+                                         const double *__restrict__ theta,
+                                         const DevModel *__restrict__ M, double2 *__restrict__ v0,
+                                         double2 *__restrict__ v1, char *smem, uint64_t tile0,
+                                         uint64_t tstep, const Sink &sink)
 {
     constexpr int NV = (MODE == M_FWD || MODE == M_EXP) ? 1 : 2;
-    extern __shared__ __align__(16) char smem[];
     const int T = blockDim.x, tid = threadIdx.x;
+    // a batch workgroup may be wider than this pass's 2^tbits threads: the
+    // extra threads keep zero registers and only join the barriers
+    const bool act = tid < (1 << P.tbits);
     const bool ham_first = (MODE == M_HAM) && (P.flags & PF_HAM_FIRST);
     const bool ham_last = (MODE == M_HAM) && (P.flags & PF_HAM_LAST);
     const int n_red = (MODE == M_REV) ? P.n_red : (MODE == M_EXP) ? 1 : P.n_red;
-    const SmemPlan sp = smem_plan(P.k, P.c, P.n_ops, P.n_diag, n_red, T);
+    const bool single = (P.nfree == 0);
+    const SmemPlan sp = smem_plan(P.k, P.c, P.n_ops, P.n_diag, n_red, T, single);
     double2 *xbuf = (double2 *)(smem + sp.xbuf);
     uint32_t *offs = (uint32_t *)(smem + sp.offs);
     double2 *opc = (double2 *)(smem + sp.opc);
@@ -271,10 +287,16 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
                 }
             }
         }
-        for (int r = 0; r < n_red; ++r)
-            red[r * T + tid] = 0.0;
+        if (single) {
+            for (int r = tid; r < n_red; r += T)
+                red[r] = 0.0;
+        } else {
+            for (int r = 0; r < n_red; ++r)
+                red[r * T + tid] = 0.0;
+        }
     }
     __syncthreads();
+    double *wsum = red + n_red * (single ? 1 : T);
 
     const uint32_t cmask = (1u << P.c) - 1u;
     const uint64_t ntiles = (uint64_t)1 << P.nfree;
@@ -283,7 +305,7 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
     double eacc = 0.0;
     double2 v[NV][kRegs];
 
-    for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    for (uint64_t tl = tile0; tl < ntiles; tl += tstep) {
         const uint32_t base = pdep32((uint32_t)tl, P.free_mask);
         uint32_t tloc = thread_local_index(ph[0].tmask, tid);
         uint32_t gthr = base | offs[tloc >> P.c] | (tloc & cmask);
@@ -295,7 +317,7 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
             v[0][j] = make_double2(0.0, 0.0);
             if constexpr (NV == 2)
                 v[NV - 1][j] = make_double2(0.0, 0.0);
-            if ((valid >> j) & 1u) {
+            if (act && ((valid >> j) & 1u)) {
                 const uint64_t g = gthr | ph[0].goff[j];
                 v[0][j] = v0[g];
                 if constexpr (NV == 2)
@@ -306,12 +328,13 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
         for (int q = 0; q < P.n_phases; ++q) {
             if (q > 0) {
                 const uint32_t tnew = thread_local_index(ph[q].tmask, tid);
-                relayout<NV>(v, xbuf, tloc, ph[q - 1], tnew, ph[q], valid);
+                relayout<NV>(v, xbuf, tloc, ph[q - 1], tnew, ph[q], act ? valid : 0u);
                 tloc = tnew;
                 gthr = base | offs[tloc >> P.c] | (tloc & cmask);
             }
             for (int o = ph[q].op_begin; o < ph[q].op_end; ++o) {
                 const DevOp op = ops[P.op_begin + o];
+                double dacc = 0.0;   // reverse: this op's Im <lambda|D_sub|psi>
                 if (op.kind == OP_DIAG) {
 #pragma unroll
                     for (int j = 0; j < kRegs; ++j) {
@@ -331,7 +354,7 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
                             }
                             if constexpr (MODE == M_REV) {
                                 double d = diag_value<GEN>(op, g, M, vb);
-                                red[op.red * T + tid] += d * im_conj_mul(v[NV - 1][j], v[0][j]);
+                                dacc += d * im_conj_mul(v[NV - 1][j], v[0][j]);
                                 v[NV - 1][j] = cmul(v[NV - 1][j], phs);
                             }
                             v[0][j] = cmul(v[0][j], phs);
@@ -342,6 +365,15 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
                         } else {
                             double2 a = v[0][j];
                             eacc += diag_value<GEN>(op, g, M, vb) * (a.x * a.x + a.y * a.y);
+                        }
+                    }
+                    if constexpr (MODE == M_REV) {
+                        if (single) {
+                            const double tot = block_sum(dacc, wsum);
+                            if (tid == 0)
+                                red[op.red] += tot;
+                        } else {
+                            red[op.red * T + tid] += dacc;
                         }
                     }
                 } else {
@@ -358,8 +390,15 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
                         x.cs = x.sn = 0.0;
                     }
                     hop_regs<MODE, NV>(op.pair, v, x);
-                    if constexpr (MODE == M_REV)
-                        red[op.red * T + tid] += -op.t * x.acc;
+                    if constexpr (MODE == M_REV) {
+                        if (single) {
+                            const double tot = block_sum(-op.t * x.acc, wsum);
+                            if (tid == 0)
+                                red[op.red] += tot;
+                        } else {
+                            red[op.red * T + tid] += -op.t * x.acc;
+                        }
+                    }
                     if constexpr (MODE == M_EXP)
                         eacc += -2.0 * op.t * x.acc;
                 }
@@ -370,7 +409,7 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
         if constexpr (MODE != M_EXP) {
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) {
-                if ((valid >> j) & 1u) {
+                if (act && ((valid >> j) & 1u)) {
                     const uint64_t g = gthr | pl.goff[j];
                     if constexpr (MODE == M_FWD || MODE == M_REV)
                         v0[g] = v[0][j];
@@ -382,11 +421,118 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
             }
         }
     }
+    __syncthreads();
     if (MODE == M_EXP || (MODE == M_HAM && n_red > 0)) {
+        const double tot = block_sum(eacc, wsum);
+        if (tid == 0)
+            red[0] = tot;
         __syncthreads();
-        red[tid] = eacc;
+    } else if (!single) {
+        // per-thread rows -> row sums in red[r * T]
+        for (int r = 0; r < n_red; ++r) {
+            double *row = red + r * T;
+            for (int s = T >> 1; s > 0; s >>= 1) {
+                __syncthreads();
+                if (tid < s)
+                    row[tid] += row[tid + s];
+            }
+        }
+        __syncthreads();
     }
-    block_reduce_rows(red, n_red, partial, P.red_base, stride);
+    if (tid == 0) {
+        const int rstride = (MODE == M_EXP || MODE == M_HAM || single) ? 1 : T;
+        for (int r = 0; r < n_red; ++r) {
+            const double val = red[r * rstride];
+            if (sink.row_param) {
+                const int prm = sink.row_param[P.red_base + r];
+                if (prm < 0)
+                    sink.E[0] = val;
+                else
+                    sink.grad[prm] += 2.0 * val;
+            } else {
+                sink.partial[(size_t)(P.red_base + r) * sink.stride + sink.block] = val;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int MODE, bool GEN>
+__global__ void __launch_bounds__(512)
+k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__ ops,
+       const DevVBond *__restrict__ vb, const double *__restrict__ theta,
+       const DevModel *__restrict__ M, double2 *__restrict__ v0, double2 *__restrict__ v1,
+       double *__restrict__ partial, int stride)
+{
+    extern __shared__ __align__(16) char smem[];
+    Sink sink{partial, stride, (int)blockIdx.x, nullptr, nullptr, nullptr};
+    run_pass<MODE, GEN>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x, gridDim.x, sink);
+}
+
+// Persistent batch kernel: each workgroup claims whole instances from a
+// work counter (instances are listed largest first) and runs the instance's
+// initial state, forward passes, H passes and reverse passes itself, looping
+// over all tiles of every pass, so no synchronisation between workgroups is
+// needed.  Results go straight into the instance's E and gradient.  The
+// counter must be zero at launch (k_fill_u32 before this kernel).
+__global__ void __launch_bounds__(512)
+k_batch(const DevInstance *__restrict__ inst, const DevPass *__restrict__ passes, int n_inst,
+        unsigned int *__restrict__ counter)
+{
+    extern __shared__ __align__(16) char smem_all[];
+    int *claim = (int *)smem_all;   // first 16 bytes; the passes use the rest
+    char *smem = smem_all + 16;
+    const int T = blockDim.x, tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0)
+            *claim = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int i = *claim;
+        __syncthreads();
+        if (i >= n_inst)
+            break;
+        const DevInstance I = inst[i];
+        double2 *psi = (double2 *)I.psi, *lam = (double2 *)I.lam;
+        for (uint64_t b = tid; b < I.dim; b += T)
+            psi[b] = make_double2(b == I.neel ? 1.0 : 0.0, 0.0);
+        for (int p = tid; p < I.n_params; p += T)
+            I.grad[p] = 0.0;
+        __syncthreads();
+        Sink sink{nullptr, 0, 0, I.row_param, I.E, I.grad};
+        const DevPass *ps = passes + I.pass_begin;
+        for (int p = 0; p < I.n_fwd; ++p) {
+            if (I.general)
+                run_pass<M_FWD, true>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                                      smem, 0, 1, sink);
+            else
+                run_pass<M_FWD, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                                       smem, 0, 1, sink);
+        }
+        ps += I.n_fwd;
+        for (int p = 0; p < I.n_ham; ++p) {
+            if (I.general)
+                run_pass<M_HAM, true>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                                      smem, 0, 1, sink);
+            else
+                run_pass<M_HAM, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                                       smem, 0, 1, sink);
+        }
+        ps += I.n_ham;
+        for (int p = 0; p < I.n_rev; ++p) {
+            if (I.general)
+                run_pass<M_REV, true>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                                      smem, 0, 1, sink);
+            else
+                run_pass<M_REV, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                                       smem, 0, 1, sink);
+        }
+    }
+}
+
+__global__ void k_fill_u32(unsigned int *p, unsigned int v, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 #define HV_INSTANTIATE(MODE, GEN)                                                          \

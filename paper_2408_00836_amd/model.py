@@ -8,6 +8,7 @@ come from torch, every step of the path runs in the library's kernels.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import abi
@@ -148,3 +149,71 @@ class EnergyGrad(torch.autograd.Function):
     def backward(ctx, gE):
         (g,) = ctx.saved_tensors
         return gE * g, None
+
+
+class Batch:
+    """Many independent instances evaluated (energy + adjoint gradient) in one
+    persistent launch.  Parameters of instance i live at
+    theta[offsets[i] : offsets[i] + n_params[i]] of one device vector; the
+    gradient uses the same layout.
+
+        b = Batch(models, layers)
+        E, g = b.energy_grad(theta)        # eager
+        b.capture(theta)                   # optional: hipGraph of the launch
+        E, g = b.replay()                  # reads theta in place
+    """
+
+    def __init__(self, models, layers, device="cuda"):
+        self.models = list(models)
+        self.layers = [int(L) for L in layers]
+        self.n_params = [m.n_params(L) for m, L in zip(self.models, self.layers)]
+        self.offsets = np.concatenate([[0], np.cumsum(self.n_params)[:-1]]).astype(np.int64)
+        self.total = int(sum(self.n_params))
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        hs = [m.handle for m in self.models]
+        self.ws = torch.empty(abi.hubbard_batch_workspace_size(hs), dtype=torch.uint8, device=dev)
+        self.E = torch.empty(len(self.models), dtype=torch.float64, device=dev)
+        self.grad = torch.empty(max(self.total, 1), dtype=torch.float64, device=dev)
+        self.theta = torch.zeros(max(self.total, 1), dtype=torch.float64, device=dev)
+        self.graph = None
+
+    def _launch(self):
+        abi.energy_grad_batch([m.handle for m in self.models], self.theta.data_ptr(),
+                              self.offsets, self.layers, self.E.data_ptr(),
+                              self.grad.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+                              _stream())
+
+    def energy_grad(self, theta: torch.Tensor):
+        _require_gpu(theta, "theta", torch.float64)
+        if theta.numel() != self.total:
+            raise ValueError("theta must hold every instance's parameters")
+        self.theta[: self.total].copy_(theta)
+        self._launch()
+        return self.E, self.grad[: self.total]
+
+    def capture(self, theta: torch.Tensor):
+        """Record the batch launch in a graph (after one eager call, which
+        plans and uploads the batch tables)."""
+        self.energy_grad(theta)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            g.capture_begin()
+            self._launch()
+            g.capture_end()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = g
+        return g
+
+    def replay(self, theta: torch.Tensor | None = None):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        if theta is not None:
+            self.theta[: self.total].copy_(theta)
+        self.graph.replay()
+        return self.E, self.grad[: self.total]
