@@ -33,6 +33,22 @@ hubbard_status hubbard_plan_dump(hubbard_t h, int32_t n_layers, int32_t which, i
  * call it before queueing work, not while work is in flight. */
 hubbard_status hubbard_set_tiles(hubbard_t h, int32_t fwd_k, int32_t rev_k, int32_t c);
 
+/* Current tile configuration: cfg[0] forward k, cfg[1] reverse k, cfg[2] c. */
+hubbard_status hubbard_get_tiles(hubbard_t h, int32_t *cfg);
+
+/* Autotuner: times energy_grad (n_layers, theta_dev) for each candidate tile
+ * configuration (forward k in {11,12,13}, reverse/H k in {10,11,12}, c in
+ * {4,5}, clipped to the qubit count; each fixes a different fusion schedule)
+ * with HIP events on `stream`, best of `reps` runs, and leaves the fastest
+ * configured on the handle.  Configurations whose workspace exceeds ws_bytes
+ * are skipped.  If table is not NULL it receives up to table_cap rows of
+ * (fwd_k, rev_k, c) and table_ms their times; *n_tried counts the timed
+ * configurations.  Allocates two small output buffers for its own runs and
+ * synchronises the stream; not for use under graph capture. */
+hubbard_status hubbard_tune(hubbard_t h, int32_t n_layers, const double *theta_dev, void *ws_dev,
+                            size_t ws_bytes, void *stream, int32_t reps, int32_t *table,
+                            int32_t table_cap, int32_t *n_tried, float *table_ms);
+
 /* Phase timing.  When enabled, every later call records HIP events on its own
  * stream around its phases: the forward passes, the H (or expectation)
  * passes and the reverse passes.  hubbard_phase_ms waits for the last

@@ -30,7 +30,7 @@ EXPORTED = [
     "hubbard_last_error", "hubbard_workspace_size", "hubbard_init_neel",
     "ansatz_apply", "hamiltonian_apply", "energy", "energy_grad",
     "hubbard_plan_dump", "hubbard_set_tiles", "hubbard_set_timing", "hubbard_phase_ms",
-    "hubbard_batch_workspace_size", "energy_grad_batch",
+    "hubbard_batch_workspace_size", "energy_grad_batch", "hubbard_get_tiles", "hubbard_tune",
 ]
 
 
@@ -81,6 +81,9 @@ def lib() -> ctypes.CDLL:
             "hubbard_plan_dump": ([vp, i32, i32, P(i32), i64, P(i64)], st),
             "hubbard_set_tiles": ([vp, i32, i32, i32], st),
             "hubbard_set_timing": ([vp, i32], st),
+            "hubbard_get_tiles": ([vp, P(i32)], st),
+            "hubbard_tune": ([vp, i32, vp, vp, ctypes.c_size_t, vp, i32, P(i32), i32, P(i32),
+                              P(ctypes.c_float)], st),
             "hubbard_batch_workspace_size": ([P(vp), i32, P(ctypes.c_size_t)], st),
             "energy_grad_batch": ([P(vp), i32, vp, P(i64), P(i32), vp, vp, vp, ctypes.c_size_t,
                                    vp], st),
@@ -239,3 +242,21 @@ def energy_grad_batch(hs, theta_dev: int, theta_off, n_layers, E_dev: int, grad_
                                    off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                    lay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                    E_dev, grad_dev, ws_dev, int(ws_bytes), stream))
+
+
+def hubbard_get_tiles(h: int):
+    cfg = (ctypes.c_int32 * 3)()
+    _check(lib().hubbard_get_tiles(h, cfg))
+    return tuple(cfg)
+
+
+def hubbard_tune(h: int, n_layers: int, theta_dev: int, ws_dev: int, ws_bytes: int,
+                 stream: int = 0, reps: int = 2):
+    """Returns [(fwd_k, rev_k, c, ms), ...]; the best is left configured."""
+    cap = 64
+    table = (ctypes.c_int32 * (3 * cap))()
+    ms = (ctypes.c_float * cap)()
+    n = ctypes.c_int32()
+    _check(lib().hubbard_tune(h, int(n_layers), theta_dev, ws_dev, int(ws_bytes), stream,
+                              int(reps), table, cap, ctypes.byref(n), ms))
+    return [(table[3 * i], table[3 * i + 1], table[3 * i + 2], ms[i]) for i in range(n.value)]

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -1038,6 +1039,101 @@ hubbard_status hubbard_set_tiles(hubbard_t h, int32_t fwd_k, int32_t rev_k, int3
     h->rev_tc = TileConfig{rev_k, c};
     for (auto &kv : h->dev)
         kv.second.progs.clear();
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_get_tiles(hubbard_t h, int32_t *cfg)
+{
+    if (!h || !cfg)
+        return fail(HUBBARD_ERR_ARG, "NULL argument to hubbard_get_tiles");
+    cfg[0] = h->fwd_tc.k;
+    cfg[1] = h->rev_tc.k;
+    cfg[2] = h->fwd_tc.c;
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_tune(hubbard_t h, int32_t n_layers, const double *theta_dev, void *ws_dev,
+                            size_t ws_bytes, void *stream, int32_t reps, int32_t *table,
+                            int32_t table_cap, int32_t *n_tried, float *table_ms)
+{
+    if (!h || n_layers < 1 || !theta_dev || !ws_dev || reps < 1 || !n_tried)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_tune");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = h->m.nq;
+    std::vector<std::array<int, 3>> cands;
+    for (int fk : {11, 12, 13})
+        for (int rk : {10, 11, 12})
+            for (int c : {4, 5}) {
+                int f = std::min(fk, n), r = std::min(rk, n), cc = std::min(c, std::min(f, r));
+                std::array<int, 3> x{f, r, cc};
+                if (std::find(cands.begin(), cands.end(), x) == cands.end())
+                    cands.push_back(x);
+            }
+    const TileConfig keep_f = h->fwd_tc, keep_r = h->rev_tc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, "creating tuning events");
+    double *E = nullptr, *g = nullptr;
+    const int P = n_layers * h->m.params_per_layer();
+    if (hipMalloc((void **)&E, sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&g, sizeof(double) * (size_t)P) != hipSuccess) {
+        (void)hipFree(E);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(HUBBARD_ERR_NOMEM, "tuning outputs");
+    }
+    float best = -1.0f;
+    std::array<int, 3> bestc{keep_f.k, keep_r.k, keep_f.c};
+    int tried = 0;
+    hubbard_status st = HUBBARD_OK;
+    for (const auto &cf : cands) {
+        hubbard_set_tiles(h, cf[0], cf[1], cf[2]);
+        size_t need = 0;
+        if (hubbard_workspace_size(h, n_layers, HUBBARD_OP_ENERGY_GRAD, &need) != HUBBARD_OK ||
+            need > ws_bytes)
+            continue;
+        if ((st = energy_grad(h, theta_dev, n_layers, E, g, ws_dev, ws_bytes, stream)) !=
+            HUBBARD_OK)
+            break;   // (also plans and uploads this configuration)
+        float ms = 1e30f;
+        for (int r = 0; r < reps; ++r) {
+            (void)hipEventRecord(e0, s);
+            energy_grad(h, theta_dev, n_layers, E, g, ws_dev, ws_bytes, stream);
+            (void)hipEventRecord(e1, s);
+            float t = 0.0f;
+            if (hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+                st = fail(HUBBARD_ERR_DEVICE, "tuning timing");
+                break;
+            }
+            ms = std::min(ms, t);
+        }
+        if (st != HUBBARD_OK)
+            break;
+        if (table && tried < table_cap) {
+            table[3 * tried] = cf[0];
+            table[3 * tried + 1] = cf[1];
+            table[3 * tried + 2] = cf[2];
+            if (table_ms)
+                table_ms[tried] = ms;
+        }
+        ++tried;
+        if (best < 0.0f || ms < best) {
+            best = ms;
+            bestc = cf;
+        }
+    }
+    (void)hipFree(E);
+    (void)hipFree(g);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *n_tried = tried;
+    if (st != HUBBARD_OK) {
+        h->fwd_tc = keep_f;
+        h->rev_tc = keep_r;
+        return st;
+    }
+    hubbard_set_tiles(h, bestc[0], bestc[1], bestc[2]);
     return HUBBARD_OK;
 }
 

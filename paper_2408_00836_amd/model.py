@@ -33,6 +33,8 @@ class Hubbard:
     def __init__(self, nx: int, ny: int, *, periodic_x: bool = False, periodic_y: bool = False,
                  t=None, U: float = 0.0, V=None, eps=None, groups=None):
         self.handle = abi.hubbard_create(nx, ny, periodic_x, periodic_y, t, U, V, eps, groups)
+        self.nx, self.ny = nx, ny
+        self.periodic_x, self.periodic_y = bool(periodic_x), bool(periodic_y)
         q = abi.hubbard_query(self.handle)
         self.n_qubits = q["n_qubits"]
         self.n_bonds = q["n_bonds"]
