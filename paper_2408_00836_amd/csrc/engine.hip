@@ -234,13 +234,23 @@ struct Builder {
                 std::memset(&D, 0, sizeof(D));
                 D.op_begin = hph.op_begin;
                 D.op_end = hph.op_end;
-                uint32_t regmask = 0;
+                uint32_t regmask = 0, wmask = 0;
                 for (int b : hph.regs)
                     regmask |= 1u << b;
-                D.tmask = 0;
+                for (int b : hph.wave)
+                    wmask |= 1u << b;
+                D.wmask = wmask;
+                D.lmask = 0;
                 for (int b = 0; b < P.k; ++b)
-                    if (!((regmask >> b) & 1u))
-                        D.tmask |= 1u << b;
+                    if (!((regmask >> b) & 1u) && !((wmask >> b) & 1u))
+                        D.lmask |= 1u << b;
+                if (__builtin_popcount(D.lmask) > 6 ||
+                    (__builtin_popcount(wmask) > 0 && __builtin_popcount(D.lmask) != 6))
+                    throw std::runtime_error("phase layout needs 6 lane bits before wave bits");
+                D.cross = (!phases.empty() && (int)phases.size() > P.phase_begin &&
+                           phases.back().wmask != wmask)
+                              ? 1u
+                              : 0u;
                 D.valid = 0;
                 for (int j = 0; j < kRegs; ++j) {
                     uint32_t lo = 0, go = 0;
@@ -278,6 +288,10 @@ struct Builder {
                     static const int pair_of[4][4] = {
                         {-1, 0, 1, 2}, {0, -1, 3, 4}, {1, 3, -1, 5}, {2, 4, 5, -1}};
                     op.pair = pair_of[a][b];
+                    op.flip = 0;
+                    for (int j = 0; j < kRegs; ++j)
+                        if (__builtin_popcount(D.roff[j] & op.bm_local) & 1)
+                            op.flip |= 1u << j;
                 }
                 phases.push_back(D);
             }

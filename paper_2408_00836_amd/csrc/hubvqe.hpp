@@ -41,7 +41,7 @@ struct DevOp {
     int32_t red;        // reduction row within the pass (-1: none)
     int32_t dtab;       // DIAG: index of its phase table within the pass
     int32_t pair;       // HOP: register-bit pair (0..5: 01 02 03 12 13 23) in its phase
-    int32_t pad0;
+    uint32_t flip;      // HOP: bit j = parity of register j's local bits in bm_local
     uint32_t bm_local;  // HOP: Jordan-Wigner between-mask over tile-local bits
     uint32_t bm_free;   // HOP: between-mask over the free (tile-index) bits
     uint32_t umask;     // DIAG: spin-up qubits of the sites whose U term it carries
@@ -55,7 +55,7 @@ static_assert(sizeof(DevOp) == 64, "DevOp layout");
 
 // Register layout of one phase of a pass.  Each thread holds 16 amplitudes of
 // the tile in registers: register j holds tile-local index tloc | roff[j],
-// where tloc deposits the thread id over the local bits in tmask and roff[j]
+// where tloc deposits the lane id over lmask and the wave id over wmask, and roff[j]
 // deposits j over the phase's four register bits.  Gates of the phase act on
 // register bits only; between phases the tile is re-laid out through LDS.
 constexpr int kRegs = 16;
@@ -64,9 +64,10 @@ struct DevPhase {
     int32_t op_begin, op_end;   // ops of this phase (absolute indices)
     uint32_t roff[kRegs];       // tile-local bits of register j
     uint32_t goff[kRegs];       // global index bits of register j
-    uint32_t tmask;             // tile-local bits that carry the thread id (ascending)
+    uint32_t lmask;             // tile-local bits that carry the lane id (ascending)
+    uint32_t wmask;             // tile-local bits that carry the wave id (ascending)
     uint32_t valid;             // bit j: register j holds an amplitude (tiles < 16)
-    uint32_t pad[2];
+    uint32_t cross;             // 1: entering this phase moves data between waves
 };
 
 // A V bond as the device reads it: qubits (i up, i dn, j up, j dn) and V_b.
@@ -185,6 +186,7 @@ struct HostOp {
 // phase's register bits `regs` (tile-local bit indices, at most four).
 struct HostPhase {
     std::vector<int> regs;
+    std::vector<int> wave;   // tile-local bits that index the workgroup's waves
     int op_begin = 0, op_end = 0;
 };
 

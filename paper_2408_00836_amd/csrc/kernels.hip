@@ -52,18 +52,11 @@ __device__ __forceinline__ uint32_t slot(uint32_t l)
     return l ^ (((l >> 4) ^ (l >> 8)) & 15u);
 }
 
-// Deposit the thread id over the local bits of tmask (lowest id bit into the
-// lowest set bit).  tmask is uniform, so the loop is scalar control flow.
-__device__ __forceinline__ uint32_t thread_local_index(uint32_t tmask, int tid)
+// Tile-local index bits of this thread: the lane id deposited over lmask and
+// the wave id over wmask (masks are wave-uniform: scalar loops).
+__device__ __forceinline__ uint32_t thread_local_index(uint32_t lmask, uint32_t wmask, int tid)
 {
-    uint32_t t = 0;
-    for (int i = 0; tmask; ++i) {
-        const uint32_t low = tmask & (0u - tmask);
-        if ((tid >> i) & 1)
-            t |= low;
-        tmask ^= low;
-    }
-    return t;
+    return pdep32((uint32_t)(tid & 63), lmask) | pdep32((uint32_t)(tid >> 6), wmask);
 }
 
 // Diagonal sub-term value D_sub(g); GEN: the model has eps or V terms.
@@ -111,38 +104,43 @@ __device__ __forceinline__ void rotate(double2 &x, double2 &y, double c, double 
     y = make_double2(c * b.x - s * a.y, c * b.y + s * a.x);
 }
 
-// Per-op context of a hopping term applied in registers.
+// Per-op context of a hopping term applied in registers.  The Jordan-Wigner
+// sign of a pair is (-1)^(par_thread + par_reg): the thread/tile part is
+// folded into sn and t once per op; the register part is a wave-uniform bit
+// of the op's flip mask (precomputed from the phase layout), applied by one
+// XOR of the sign bit -- no loads and no branches per pair.
 struct PairCtx {
-    double cs, sn, t;      // rotation (cos, sin) and bond hopping
-    uint32_t par0, bm;     // sign parity from thread/tile bits; between-mask
-    const uint32_t *roff;  // tile-local bits of each register (uniform)
-    double acc;            // reduction of the op
+    double cs, sn, t;      // rotation (cos, thread-signed sin); thread-signed (-t)
+    uint32_t flip;         // bit j: register j's part of the sign is odd
+    double acc;            // reduction of the op (register part of the sign applied)
 };
 
-// The pair (J, JJ) of registers that the term couples; J has the term's
-// first register bit set and the second clear.  All register indices are
-// compile-time constants, so the register arrays never go to scratch.
+__device__ __forceinline__ double flip_sign(double x, uint32_t bit)
+{
+    return __longlong_as_double(__double_as_longlong(x) ^ ((long long)bit << 63));
+}
+
 template <int MODE, int NV, int J, int JJ>
 __device__ __forceinline__ void pair_op(double2 (&v)[NV][kRegs], PairCtx &x)
 {
-    const uint32_t par = (x.par0 + __popc(x.roff[J] & x.bm)) & 1u;
+    const uint32_t fb = (x.flip >> J) & 1u;   // wave-uniform
     if constexpr (MODE == 0) {            // forward gate
-        rotate(v[0][J], v[0][JJ], x.cs, par ? -x.sn : x.sn);
+        rotate(v[0][J], v[0][JJ], x.cs, flip_sign(x.sn, fb));
     } else if constexpr (MODE == 1) {     // reverse: reduce, then un-apply
-        double w = im_conj_mul(v[NV - 1][J], v[0][JJ]) + im_conj_mul(v[NV - 1][JJ], v[0][J]);
-        x.acc += par ? -w : w;
-        const double ss = par ? -x.sn : x.sn;
+        const double w =
+            im_conj_mul(v[NV - 1][J], v[0][JJ]) + im_conj_mul(v[NV - 1][JJ], v[0][J]);
+        x.acc += flip_sign(w, fb);
+        const double ss = flip_sign(x.sn, fb);
         rotate(v[0][J], v[0][JJ], x.cs, ss);
         rotate(v[NV - 1][J], v[NV - 1][JJ], x.cs, ss);
     } else if constexpr (MODE == 2) {     // phi += (-t) s (swap) psi
-        const double w = par ? x.t : -x.t;
+        const double w = flip_sign(x.t, fb);
         v[NV - 1][J].x += w * v[0][JJ].x;
         v[NV - 1][J].y += w * v[0][JJ].y;
         v[NV - 1][JJ].x += w * v[0][J].x;
         v[NV - 1][JJ].y += w * v[0][J].y;
     } else {                              // expectation
-        const double r = re_conj_mul(v[0][J], v[0][JJ]);
-        x.acc += par ? -r : r;
+        x.acc += flip_sign(re_conj_mul(v[0][J], v[0][JJ]), fb);
     }
 }
 
@@ -177,35 +175,40 @@ __device__ __forceinline__ void hop_regs(int pair, double2 (&v)[NV][kRegs], Pair
     }
 }
 
+// Re-lay the tile out from one phase's register layout to the next through
+// LDS.  slot() is linear over GF(2) and a thread's local bits never overlap
+// a register's, so slot(tl | roff) = slot(tl) ^ slot(roff): one vector XOR
+// per register, the register part computed on the scalar unit.
+// If the wave bits stay fixed (cross == 0) every wave reads back exactly the
+// slots it wrote, in program order, so no workgroup barrier is needed; every
+// LDS slot a wave touches between cross-wave exchanges is its own.
 template <int NV>
-__device__ __forceinline__ void relayout(double2 (&v)[NV][kRegs], double2 *xbuf, uint32_t tl_from,
+__device__ __forceinline__ void relayout(double2 (&v)[NV][kRegs], char *xbuf, uint32_t tl_from,
                                          const DevPhase &from, uint32_t tl_to,
                                          const DevPhase &to, uint32_t valid)
 {
+    const uint32_t xf = slot(tl_from) << 4, xt = slot(tl_to) << 4;
+    const bool cross = to.cross != 0;
 #pragma unroll
     for (int w = 0; w < NV; ++w) {
+        if (cross && w > 0)
+            __syncthreads();   // the previous vector's reads are done everywhere
 #pragma unroll
         for (int j = 0; j < kRegs; ++j)
             if ((valid >> j) & 1u)
-                xbuf[slot(tl_from | from.roff[j])] = v[w][j];
-        __syncthreads();
+                *(double2 *)(xbuf + (xf ^ (slot(from.roff[j]) << 4))) = v[w][j];
+        if (cross)
+            __syncthreads();
+        else
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int j = 0; j < kRegs; ++j)
             if ((valid >> j) & 1u)
-                v[w][j] = xbuf[slot(tl_to | to.roff[j])];
-        __syncthreads();
+                v[w][j] = *(const double2 *)(xbuf + (xt ^ (slot(to.roff[j]) << 4)));
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// One pass of MODE over every tile.
-//   M_FWD: v0 = psi; apply the pass's gates.
-//   M_REV: v0 = psi, v1 = lambda; ops are listed in un-application order;
-//          for each op accumulate Im <lambda|G|psi> into its reduction row
-//          (the generator commutes with its own gate, so evaluating before the
-//          un-application is exact), then un-apply it to both vectors.
-//   M_HAM: v0 = psi (read), v1 = phi: phi <- D psi + terms (first pass) or
-//          phi += terms; the last pass also reduces Re <psi|phi> (energy).
-//   M_EXP: v0 = psi (read only): reduce <psi|term|psi> for the pass's terms.
 // Where a pass's reduction rows go: the partial array of the two-stage
 // reduction (row r, block b at partial[(red_base + r) * stride + b]), or, for
 // a batched instance, straight into its outputs (row_param != nullptr).
@@ -253,7 +256,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     const int n_red = (MODE == M_REV) ? P.n_red : (MODE == M_EXP) ? 1 : P.n_red;
     const bool single = (P.nfree == 0);
     const SmemPlan sp = smem_plan(P.k, P.c, P.n_ops, P.n_diag, n_red, T, single);
-    double2 *xbuf = (double2 *)(smem + sp.xbuf);
+    char *xbuf = smem + sp.xbuf;
     uint32_t *offs = (uint32_t *)(smem + sp.offs);
     double2 *opc = (double2 *)(smem + sp.opc);
     double2 *dtab = (double2 *)(smem + sp.dtab);
@@ -304,30 +307,52 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     const uint32_t valid = ph[0].valid;
     double eacc = 0.0;
     double2 v[NV][kRegs];
+    // the first phase's layout is the load layout; its thread part of the
+    // global index is the same for every tile
+    const uint32_t tloc0 = thread_local_index(ph[0].lmask, ph[0].wmask, tid);
+    const uint32_t gthr0 = offs[tloc0 >> P.c] | (tloc0 & cmask);
+    // Registers of a tile smaller than 16 amplitudes that hold nothing are
+    // zero, so they add nothing to any reduction.
+    auto load_tile = [&](double2 (&dst)[NV][kRegs], uint64_t t) __attribute__((always_inline)) {
+        const uint32_t gb = pdep32((uint32_t)t, P.free_mask) | gthr0;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            dst[0][j] = make_double2(0.0, 0.0);
+            if constexpr (NV == 2)
+                dst[NV - 1][j] = make_double2(0.0, 0.0);
+            if (act && ((valid >> j) & 1u)) {
+                const uint64_t g = gb | ph[0].goff[j];
+                dst[0][j] = v0[g];
+                if constexpr (NV == 2)
+                    if (!ham_first)
+                        dst[NV - 1][j] = v1[g];
+            }
+        }
+    };
+    // One-vector passes prefetch the next tile into a second register set
+    // while the current one is computed (the registers are there: occupancy
+    // is bounded by LDS, not by VGPRs, for these kernels).
+    constexpr bool PREFETCH = (NV == 1);
+    double2 nxt[NV][kRegs];
+    if (PREFETCH && tile0 < ntiles)
+        load_tile(nxt, tile0);
 
     for (uint64_t tl = tile0; tl < ntiles; tl += tstep) {
         const uint32_t base = pdep32((uint32_t)tl, P.free_mask);
-        uint32_t tloc = thread_local_index(ph[0].tmask, tid);
-        uint32_t gthr = base | offs[tloc >> P.c] | (tloc & cmask);
-        // ---- load in the first phase's layout
-        // (registers of a tile smaller than 16 amplitudes that hold nothing
-        // are zero, so they add nothing to any reduction)
+        uint32_t tloc = tloc0;
+        uint32_t gthr = base | gthr0;
+        if constexpr (PREFETCH) {
 #pragma unroll
-        for (int j = 0; j < kRegs; ++j) {
-            v[0][j] = make_double2(0.0, 0.0);
-            if constexpr (NV == 2)
-                v[NV - 1][j] = make_double2(0.0, 0.0);
-            if (act && ((valid >> j) & 1u)) {
-                const uint64_t g = gthr | ph[0].goff[j];
-                v[0][j] = v0[g];
-                if constexpr (NV == 2)
-                    if (!ham_first)
-                        v[NV - 1][j] = v1[g];
-            }
+            for (int j = 0; j < kRegs; ++j)
+                v[0][j] = nxt[0][j];
+            if (tl + tstep < ntiles)
+                load_tile(nxt, tl + tstep);
+        } else {
+            load_tile(v, tl);
         }
         for (int q = 0; q < P.n_phases; ++q) {
             if (q > 0) {
-                const uint32_t tnew = thread_local_index(ph[q].tmask, tid);
+                const uint32_t tnew = thread_local_index(ph[q].lmask, ph[q].wmask, tid);
                 relayout<NV>(v, xbuf, tloc, ph[q - 1], tnew, ph[q], act ? valid : 0u);
                 tloc = tnew;
                 gthr = base | offs[tloc >> P.c] | (tloc & cmask);
@@ -378,29 +403,31 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                     }
                 } else {
                     PairCtx x;
-                    x.par0 = (__popc(tloc & op.bm_local) + __popc((uint32_t)tl & op.bm_free)) & 1u;
-                    x.bm = op.bm_local;
-                    x.roff = ph[q].roff;
-                    x.t = op.t;
+                    const bool podd =
+                        ((__popc(tloc & op.bm_local) + __popc((uint32_t)tl & op.bm_free)) & 1u) != 0;
+                    x.flip = op.flip;
+                    x.t = podd ? op.t : -op.t;   // (-t) times the thread part of the sign
                     x.acc = 0.0;
                     if constexpr (MODE == M_FWD || MODE == M_REV) {
                         x.cs = opc[o].x;
-                        x.sn = opc[o].y;
+                        x.sn = podd ? -opc[o].y : opc[o].y;
                     } else {
                         x.cs = x.sn = 0.0;
                     }
                     hop_regs<MODE, NV>(op.pair, v, x);
+                    // (-t) s summed: thread part of s applied here
+                    const double red_op = x.t * x.acc;
                     if constexpr (MODE == M_REV) {
                         if (single) {
-                            const double tot = block_sum(-op.t * x.acc, wsum);
+                            const double tot = block_sum(red_op, wsum);
                             if (tid == 0)
                                 red[op.red] += tot;
                         } else {
-                            red[op.red * T + tid] += -op.t * x.acc;
+                            red[op.red * T + tid] += red_op;
                         }
                     }
                     if constexpr (MODE == M_EXP)
-                        eacc += -2.0 * op.t * x.acc;
+                        eacc += 2.0 * red_op;
                 }
             }
         }

@@ -15,6 +15,7 @@
 // gate only waits for the sub-terms on its own sites.
 #include <algorithm>
 #include <cstdint>
+#include <tuple>
 #include <vector>
 
 #include "hubvqe.hpp"
@@ -387,31 +388,76 @@ void plan_phases(HostPass &p)
     uint32_t io_forbid = 0;
     for (int b = 0; b < std::min(4, k - kRegBits); ++b)
         io_forbid |= 1u << b;
-    auto pad = [&](uint32_t S) {
+    // Thread-id bits beyond the 6 lane bits index the waves of a workgroup.
+    // A re-layout that keeps the wave bits fixed moves data only inside each
+    // wave and needs no workgroup barrier, so the wave bits go on the tile
+    // bits (other than the coalescing ones) that the fewest hopping terms
+    // touch.
+    const int wb = std::max(0, k - rbits - 6);
+    std::vector<int> touch(k, 0);
+    for (const HostOp &o : lops)
+        if (o.kind == OP_HOP)
+            for (int b = 0; b < k; ++b)
+                touch[b] += (o.qmask >> b) & 1u;
+    auto wave_rank = [&](int b) {
+        // never on the coalescing bits: a wave's loads stay 256-byte runs
+        int io = ((io_forbid >> b) & 1u) ? 1 : 0;
+        return std::make_tuple(io, touch[b], -b);
+    };
+    auto pick_wave = [&](uint32_t excl) {
+        std::vector<int> cand;
+        for (int b = 0; b < k; ++b)
+            if (!((excl >> b) & 1u))
+                cand.push_back(b);
+        std::sort(cand.begin(), cand.end(),
+                  [&](int a, int b) { return wave_rank(a) < wave_rank(b); });
+        std::vector<int> w(cand.begin(), cand.begin() + std::min<int>(wb, (int)cand.size()));
+        std::sort(w.begin(), w.end());
+        return w;
+    };
+    auto bits_of = [](const std::vector<int> &v) {
+        uint32_t m = 0;
+        for (int b : v)
+            m |= 1u << b;
+        return m;
+    };
+    const std::vector<int> W0 = pick_wave(0u);
+    // register set of size rbits containing S and avoiding W (and, if it can,
+    // the low bits the load/store layout needs on lanes)
+    auto pad = [&](uint32_t S, uint32_t W) {
         std::vector<int> regs;
         for (int b = 0; b < k; ++b)
             if ((S >> b) & 1u)
                 regs.push_back(b);
-        for (int b = k - 1; b >= 0 && (int)regs.size() < rbits; --b)
-            if (!((S >> b) & 1u) && !((io_forbid >> b) & 1u))
-                regs.push_back(b), S |= 1u << b;
-        for (int b = k - 1; b >= 0 && (int)regs.size() < rbits; --b)
-            if (!((S >> b) & 1u))
-                regs.push_back(b), S |= 1u << b;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int b = k - 1; b >= 0 && (int)regs.size() < rbits; --b) {
+                const uint32_t bit = 1u << b;
+                if ((S & bit) || (W & bit) || (pass == 0 && (io_forbid & bit)))
+                    continue;
+                regs.push_back(b);
+                S |= bit;
+            }
         std::sort(regs.begin(), regs.end());
         return regs;
     };
-    auto io_regs = [&]() {
-        std::vector<int> regs;
-        for (int b = k - rbits; b < k; ++b)
-            regs.push_back(b);
-        return regs;
+    auto layout_for = [&](uint32_t S) {
+        HostPhase ph;
+        ph.wave = (S & bits_of(W0)) ? pick_wave(S) : W0;
+        ph.regs = pad(S, bits_of(ph.wave));
+        return ph;
     };
-    auto io_ok = [&](const std::vector<int> &regs) {
-        for (int b : regs)
+    auto io_ok = [&](const HostPhase &ph) {
+        for (int b : ph.regs)
             if ((io_forbid >> b) & 1u)
                 return false;
         return true;
+    };
+    auto io_phase = [&](const std::vector<int> &wave, int at) {
+        HostPhase io;
+        io.wave = wave;
+        io.regs = pad(0u, bits_of(wave));
+        io.op_begin = io.op_end = at;
+        return io;
     };
 
     std::vector<HostPhase> phases;
@@ -447,8 +493,7 @@ void plan_phases(HostPass &p)
             if (cl.hops > best.hops || (cl.hops == best.hops && cl.inc.size() > best.inc.size()))
                 best = cl;
         }
-        HostPhase ph;
-        ph.regs = pad(best.S);
+        HostPhase ph = layout_for(best.S);
         ph.op_begin = (int)ordered.size();
         for (int i : best.inc) {
             ordered.push_back(p.ops[i]);
@@ -456,23 +501,18 @@ void plan_phases(HostPass &p)
             --left;
         }
         ph.op_end = (int)ordered.size();
-        // a phase whose register set equals the previous one's extends it
-        if (!phases.empty() && phases.back().regs == ph.regs)
+        // a phase with the previous one's layout extends it
+        if (!phases.empty() && phases.back().regs == ph.regs && phases.back().wave == ph.wave)
             phases.back().op_end = ph.op_end;
         else
             phases.push_back(ph);
     }
-    if (phases.empty() || !io_ok(phases.front().regs)) {
-        HostPhase io;
-        io.regs = io_regs();
-        phases.insert(phases.begin(), io);
-    }
-    if (!io_ok(phases.back().regs)) {
-        HostPhase io;
-        io.regs = io_regs();
-        io.op_begin = io.op_end = (int)ordered.size();
-        phases.push_back(io);
-    }
+    if (phases.empty() || !io_ok(phases.front()))
+        phases.insert(phases.begin(), io_phase(phases.empty() ? W0 : phases.front().wave, 0));
+    // the store layout must be load-compatible and keep the load layout's
+    // wave bits, so that consecutive tiles never share LDS slots across waves
+    if (!io_ok(phases.back()) || phases.back().wave != phases.front().wave)
+        phases.push_back(io_phase(phases.front().wave, (int)ordered.size()));
     p.ops.swap(ordered);
     p.phases.swap(phases);
 }

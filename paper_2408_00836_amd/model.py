@@ -8,6 +8,8 @@ come from torch, every step of the path runs in the library's kernels.
 """
 from __future__ import annotations
 
+import sys
+
 import numpy as np
 import torch
 
@@ -45,7 +47,9 @@ class Hubbard:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        # at interpreter exit the process releases the device tables itself,
+        # and module globals this path needs may already be gone
+        if h and not sys.is_finalizing():
             try:
                 torch.cuda.synchronize()
             except Exception:
