@@ -28,6 +28,65 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    """sha256 over the HIP sources, plan and headers the pass kernels come from."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2408_00836_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".cpp", ".hpp")):
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a
+    plain copy), or None when no summary exists or the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_pass_4x4_32q.md")
+    try:
+        with open(path) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ln.startswith("- ") and ": " in ln:
+            k, v = ln[2:].split(": ", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if kv.get("source_sha256") != kernel_source_hash() or kv.get("workload") != workload:
+        return None
+    val = kv.get(f"traffic_bytes_per_launch {kernel}")
+    return float(val) if val else None
+
+
+def copy_reference(torch, dev, gib=8, reps=3):
+    """Bandwidth of a plain device copy (torch elementwise kernel, `gib` GiB
+    read + `gib` GiB written): the practical HBM ceiling for an in-place
+    read-modify-write stream on this GPU, and the calibration launch for the
+    FETCH_SIZE/WRITE_SIZE counters."""
+    n = (gib << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        torch.mul(src, 1.0, out=dst)
+        b.record(s)
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": 2.0 * (gib << 30), "ms": best,
+            "GBs": 2.0 * (gib << 30) / (best * 1e-3) / 1e9,
+            "kernel": "torch mul(src, 1.0, out=dst), float64"}
+
+
 def pick_workload(name):
     from paper_2408_00836_amd import workloads as W
     return {"c5": W.config5, "c3": W.config3, "c2": lambda: W.config2(4.0),
@@ -113,6 +172,8 @@ def main():
         log(f"[bench] warmup {i + 1}/{args.warmup} E={E.item():.12f}")
 
     fwd_ms = ham_ms = rev_ms = 0.0
+    # per kernel mode: [summed launch ms, launches] over the timed steps
+    kt = {mode: [0.0, 0] for mode in abi.KERNEL_MODES}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -121,6 +182,10 @@ def main():
         fwd_ms += f
         ham_ms += h_
         rev_ms += r
+        for mode, code in abi.KERNEL_MODES.items():
+            ms, cnt = abi.hubbard_kernel_ms(m.handle, code)
+            kt[mode][0] += ms
+            kt[mode][1] += cnt
         log(f"[bench] step {i + 1}/{args.steps}: fwd {f:.1f} ms, H {h_:.1f} ms, rev {r:.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -128,15 +193,24 @@ def main():
     evals_per_s = 1.0 / sec
     E_val = E.item()
 
-    # per-launch averages and algorithmic bytes
-    fwd_avg = fwd_ms / (args.steps * max(n_fwd, 1))
-    rev_avg = rev_ms / (args.steps * max(n_rev, 1))
-    fwd_gbs = 32.0 * dim / (fwd_avg * 1e-3) / 1e9
-    rev_gbs = 64.0 * dim / (rev_avg * 1e-3) / 1e9
-    if rev_ms >= fwd_ms:
-        dom = dict(kernel="k_reverse", bytes=64.0 * dim, ms=rev_avg, gbs=rev_gbs)
-    else:
-        dom = dict(kernel="k_forward", bytes=32.0 * dim, ms=fwd_avg, gbs=fwd_gbs)
+    # per-launch averages (events around each launch, on the launch stream)
+    # and algorithmic bytes: a forward pass reads and writes psi once, a
+    # reverse pass psi and lambda
+    gen = "true" if w.general else "false"   # the diagonal's kernel variant
+    vec = 16.0 * dim
+    kernels = {}
+    # the first H pass reads psi and writes phi, later ones also read phi
+    ham_vec = (2.0 + 3.0 * (n_ham - 1)) / max(n_ham, 1)
+    for mode, nvec in (("forward", 2), ("reverse", 4), ("hamiltonian", ham_vec)):
+        tot, cnt = kt[mode]
+        if cnt == 0:
+            continue
+        avg = tot / cnt
+        kernels[mode] = {"kernel": f"hv::k_pass<{abi.KERNEL_MODES[mode]}, {gen}>",
+                         "avg_ms": avg, "launches_per_step": cnt // args.steps,
+                         "bytes_per_launch": nvec * vec,
+                         "GBs": nvec * vec / (avg * 1e-3) / 1e9}
+    dom = max(kernels.values(), key=lambda k: k["avg_ms"] * k["launches_per_step"])
 
     # H|psi>: matrix-free application into the lambda buffer
     psi, lam = m.workspace_views(L)
@@ -168,6 +242,9 @@ def main():
               "note": "central FD h=1e-5: 2P+1 energy evaluations per gradient, each timed "
                       "as one energy() call (forward passes + expectation passes)"}
 
+    copy = copy_reference(torch, dev)
+    log(f"[bench] plain copy: {copy['GBs']:.0f} GB/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (bounded sample)")
@@ -190,15 +267,14 @@ def main():
                    "periodic": [w.periodic_x, w.periodic_y], "U": w.U, "qubits": n,
                    "layers": L, "params": P, "passes": {"fwd": n_fwd, "ham": n_ham,
                                                         "rev": n_rev, "exp": n_exp}},
-        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["gbs"],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["gbs"] / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_ms": dom["ms"],
-                     "bytes_per_launch": dom["bytes"]},
-        "kernels": {"k_forward": {"avg_ms": fwd_avg, "GBs": fwd_gbs, "launches_per_step": n_fwd},
-                    "k_reverse": {"avg_ms": rev_avg, "GBs": rev_gbs, "launches_per_step": n_rev},
-                    "phase_ms_per_step": {"forward": fwd_ms / args.steps,
-                                          "hamiltonian": ham_ms / args.steps,
-                                          "reverse": rev_ms / args.steps}},
+        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["GBs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GBs"] / HBM_PEAK_GBS,
+                     "traffic": traffic_bytes(dom["kernel"], w.name),
+                     "avg_launch_ms": dom["avg_ms"], "bytes_per_launch": dom["bytes_per_launch"]},
+        "kernels": dict(kernels, phase_ms_per_step={"forward": fwd_ms / args.steps,
+                                                    "hamiltonian": ham_ms / args.steps,
+                                                    "reverse": rev_ms / args.steps}),
+        "copy_reference": copy,
         "hpsi": {"ms": h_ms, "algorithmic_GBs": h_gbs, "frac": h_gbs / HBM_PEAK_GBS,
                  "passes": n_ham},
         "fd_plain": fd,

@@ -58,6 +58,15 @@ hubbard_status hubbard_tune(hubbard_t h, int32_t n_layers, const double *theta_d
 hubbard_status hubbard_set_timing(hubbard_t h, int32_t enable);
 hubbard_status hubbard_phase_ms(hubbard_t h, float *fwd_ms, float *ham_ms, float *rev_ms);
 
+/* Per-launch timing of the pass kernel.  With timing enabled, every launch of
+ * the pass kernel is bracketed by its own pair of events; this call waits for
+ * them and returns, for the most recent call, the summed duration in
+ * milliseconds and the number of launches of one kernel mode:
+ *   mode 0 forward (gate application), 1 reverse (adjoint sweep),
+ *        2 H|psi>, 3 expectation value.
+ * A mode the call did not launch gives 0 ms and 0 launches. */
+hubbard_status hubbard_kernel_ms(hubbard_t h, int32_t mode, float *total_ms, int32_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,7 @@ EXPORTED = [
     "hubbard_last_error", "hubbard_workspace_size", "hubbard_init_neel",
     "ansatz_apply", "hamiltonian_apply", "energy", "energy_grad",
     "hubbard_plan_dump", "hubbard_set_tiles", "hubbard_set_timing", "hubbard_phase_ms",
+    "hubbard_kernel_ms",
     "hubbard_batch_workspace_size", "energy_grad_batch", "hubbard_get_tiles", "hubbard_tune",
 ]
 
@@ -89,6 +90,7 @@ def lib() -> ctypes.CDLL:
                                    vp], st),
             "hubbard_phase_ms": ([vp, P(ctypes.c_float), P(ctypes.c_float),
                                   P(ctypes.c_float)], st),
+            "hubbard_kernel_ms": ([vp, i32, P(ctypes.c_float), P(i32)], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -221,6 +223,16 @@ def hubbard_phase_ms(h: int):
     a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
     _check(lib().hubbard_phase_ms(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+KERNEL_MODES = {"forward": 0, "reverse": 1, "hamiltonian": 2, "expectation": 3}
+
+
+def hubbard_kernel_ms(h: int, mode: int):
+    """(summed milliseconds, launches) of one pass-kernel mode in the last call."""
+    ms, n = ctypes.c_float(), ctypes.c_int32()
+    _check(lib().hubbard_kernel_ms(h, int(mode), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def _handles(hs):

@@ -103,6 +103,10 @@ struct hubbard_model {
     bool ev_ready = false;
     hipEvent_t ev[4];
     int ev_used = 0;
+    // per-launch timing of the pass kernels: event pairs around each launch
+    // of the last call, and the kernel mode of each
+    std::vector<hipEvent_t> kev;
+    std::vector<int> kmode;
 };
 
 namespace {
@@ -524,11 +528,38 @@ hubbard_status check_launch(const char *what)
     return HUBBARD_OK;
 }
 
+// Timing mode: an event pair around one launch (events are created on first
+// use and reused by later calls).
+bool launch_mark(hubbard_model *h, int mode, hipStream_t s, bool end)
+{
+    if (!h || !h->timing)
+        return false;
+    const size_t i = end ? 2 * h->kmode.size() - 1 : 2 * h->kmode.size();
+    if (!end) {
+        if (h->kev.size() < i + 2) {
+            hipEvent_t e0, e1;
+            if (hipEventCreate(&e0) != hipSuccess)
+                return false;
+            if (hipEventCreate(&e1) != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                return false;
+            }
+            h->kev.push_back(e0);
+            h->kev.push_back(e1);
+        }
+        h->kmode.push_back(mode);
+    }
+    (void)hipEventRecord(h->kev[i], s);
+    return true;
+}
+
 template <int MODE>
 void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, const double *theta,
-                 const double2 *a, const double2 *b, double *partial, hipStream_t s)
+                 const double2 *a, const double2 *b, double *partial, hipStream_t s,
+                 hubbard_model *h)
 {
     for (size_t i = 0; i < pl.pass.size(); ++i) {
+        const bool timed = launch_mark(h, MODE, s, false);
         if (pr.general)
             hipLaunchKernelGGL((k_pass<MODE, true>), dim3(pl.grid[i]), dim3(pl.threads[i]),
                                pl.smem[i], s, pl.pass[i], pr.d_phases, pr.d_ops, pr.d_vb, theta,
@@ -537,20 +568,22 @@ void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, c
             hipLaunchKernelGGL((k_pass<MODE, false>), dim3(pl.grid[i]), dim3(pl.threads[i]),
                                pl.smem[i], s, pl.pass[i], pr.d_phases, pr.d_ops, pr.d_vb, theta,
                                ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax);
+        if (timed)
+            launch_mark(h, MODE, s, true);
     }
 }
 
 hubbard_status run_forward(const Program &pr, const DeviceState &ds, const double *theta,
-                           double2 *psi, hipStream_t s)
+                           double2 *psi, hipStream_t s, hubbard_model *h = nullptr)
 {
-    launch_list<M_FWD>(pr, ds, pr.fwd, theta, psi, nullptr, nullptr, s);
+    launch_list<M_FWD>(pr, ds, pr.fwd, theta, psi, nullptr, nullptr, s, h);
     return check_launch("forward pass");
 }
 
 hubbard_status run_ham(const Program &pr, const DeviceState &ds, const double2 *psi, double2 *phi,
-                       double *partial, hipStream_t s)
+                       double *partial, hipStream_t s, hubbard_model *h = nullptr)
 {
-    launch_list<M_HAM>(pr, ds, pr.ham, nullptr, psi, phi, partial, s);
+    launch_list<M_HAM>(pr, ds, pr.ham, nullptr, psi, phi, partial, s, h);
     return check_launch("hamiltonian pass");
 }
 
@@ -766,6 +799,8 @@ void hubbard_destroy(hubbard_t h)
     if (h->ev_ready)
         for (int j = 0; j < 4; ++j)
             (void)hipEventDestroy(h->ev[j]);
+    for (hipEvent_t e : h->kev)
+        (void)hipEventDestroy(e);
     for (auto &kv : h->dev) {
         (void)hipSetDevice(kv.first);
         kv.second.progs.clear();
@@ -851,8 +886,9 @@ hubbard_status ansatz_apply(hubbard_t h, const double *theta_dev, int32_t n_laye
     if (st != HUBBARD_OK)
         return st;
     h->ev_used = 0;
+    h->kmode.clear();
     mark(h, 0, (hipStream_t)stream);
-    st = run_forward(*pr, *ds, theta_dev, (double2 *)psi_dev, (hipStream_t)stream);
+    st = run_forward(*pr, *ds, theta_dev, (double2 *)psi_dev, (hipStream_t)stream, h);
     mark(h, 1, (hipStream_t)stream);
     return st;
 }
@@ -871,9 +907,10 @@ hubbard_status hamiltonian_apply(hubbard_t h, const void *psi_dev, void *out_dev
     if (st != HUBBARD_OK)
         return st;
     h->ev_used = 0;
+    h->kmode.clear();
     mark(h, 1, (hipStream_t)stream);
     st = run_ham(*pr, *ds, (const double2 *)psi_dev, (double2 *)out_dev, nullptr,
-                 (hipStream_t)stream);
+                 (hipStream_t)stream, h);
     mark(h, 2, (hipStream_t)stream);
     return st;
 }
@@ -897,11 +934,12 @@ hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers, do
     if ((st = run_init(h, psi, s)) != HUBBARD_OK)
         return st;
     h->ev_used = 0;
+    h->kmode.clear();
     mark(h, 0, s);
-    if ((st = run_forward(*pr, *ds, theta_dev, psi, s)) != HUBBARD_OK)
+    if ((st = run_forward(*pr, *ds, theta_dev, psi, s, h)) != HUBBARD_OK)
         return st;
     mark(h, 1, s);
-    launch_list<M_EXP>(*pr, *ds, pr->exp, nullptr, psi, nullptr, partial, s);
+    launch_list<M_EXP>(*pr, *ds, pr->exp, nullptr, psi, nullptr, partial, s, h);
     if ((st = check_launch("expectation pass")) != HUBBARD_OK)
         return st;
     mark(h, 2, s);
@@ -928,14 +966,15 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
     if ((st = run_init(h, psi, s)) != HUBBARD_OK)
         return st;
     h->ev_used = 0;
+    h->kmode.clear();
     mark(h, 0, s);
-    if ((st = run_forward(*pr, *ds, theta_dev, psi, s)) != HUBBARD_OK)
+    if ((st = run_forward(*pr, *ds, theta_dev, psi, s, h)) != HUBBARD_OK)
         return st;
     mark(h, 1, s);
-    if ((st = run_ham(*pr, *ds, psi, lam, partial, s)) != HUBBARD_OK)
+    if ((st = run_ham(*pr, *ds, psi, lam, partial, s, h)) != HUBBARD_OK)
         return st;
     mark(h, 2, s);
-    launch_list<M_REV>(*pr, *ds, pr->rev, theta_dev, psi, lam, partial, s);
+    launch_list<M_REV>(*pr, *ds, pr->rev, theta_dev, psi, lam, partial, s, h);
     if ((st = check_launch("reverse pass")) != HUBBARD_OK)
         return st;
     mark(h, 3, s);
@@ -1182,6 +1221,27 @@ hubbard_status hubbard_phase_ms(hubbard_t h, float *fwd_ms, float *ham_ms, float
     if (st == HUBBARD_OK)
         st = span(2, 3, rev_ms);
     return st;
+}
+
+hubbard_status hubbard_kernel_ms(hubbard_t h, int32_t mode, float *total_ms, int32_t *launches)
+{
+    if (!h || !total_ms || !launches || mode < 0 || mode > 3)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_kernel_ms");
+    *total_ms = 0.0f;
+    *launches = 0;
+    for (size_t i = 0; i < h->kmode.size(); ++i) {
+        if (h->kmode[i] != mode)
+            continue;
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(h->kev[2 * i + 1]);
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, h->kev[2 * i], h->kev[2 * i + 1]);
+        if (e != hipSuccess)
+            return fail(HUBBARD_ERR_DEVICE, std::string("event timing: ") + hipGetErrorString(e));
+        *total_ms += ms;
+        ++*launches;
+    }
+    return HUBBARD_OK;
 }
 
 }  // extern "C"

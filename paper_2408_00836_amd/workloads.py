@@ -50,6 +50,11 @@ class Workload:
     def n_params(self) -> int:
         return self.layers * self.params_per_layer
 
+    @property
+    def general(self) -> bool:
+        """True when the diagonal holds V or eps terms besides U."""
+        return any(a is not None and bool(np.any(np.asarray(a) != 0)) for a in (self.V, self.eps))
+
     def kwargs(self) -> dict:
         """Keyword arguments shared by the GPU model and the oracle model."""
         return dict(periodic_x=self.periodic_x, periodic_y=self.periodic_y, t=self.t,
