@@ -18,7 +18,7 @@
 #include "hubvqe.hpp"
 
 namespace hv {
-template <int MODE, bool GEN>
+template <int MODE, bool GEN, bool FULL>
 __global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,
                        const DevModel *, double2 *, double2 *, double *, int);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t);
@@ -143,11 +143,9 @@ struct Builder {
                     P.hi_mask |= 1u << hp.tile[j];
             }
             int nf = 0;
-            std::vector<int> free_pos;
             for (int b = 0; b < n; ++b)
                 if (!(S & (1u << b))) {
                     P.free_mask |= 1u << b;
-                    free_pos.push_back(b);
                     ++nf;
                 }
             P.nfree = nf;
@@ -194,15 +192,11 @@ struct Builder {
                     }
                     op_pl.push_back(pl);
                     op_ql.push_back(ql);
-                    uint32_t bl = 0, bf = 0;
-                    for (int j = 0; j < P.k; ++j)
-                        if (hp.tile[j] > h.p && hp.tile[j] < h.q)
-                            bl |= 1u << j;
-                    for (int f = 0; f < nf; ++f)
-                        if (free_pos[f] > h.p && free_pos[f] < h.q)
-                            bf |= 1u << f;
-                    o.bm_local = bl;
-                    o.bm_free = bf;
+                    const int lo = std::min(h.p, h.q), hi = std::max(h.p, h.q);
+                    uint32_t bw = 0;
+                    for (int b = lo + 1; b < hi; ++b)
+                        bw |= 1u << b;
+                    o.between = bw;
                     o.t = h.t;
                 } else {
                     op_pl.push_back(-1);
@@ -256,21 +250,23 @@ struct Builder {
                               ? 1u
                               : 0u;
                 D.valid = 0;
-                for (int j = 0; j < kRegs; ++j) {
-                    uint32_t lo = 0, go = 0;
-                    bool ok = true;
-                    for (int i = 0; i < kRegBits; ++i) {
-                        if (!((j >> i) & 1))
-                            continue;
-                        if (i >= (int)hph.regs.size()) {
-                            ok = false;   // phantom register bit of a tile < 16
-                            continue;
-                        }
-                        lo |= 1u << hph.regs[i];
-                        go |= 1u << hp.tile[hph.regs[i]];
+                for (int i = 0; i < kRegBits; ++i) {
+                    if (i < (int)hph.regs.size()) {
+                        D.gb[i] = 1u << hp.tile[hph.regs[i]];
+                        D.sb[i] = slot(1u << hph.regs[i]) << 4;
+                    } else {
+                        D.gb[i] = D.sb[i] = 0;   // phantom register bit of a tile < 16
                     }
-                    D.roff[j] = lo;
-                    D.goff[j] = go;
+                }
+                std::vector<uint32_t> goff(kRegs, 0);
+                for (int j = 0; j < kRegs; ++j) {
+                    bool ok = true;
+                    for (int i = 0; i < kRegBits; ++i)
+                        if ((j >> i) & 1) {
+                            if (i >= (int)hph.regs.size())
+                                ok = false;
+                            goff[j] |= D.gb[i];
+                        }
                     if (ok)
                         D.valid |= 1u << j;
                 }
@@ -294,7 +290,7 @@ struct Builder {
                     op.pair = pair_of[a][b];
                     op.flip = 0;
                     for (int j = 0; j < kRegs; ++j)
-                        if (__builtin_popcount(D.roff[j] & op.bm_local) & 1)
+                        if (__builtin_popcount(goff[j] & op.between) & 1)
                             op.flip |= 1u << j;
                 }
                 phases.push_back(D);
@@ -325,7 +321,7 @@ void set_smem(PassList &pl, bool force_red1)
     for (size_t i = 0; i < pl.pass.size(); ++i) {
         const DevPass &P = pl.pass[i];
         int nred = force_red1 ? 1 : P.n_red;
-        pl.smem[i] = (int)smem_plan(P.k, P.c, P.n_ops, P.n_diag, nred, pl.threads[i],
+        pl.smem[i] = (int)smem_plan(P.k, P.n_ops, P.n_diag, nred, P.n_phases, pl.threads[i],
                                     P.nfree == 0)
                          .total;
     }
@@ -453,10 +449,14 @@ hubbard_status ensure_model(hubbard_model *h, int dev, DeviceState &ds)
     std::call_once(attr_once, [] {
         int lim = max_smem_per_block();
         const void *fns[] = {
-            (const void *)k_pass<M_FWD, false>, (const void *)k_pass<M_REV, false>,
-            (const void *)k_pass<M_HAM, false>, (const void *)k_pass<M_EXP, false>,
-            (const void *)k_pass<M_FWD, true>,  (const void *)k_pass<M_REV, true>,
-            (const void *)k_pass<M_HAM, true>,  (const void *)k_pass<M_EXP, true>};
+            (const void *)k_pass<M_FWD, false, true>,  (const void *)k_pass<M_REV, false, true>,
+            (const void *)k_pass<M_HAM, false, true>,  (const void *)k_pass<M_EXP, false, true>,
+            (const void *)k_pass<M_FWD, true, true>,   (const void *)k_pass<M_REV, true, true>,
+            (const void *)k_pass<M_HAM, true, true>,   (const void *)k_pass<M_EXP, true, true>,
+            (const void *)k_pass<M_FWD, false, false>, (const void *)k_pass<M_REV, false, false>,
+            (const void *)k_pass<M_HAM, false, false>, (const void *)k_pass<M_EXP, false, false>,
+            (const void *)k_pass<M_FWD, true, false>,  (const void *)k_pass<M_REV, true, false>,
+            (const void *)k_pass<M_HAM, true, false>,  (const void *)k_pass<M_EXP, true, false>};
         for (const void *f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     });
@@ -560,14 +560,24 @@ void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, c
 {
     for (size_t i = 0; i < pl.pass.size(); ++i) {
         const bool timed = launch_mark(h, MODE, s, false);
-        if (pr.general)
-            hipLaunchKernelGGL((k_pass<MODE, true>), dim3(pl.grid[i]), dim3(pl.threads[i]),
-                               pl.smem[i], s, pl.pass[i], pr.d_phases, pr.d_ops, pr.d_vb, theta,
-                               ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax);
-        else
-            hipLaunchKernelGGL((k_pass<MODE, false>), dim3(pl.grid[i]), dim3(pl.threads[i]),
-                               pl.smem[i], s, pl.pass[i], pr.d_phases, pr.d_ops, pr.d_vb, theta,
-                               ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax);
+        // tiles of >= 16 amplitudes fill every register of every thread
+        const bool full = pl.pass[i].k >= kRegBits;
+#define HV_LAUNCH(GEN, FULL)                                                                    \
+    hipLaunchKernelGGL((k_pass<MODE, GEN, FULL>), dim3(pl.grid[i]), dim3(pl.threads[i]),        \
+                       pl.smem[i], s, pl.pass[i], pr.d_phases, pr.d_ops, pr.d_vb, theta,        \
+                       ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax)
+        if (pr.general) {
+            if (full)
+                HV_LAUNCH(true, true);
+            else
+                HV_LAUNCH(true, false);
+        } else {
+            if (full)
+                HV_LAUNCH(false, true);
+            else
+                HV_LAUNCH(false, false);
+        }
+#undef HV_LAUNCH
         if (timed)
             launch_mark(h, MODE, s, true);
     }
@@ -725,7 +735,7 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
     int smem = 0;
     for (const DevPass &P : allp) {
         const int nred = P.n_red > 0 ? P.n_red : 1;
-        smem = std::max(smem, (int)smem_plan(P.k, P.c, P.n_ops, P.n_diag, nred, threads,
+        smem = std::max(smem, (int)smem_plan(P.k, P.n_ops, P.n_diag, nred, P.n_phases, threads,
                                              P.nfree == 0)
                                   .total);
     }

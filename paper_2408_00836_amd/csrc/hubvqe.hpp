@@ -34,41 +34,55 @@ enum PassFlags : int32_t {
     PF_HAM_LAST = 2,    // H pass: also reduce Re <psi|phi> into row 0
 };
 
-// One device operation inside a pass (64 bytes).
+// One device operation inside a pass (64 bytes).  The fields a hopping term
+// needs in the inner loop come first, so one 32-byte scalar load fetches them.
 struct DevOp {
     int32_t kind;
-    int32_t param;      // theta index (-1 for Hamiltonian terms)
+    int32_t pair;       // HOP: register-bit pair (0..5: 01 02 03 12 13 23) in its phase
+    uint32_t flip;      // HOP: bit j = parity of register j's global bits in `between`
+    uint32_t between;   // HOP: global bits strictly between p and q (Jordan-Wigner string)
     int32_t red;        // reduction row within the pass (-1: none)
     int32_t dtab;       // DIAG: index of its phase table within the pass
-    int32_t pair;       // HOP: register-bit pair (0..5: 01 02 03 12 13 23) in its phase
-    uint32_t flip;      // HOP: bit j = parity of register j's local bits in bm_local
-    uint32_t bm_local;  // HOP: Jordan-Wigner between-mask over tile-local bits
-    uint32_t bm_free;   // HOP: between-mask over the free (tile-index) bits
+    double t;           // HOP: bond hopping t_b
+    int32_t param;      // theta index (-1 for Hamiltonian terms)
     uint32_t umask;     // DIAG: spin-up qubits of the sites whose U term it carries
     uint32_t emask;     // DIAG: qubits whose eps term it carries
     int32_t v_begin;    // DIAG: V bonds [v_begin, v_end) of the plan's V table
     int32_t v_end;
-    double t;           // HOP: bond hopping t_b
-    double pad;
+    int32_t pad[3];
 };
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
 
-// Register layout of one phase of a pass.  Each thread holds 16 amplitudes of
-// the tile in registers: register j holds tile-local index tloc | roff[j],
-// where tloc deposits the lane id over lmask and the wave id over wmask, and roff[j]
-// deposits j over the phase's four register bits.  Gates of the phase act on
-// register bits only; between phases the tile is re-laid out through LDS.
+// LDS slot of tile-local index l in the exchange buffer: the low four bits
+// are XORed with a fold of the higher bits so that the 16-byte slots a wave
+// touches in one access spread over the banks.  Linear over GF(2), hence a
+// bijection on [0, 2^k), and slot(a ^ b) = slot(a) ^ slot(b).
+__host__ __device__ inline uint32_t slot(uint32_t l)
+{
+    return l ^ (((l >> 4) ^ (l >> 8)) & 15u);
+}
+
+// Register layout of one phase of a pass (64 bytes).  Each thread holds 16
+// amplitudes of the tile in registers: register j holds tile-local index
+// tloc | pdep(j, register bits), where tloc deposits the lane id over lmask
+// and the wave id over wmask.  Because the deposit and slot() are linear,
+// register j's global-index bits are the OR of gb[i] over the set bits i of
+// j, and its LDS byte offset is slot(tloc) * 16 XOR the XOR of sb[i].  Gates
+// of the phase act on register bits only; between phases the tile is
+// re-laid out through LDS.
 constexpr int kRegs = 16;
 constexpr int kRegBits = 4;
 struct DevPhase {
-    int32_t op_begin, op_end;   // ops of this phase (absolute indices)
-    uint32_t roff[kRegs];       // tile-local bits of register j
-    uint32_t goff[kRegs];       // global index bits of register j
+    int32_t op_begin, op_end;   // ops of this phase (pass-relative indices)
+    uint32_t gb[kRegBits];      // global index bit of register bit i (0: phantom bit)
+    uint32_t sb[kRegBits];      // slot(tile-local bit of register bit i) * 16
     uint32_t lmask;             // tile-local bits that carry the lane id (ascending)
     uint32_t wmask;             // tile-local bits that carry the wave id (ascending)
     uint32_t valid;             // bit j: register j holds an amplitude (tiles < 16)
     uint32_t cross;             // 1: entering this phase moves data between waves
+    int32_t pad[2];
 };
+static_assert(sizeof(DevPhase) == 64, "DevPhase layout");
 
 // A V bond as the device reads it: qubits (i up, i dn, j up, j dn) and V_b.
 struct DevVBond {
@@ -125,29 +139,41 @@ struct DevModel {
 };
 
 // LDS carve-up shared by host (launch size) and device: one tile-sized
-// exchange buffer, the tile's global-offset table, per-op rotation
-// coefficients, diagonal phase tables and reduction rows.
+// exchange buffer, per-phase lane and wave tables (global bits and LDS byte
+// offset of each lane's and each wave's part of the tile-local index),
+// per-op rotation coefficients, diagonal phase tables and reduction rows.
+constexpr int kMaxWaves = 8;   // 512 threads
 struct SmemPlan {
-    uint32_t xbuf, offs, opc, dtab, red, total;
+    uint32_t xbuf, ltab, wtab, opc, dtab, red, rows, total;
 };
 
-// Reduction rows: a pass over many tiles keeps one accumulator per thread
-// and row; a single-tile pass reduces every op at once into one value per row.
-__host__ __device__ inline SmemPlan smem_plan(int k, int c, int n_ops, int n_diag, int n_red,
-                                              int threads, bool single_tile)
+// Reduction rows: a pass over many tiles keeps one accumulator per row and
+// group of four lanes (the four are summed in registers first; one per
+// thread below four threads); a single-tile pass reduces every op at once
+// into one value per row.
+__host__ __device__ inline uint32_t red_rows_per(int threads, bool single_tile)
+{
+    return single_tile ? 1u : (threads >= 4 ? (uint32_t)threads / 4u : (uint32_t)threads);
+}
+
+__host__ __device__ inline SmemPlan smem_plan(int k, int n_ops, int n_diag, int n_red,
+                                              int n_phases, int threads, bool single_tile)
 {
     SmemPlan s;
     uint32_t at = 0;
     s.xbuf = at;
     at += (1u << k) * 16u;
-    s.offs = at;
-    at += ((1u << (k - c)) * 4u + 15u) & ~15u;
+    s.ltab = at;
+    at += (uint32_t)n_phases * 64u * 8u;
+    s.wtab = at;
+    at += (uint32_t)n_phases * kMaxWaves * 8u;
     s.opc = at;
     at += (uint32_t)n_ops * 16u;
     s.dtab = at;
     at += (uint32_t)n_diag * kDiagTab * 16u;
     s.red = at;
-    at += (uint32_t)n_red * (single_tile ? 1u : (uint32_t)threads) * 8u;
+    s.rows = red_rows_per(threads, single_tile);
+    at += (uint32_t)n_red * s.rows * 8u;
     at += 16u * 8u;   // per-wave partial sums
     s.total = at;
     return s;

@@ -44,21 +44,6 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t x, uint32_t mask)
     return r;
 }
 
-// LDS slot of tile-local index l: the low four bits are XORed with a fold of
-// the higher bits so that lanes whose indices differ only in high bits land
-// in different banks.  A bijection on [0, 2^k).
-__device__ __forceinline__ uint32_t slot(uint32_t l)
-{
-    return l ^ (((l >> 4) ^ (l >> 8)) & 15u);
-}
-
-// Tile-local index bits of this thread: the lane id deposited over lmask and
-// the wave id over wmask (masks are wave-uniform: scalar loops).
-__device__ __forceinline__ uint32_t thread_local_index(uint32_t lmask, uint32_t wmask, int tid)
-{
-    return pdep32((uint32_t)(tid & 63), lmask) | pdep32((uint32_t)(tid >> 6), wmask);
-}
-
 // Diagonal sub-term value D_sub(g); GEN: the model has eps or V terms.
 template <bool GEN>
 __device__ __forceinline__ double diag_value(const DevOp &op, uint32_t g, const DevModel *M,
@@ -175,38 +160,90 @@ __device__ __forceinline__ void hop_regs(int pair, double2 (&v)[NV][kRegs], Pair
     }
 }
 
-// Re-lay the tile out from one phase's register layout to the next through
-// LDS.  slot() is linear over GF(2) and a thread's local bits never overlap
-// a register's, so slot(tl | roff) = slot(tl) ^ slot(roff): one vector XOR
-// per register, the register part computed on the scalar unit.
-// If the wave bits stay fixed (cross == 0) every wave reads back exactly the
-// slots it wrote, in program order, so no workgroup barrier is needed; every
-// LDS slot a wave touches between cross-wave exchanges is its own.
-template <int NV>
-__device__ __forceinline__ void relayout(double2 (&v)[NV][kRegs], char *xbuf, uint32_t tl_from,
-                                         const DevPhase &from, uint32_t tl_to,
-                                         const DevPhase &to, uint32_t valid)
+// Register part of a phase's layout, held in scalar registers: goff(j) is
+// register j's global-index bits, roff(j) its LDS byte offset relative to
+// the thread's slot.  Both are linear in the bits of j (see DevPhase).
+struct RegLayout {
+    uint32_t gb[kRegBits], sb[kRegBits];
+    __device__ __forceinline__ uint32_t goff(int j) const
+    {
+        uint32_t r = 0;
+#pragma unroll
+        for (int i = 0; i < kRegBits; ++i)
+            if ((j >> i) & 1)
+                r |= gb[i];
+        return r;
+    }
+    __device__ __forceinline__ uint32_t roff(int j) const
+    {
+        uint32_t r = 0;
+#pragma unroll
+        for (int i = 0; i < kRegBits; ++i)
+            if ((j >> i) & 1)
+                r ^= sb[i];
+        return r;
+    }
+};
+
+__device__ __forceinline__ RegLayout reg_layout(const DevPhase &ph)
 {
-    const uint32_t xf = slot(tl_from) << 4, xt = slot(tl_to) << 4;
-    const bool cross = to.cross != 0;
+    RegLayout r;
+#pragma unroll
+    for (int i = 0; i < kRegBits; ++i) {
+        r.gb[i] = ph.gb[i];
+        r.sb[i] = ph.sb[i];
+    }
+    return r;
+}
+
+// Re-lay the tile out from one phase's register layout to the next through
+// LDS: every register goes to the slot of its tile-local index and comes
+// back from the slot of its new one.  xf/xt are the thread's slot byte
+// offsets in the old and new layouts.
+// If the wave bits stay fixed (cross == false) every wave reads back exactly
+// the slots it wrote, in program order, so no workgroup barrier is needed;
+// every LDS slot a wave touches between cross-wave exchanges is its own.
+template <int NV, bool FULL>
+__device__ __forceinline__ void relayout(double2 (&v)[NV][kRegs], char *xbuf, uint32_t xf,
+                                         const RegLayout &from, uint32_t xt, const RegLayout &to,
+                                         bool cross, uint32_t valid)
+{
 #pragma unroll
     for (int w = 0; w < NV; ++w) {
         if (cross && w > 0)
             __syncthreads();   // the previous vector's reads are done everywhere
 #pragma unroll
         for (int j = 0; j < kRegs; ++j)
-            if ((valid >> j) & 1u)
-                *(double2 *)(xbuf + (xf ^ (slot(from.roff[j]) << 4))) = v[w][j];
+            if (FULL || ((valid >> j) & 1u))
+                *(double2 *)(xbuf + (xf ^ from.roff(j))) = v[w][j];
         if (cross)
             __syncthreads();
         else
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int j = 0; j < kRegs; ++j)
-            if ((valid >> j) & 1u)
-                v[w][j] = *(const double2 *)(xbuf + (xt ^ (slot(to.roff[j]) << 4)));
+            if (FULL || ((valid >> j) & 1u))
+                v[w][j] = *(const double2 *)(xbuf + (xt ^ to.roff(j)));
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+// Sum of x over each aligned group of four lanes (the same value in every
+// lane of the group), by DPP quad permutations of the two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double y)
+{
+    const long long b = __double_as_longlong(y);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double quad_sum(double x)
+{
+    x += dpp_f64<0xB1>(x);   // quad_perm [1,0,3,2]: lane ^ 1
+    x += dpp_f64<0x4E>(x);   // quad_perm [2,3,0,1]: lane ^ 2
+    return x;
 }
 
 // Where a pass's reduction rows go: the partial array of the two-stage
@@ -237,7 +274,26 @@ __device__ __forceinline__ double block_sum(double x, double *wsum)
     return tot;
 }
 
-template <int MODE, bool GEN>
+// Global-index bits of a tile-local index x: tile bits 0..c-1 are global bits
+// 0..c-1, the others are deposited over hi_mask (the tile's bits, ascending).
+__device__ __forceinline__ uint32_t tile_global(uint32_t x, int c, uint32_t hi_mask)
+{
+    const uint32_t cmask = (1u << c) - 1u;
+    return pdep32(x >> c, hi_mask) | (x & cmask);
+}
+
+// Tile id -> its global bits, advanced by a fixed step: adding the deposited
+// step with every non-free bit set carries straight through those bits.
+__device__ __forceinline__ uint32_t tile_advance(uint32_t base, uint32_t step_dep,
+                                                 uint32_t free_mask)
+{
+    return (uint32_t)((((uint64_t)(base | ~free_mask)) + step_dep) & free_mask);
+}
+
+// One pass over the tiles [tile0, 2^nfree) with stride tstep.  FULL: all
+// threads own amplitudes and all 16 registers hold one (tiles of >= 16
+// amplitudes launched with exactly 2^tbits threads): no per-register guards.
+template <int MODE, bool GEN, bool FULL>
 __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__restrict__ phases,
                                          const DevOp *__restrict__ ops,
                                          const DevVBond *__restrict__ vb,
@@ -247,30 +303,40 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                                          uint64_t tstep, const Sink &sink)
 {
     constexpr int NV = (MODE == M_FWD || MODE == M_EXP) ? 1 : 2;
-    const int T = blockDim.x, tid = threadIdx.x;
+    const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // a batch workgroup may be wider than this pass's 2^tbits threads: the
     // extra threads keep zero registers and only join the barriers
-    const bool act = tid < (1 << P.tbits);
+    const bool act = FULL || tid < (1 << P.tbits);
     const bool ham_first = (MODE == M_HAM) && (P.flags & PF_HAM_FIRST);
     const bool ham_last = (MODE == M_HAM) && (P.flags & PF_HAM_LAST);
-    const int n_red = (MODE == M_REV) ? P.n_red : (MODE == M_EXP) ? 1 : P.n_red;
+    const int n_red = (MODE == M_EXP) ? 1 : P.n_red;
     const bool single = (P.nfree == 0);
-    const SmemPlan sp = smem_plan(P.k, P.c, P.n_ops, P.n_diag, n_red, T, single);
+    const SmemPlan sp = smem_plan(P.k, P.n_ops, P.n_diag, n_red, P.n_phases, T, single);
     char *xbuf = smem + sp.xbuf;
-    uint32_t *offs = (uint32_t *)(smem + sp.offs);
+    uint2 *ltab = (uint2 *)(smem + sp.ltab);
+    uint2 *wtab = (uint2 *)(smem + sp.wtab);
     double2 *opc = (double2 *)(smem + sp.opc);
     double2 *dtab = (double2 *)(smem + sp.dtab);
     double *red = (double *)(smem + sp.red);
+    const int R = (int)sp.rows;            // accumulators per reduction row
+    const bool quad = !single && T >= 4;   // rows hold sums over four lanes
 
-    // ---- per-workgroup set-up
+    const DevPhase *ph = phases + P.phase_begin;
+    // ---- per-workgroup set-up: lane and wave parts of every phase's
+    // tile-local index, as global bits and as LDS slot byte offsets
     const double sign = (MODE == M_REV) ? -1.0 : 1.0;
     {
-        const int nhi = P.k - P.c;
-        for (int i = tid; i < (1 << nhi); i += T)
-            offs[i] = pdep32((uint32_t)i, P.hi_mask);
+        for (int i = tid; i < P.n_phases * 64; i += T) {
+            const uint32_t lp = pdep32((uint32_t)(i & 63), ph[i >> 6].lmask);
+            ltab[i] = make_uint2(tile_global(lp, P.c, P.hi_mask), slot(lp) << 4);
+        }
+        for (int i = tid; i < P.n_phases * kMaxWaves; i += T) {
+            const uint32_t wp = pdep32((uint32_t)(i % kMaxWaves), ph[i / kMaxWaves].wmask);
+            wtab[i] = make_uint2(tile_global(wp, P.c, P.hi_mask), slot(wp) << 4);
+        }
         if constexpr (MODE == M_FWD || MODE == M_REV) {
             for (int o = tid; o < P.n_ops; o += T) {
-                const DevOp op = ops[P.op_begin + o];
+                const DevOp &op = ops[P.op_begin + o];
                 if (op.kind == OP_HOP) {
                     double s, c;
                     sincos(theta[op.param] * op.t, &s, &c);
@@ -279,7 +345,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
             }
             if constexpr (!GEN) {
                 for (int o = 0; o < P.n_ops; ++o) {
-                    const DevOp op = ops[P.op_begin + o];
+                    const DevOp &op = ops[P.op_begin + o];
                     if (op.kind != OP_DIAG)
                         continue;
                     for (int m = tid; m < kDiagTab; m += T) {
@@ -290,42 +356,46 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                 }
             }
         }
-        if (single) {
-            for (int r = tid; r < n_red; r += T)
-                red[r] = 0.0;
-        } else {
-            for (int r = 0; r < n_red; ++r)
-                red[r * T + tid] = 0.0;
-        }
+        for (int r = tid; r < n_red * R; r += T)
+            red[r] = 0.0;
     }
     __syncthreads();
-    double *wsum = red + n_red * (single ? 1 : T);
+    double *wsum = red + n_red * R;
 
-    const uint32_t cmask = (1u << P.c) - 1u;
     const uint64_t ntiles = (uint64_t)1 << P.nfree;
-    const DevPhase *ph = phases + P.phase_begin;
-    const uint32_t valid = ph[0].valid;
+    const uint32_t valid = FULL ? 0xFFFFu : ph[0].valid;
+    const uint32_t step_dep = pdep32((uint32_t)tstep, P.free_mask);
     double eacc = 0.0;
     double2 v[NV][kRegs];
-    // the first phase's layout is the load layout; its thread part of the
-    // global index is the same for every tile
-    const uint32_t tloc0 = thread_local_index(ph[0].lmask, ph[0].wmask, tid);
-    const uint32_t gthr0 = offs[tloc0 >> P.c] | (tloc0 & cmask);
+
+    // the thread's part of phase q's layout: global bits and slot offset
+    auto thread_part = [&](int q) __attribute__((always_inline)) {
+        const uint2 a = ltab[q * 64 + lane], b = wtab[q * kMaxWaves + wave];
+        return make_uint2(a.x | b.x, a.y ^ b.y);
+    };
+    const uint2 tp0 = thread_part(0);
+    const RegLayout L0 = reg_layout(ph[0]);
+
     // Registers of a tile smaller than 16 amplitudes that hold nothing are
     // zero, so they add nothing to any reduction.
-    auto load_tile = [&](double2 (&dst)[NV][kRegs], uint64_t t) __attribute__((always_inline)) {
-        const uint32_t gb = pdep32((uint32_t)t, P.free_mask) | gthr0;
+    auto load_tile = [&](double2 (&dst)[NV][kRegs], uint32_t base) __attribute__((always_inline)) {
+        const uint32_t gb = base | tp0.x;
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) {
-            dst[0][j] = make_double2(0.0, 0.0);
-            if constexpr (NV == 2)
-                dst[NV - 1][j] = make_double2(0.0, 0.0);
-            if (act && ((valid >> j) & 1u)) {
-                const uint64_t g = gb | ph[0].goff[j];
-                dst[0][j] = v0[g];
+            if constexpr (!FULL) {
+                dst[0][j] = make_double2(0.0, 0.0);
                 if constexpr (NV == 2)
+                    dst[NV - 1][j] = make_double2(0.0, 0.0);
+            }
+            if (FULL || (act && ((valid >> j) & 1u))) {
+                const uint64_t g = gb | L0.goff(j);
+                dst[0][j] = v0[g];
+                if constexpr (NV == 2) {
                     if (!ham_first)
                         dst[NV - 1][j] = v1[g];
+                    else if constexpr (FULL)
+                        dst[NV - 1][j] = make_double2(0.0, 0.0);
+                }
             }
         }
     };
@@ -334,110 +404,109 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     // is bounded by LDS, not by VGPRs, for these kernels).
     constexpr bool PREFETCH = (NV == 1);
     double2 nxt[NV][kRegs];
+    uint32_t base = pdep32((uint32_t)tile0, P.free_mask);
     if (PREFETCH && tile0 < ntiles)
-        load_tile(nxt, tile0);
+        load_tile(nxt, base);
 
     for (uint64_t tl = tile0; tl < ntiles; tl += tstep) {
-        const uint32_t base = pdep32((uint32_t)tl, P.free_mask);
-        uint32_t tloc = tloc0;
-        uint32_t gthr = base | gthr0;
+        const uint32_t nbase = tile_advance(base, step_dep, P.free_mask);
         if constexpr (PREFETCH) {
 #pragma unroll
             for (int j = 0; j < kRegs; ++j)
                 v[0][j] = nxt[0][j];
             if (tl + tstep < ntiles)
-                load_tile(nxt, tl + tstep);
+                load_tile(nxt, nbase);
         } else {
-            load_tile(v, tl);
+            load_tile(v, base);
         }
+        uint2 tp = tp0;
+        RegLayout L = L0;
+        uint32_t gthr = base | tp.x;
         for (int q = 0; q < P.n_phases; ++q) {
+            const DevPhase &phq = ph[q];
             if (q > 0) {
-                const uint32_t tnew = thread_local_index(ph[q].lmask, ph[q].wmask, tid);
-                relayout<NV>(v, xbuf, tloc, ph[q - 1], tnew, ph[q], act ? valid : 0u);
-                tloc = tnew;
-                gthr = base | offs[tloc >> P.c] | (tloc & cmask);
+                const uint2 tn = thread_part(q);
+                const RegLayout Ln = reg_layout(phq);
+                relayout<NV, FULL>(v, xbuf, tp.y, L, tn.y, Ln, phq.cross != 0,
+                                   act ? valid : 0u);
+                tp = tn;
+                L = Ln;
+                gthr = base | tp.x;
             }
-            for (int o = ph[q].op_begin; o < ph[q].op_end; ++o) {
-                const DevOp op = ops[P.op_begin + o];
-                double dacc = 0.0;   // reverse: this op's Im <lambda|D_sub|psi>
+            for (int o = phq.op_begin; o < phq.op_end; ++o) {
+                const DevOp &op = ops[P.op_begin + o];
+                double racc = 0.0;   // this op's reduction (thread part)
                 if (op.kind == OP_DIAG) {
 #pragma unroll
                     for (int j = 0; j < kRegs; ++j) {
-                        if (!((valid >> j) & 1u))
+                        if (!FULL && !((valid >> j) & 1u))
                             continue;
-                        const uint32_t g = gthr | ph[q].goff[j];
+                        const uint32_t g = gthr | L.goff(j);
                         if constexpr (MODE == M_FWD || MODE == M_REV) {
                             double2 phs;
                             if constexpr (!GEN) {
-                                uint32_t up = g & op.umask;
-                                uint32_t dn = (uint32_t)((uint64_t)g >> M->ns) & op.umask;
-                                phs = dtab[op.dtab * kDiagTab + __popc(up & dn)];
+                                const uint32_t dbl = g & (g >> M->ns) & op.umask;
+                                phs = dtab[op.dtab * kDiagTab + __popc(dbl)];
                             } else {
                                 double s, c;
                                 sincos(theta[op.param] * diag_value<GEN>(op, g, M, vb), &s, &c);
                                 phs = make_double2(c, -sign * s);
                             }
                             if constexpr (MODE == M_REV) {
-                                double d = diag_value<GEN>(op, g, M, vb);
-                                dacc += d * im_conj_mul(v[NV - 1][j], v[0][j]);
+                                const double d = diag_value<GEN>(op, g, M, vb);
+                                racc += d * im_conj_mul(v[NV - 1][j], v[0][j]);
                                 v[NV - 1][j] = cmul(v[NV - 1][j], phs);
                             }
                             v[0][j] = cmul(v[0][j], phs);
                         } else if constexpr (MODE == M_HAM) {
-                            double d = diag_value<GEN>(op, g, M, vb);
+                            const double d = diag_value<GEN>(op, g, M, vb);
                             v[NV - 1][j].x += d * v[0][j].x;
                             v[NV - 1][j].y += d * v[0][j].y;
                         } else {
-                            double2 a = v[0][j];
+                            const double2 a = v[0][j];
                             eacc += diag_value<GEN>(op, g, M, vb) * (a.x * a.x + a.y * a.y);
-                        }
-                    }
-                    if constexpr (MODE == M_REV) {
-                        if (single) {
-                            const double tot = block_sum(dacc, wsum);
-                            if (tid == 0)
-                                red[op.red] += tot;
-                        } else {
-                            red[op.red * T + tid] += dacc;
                         }
                     }
                 } else {
                     PairCtx x;
-                    const bool podd =
-                        ((__popc(tloc & op.bm_local) + __popc((uint32_t)tl & op.bm_free)) & 1u) != 0;
+                    // thread and tile part of the Jordan-Wigner sign
+                    const bool podd = (__popc(gthr & op.between) & 1u) != 0;
                     x.flip = op.flip;
                     x.t = podd ? op.t : -op.t;   // (-t) times the thread part of the sign
                     x.acc = 0.0;
                     if constexpr (MODE == M_FWD || MODE == M_REV) {
-                        x.cs = opc[o].x;
-                        x.sn = podd ? -opc[o].y : opc[o].y;
+                        const double2 cs = opc[o];
+                        x.cs = cs.x;
+                        x.sn = podd ? -cs.y : cs.y;
                     } else {
                         x.cs = x.sn = 0.0;
                     }
                     hop_regs<MODE, NV>(op.pair, v, x);
-                    // (-t) s summed: thread part of s applied here
-                    const double red_op = x.t * x.acc;
-                    if constexpr (MODE == M_REV) {
-                        if (single) {
-                            const double tot = block_sum(red_op, wsum);
-                            if (tid == 0)
-                                red[op.red] += tot;
-                        } else {
-                            red[op.red * T + tid] += red_op;
-                        }
-                    }
+                    racc = x.t * x.acc;   // (-t) s summed, thread part of s applied
                     if constexpr (MODE == M_EXP)
-                        eacc += 2.0 * red_op;
+                        eacc += 2.0 * racc;
+                }
+                if constexpr (MODE == M_REV) {
+                    if (single) {
+                        const double tot = block_sum(racc, wsum);
+                        if (tid == 0)
+                            red[op.red] += tot;
+                    } else if (quad) {
+                        const double qs = quad_sum(racc);
+                        if ((tid & 3) == 0)
+                            red[op.red * R + (tid >> 2)] += qs;
+                    } else {
+                        red[op.red * R + tid] += racc;
+                    }
                 }
             }
         }
         // ---- store from the last phase's layout
-        const DevPhase &pl = ph[P.n_phases - 1];
         if constexpr (MODE != M_EXP) {
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) {
-                if (act && ((valid >> j) & 1u)) {
-                    const uint64_t g = gthr | pl.goff[j];
+                if (FULL || (act && ((valid >> j) & 1u))) {
+                    const uint64_t g = gthr | L.goff(j);
                     if constexpr (MODE == M_FWD || MODE == M_REV)
                         v0[g] = v[0][j];
                     if constexpr (NV == 2)
@@ -447,6 +516,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                 }
             }
         }
+        base = nbase;
     }
     __syncthreads();
     if (MODE == M_EXP || (MODE == M_HAM && n_red > 0)) {
@@ -455,10 +525,10 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
             red[0] = tot;
         __syncthreads();
     } else if (!single) {
-        // per-thread rows -> row sums in red[r * T]
+        // accumulators -> row sums in red[r * R], fixed tree order
         for (int r = 0; r < n_red; ++r) {
-            double *row = red + r * T;
-            for (int s = T >> 1; s > 0; s >>= 1) {
+            double *row = red + r * R;
+            for (int s = R >> 1; s > 0; s >>= 1) {
                 __syncthreads();
                 if (tid < s)
                     row[tid] += row[tid + s];
@@ -467,7 +537,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
         __syncthreads();
     }
     if (tid == 0) {
-        const int rstride = (MODE == M_EXP || MODE == M_HAM || single) ? 1 : T;
+        const int rstride = (MODE == M_EXP || MODE == M_HAM || single) ? 1 : R;
         for (int r = 0; r < n_red; ++r) {
             const double val = red[r * rstride];
             if (sink.row_param) {
@@ -484,7 +554,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     __syncthreads();
 }
 
-template <int MODE, bool GEN>
+template <int MODE, bool GEN, bool FULL>
 __global__ void __launch_bounds__(512)
 k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__ ops,
        const DevVBond *__restrict__ vb, const double *__restrict__ theta,
@@ -493,7 +563,8 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
 {
     extern __shared__ __align__(16) char smem[];
     Sink sink{partial, stride, (int)blockIdx.x, nullptr, nullptr, nullptr};
-    run_pass<MODE, GEN>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x, gridDim.x, sink);
+    run_pass<MODE, GEN, FULL>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x, gridDim.x,
+                              sink);
 }
 
 // Persistent batch kernel: each workgroup claims whole instances from a
@@ -529,28 +600,28 @@ k_batch(const DevInstance *__restrict__ inst, const DevPass *__restrict__ passes
         const DevPass *ps = passes + I.pass_begin;
         for (int p = 0; p < I.n_fwd; ++p) {
             if (I.general)
-                run_pass<M_FWD, true>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_FWD, true, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                       smem, 0, 1, sink);
             else
-                run_pass<M_FWD, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_FWD, false, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                        smem, 0, 1, sink);
         }
         ps += I.n_fwd;
         for (int p = 0; p < I.n_ham; ++p) {
             if (I.general)
-                run_pass<M_HAM, true>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_HAM, true, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                       smem, 0, 1, sink);
             else
-                run_pass<M_HAM, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_HAM, false, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                        smem, 0, 1, sink);
         }
         ps += I.n_ham;
         for (int p = 0; p < I.n_rev; ++p) {
             if (I.general)
-                run_pass<M_REV, true>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_REV, true, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                       smem, 0, 1, sink);
             else
-                run_pass<M_REV, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_REV, false, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                        smem, 0, 1, sink);
         }
     }
@@ -562,19 +633,27 @@ __global__ void k_fill_u32(unsigned int *p, unsigned int v, int n)
         p[i] = v;
 }
 
-#define HV_INSTANTIATE(MODE, GEN)                                                          \
-    template __global__ void k_pass<MODE, GEN>(DevPass, const DevPhase *, const DevOp *,   \
-                                               const DevVBond *, const double *,           \
-                                               const DevModel *, double2 *, double2 *,     \
-                                               double *, int);
-HV_INSTANTIATE(M_FWD, false)
-HV_INSTANTIATE(M_REV, false)
-HV_INSTANTIATE(M_HAM, false)
-HV_INSTANTIATE(M_EXP, false)
-HV_INSTANTIATE(M_FWD, true)
-HV_INSTANTIATE(M_REV, true)
-HV_INSTANTIATE(M_HAM, true)
-HV_INSTANTIATE(M_EXP, true)
+#define HV_INSTANTIATE(MODE, GEN, FULL)                                                    \
+    template __global__ void k_pass<MODE, GEN, FULL>(DevPass, const DevPhase *, const DevOp *, \
+                                                     const DevVBond *, const double *,         \
+                                                     const DevModel *, double2 *, double2 *,   \
+                                                     double *, int);
+HV_INSTANTIATE(M_FWD, false, true)
+HV_INSTANTIATE(M_REV, false, true)
+HV_INSTANTIATE(M_HAM, false, true)
+HV_INSTANTIATE(M_EXP, false, true)
+HV_INSTANTIATE(M_FWD, true, true)
+HV_INSTANTIATE(M_REV, true, true)
+HV_INSTANTIATE(M_HAM, true, true)
+HV_INSTANTIATE(M_EXP, true, true)
+HV_INSTANTIATE(M_FWD, false, false)
+HV_INSTANTIATE(M_REV, false, false)
+HV_INSTANTIATE(M_HAM, false, false)
+HV_INSTANTIATE(M_EXP, false, false)
+HV_INSTANTIATE(M_FWD, true, false)
+HV_INSTANTIATE(M_REV, true, false)
+HV_INSTANTIATE(M_HAM, true, false)
+HV_INSTANTIATE(M_EXP, true, false)
 #undef HV_INSTANTIATE
 
 // ------------------------------------------------------------ misc kernels --
