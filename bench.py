@@ -206,7 +206,9 @@ def main():
         if cnt == 0:
             continue
         avg = tot / cnt
-        kernels[mode] = {"kernel": f"hv::k_pass<{abi.KERNEL_MODES[mode]}, {gen}>",
+        # kernel template: <mode, general diagonal, full tiles, tiles per iteration>
+        nt = 2 if (mode == "forward" and not w.general) else 1
+        kernels[mode] = {"kernel": f"hv::k_pass<{abi.KERNEL_MODES[mode]}, {gen}, true, {nt}>",
                          "avg_ms": avg, "launches_per_step": cnt // args.steps,
                          "bytes_per_launch": nvec * vec,
                          "GBs": nvec * vec / (avg * 1e-3) / 1e9}

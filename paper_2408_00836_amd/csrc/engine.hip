@@ -18,7 +18,7 @@
 #include "hubvqe.hpp"
 
 namespace hv {
-template <int MODE, bool GEN, bool FULL>
+template <int MODE, bool GEN, bool FULL, int NT>
 __global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,
                        const DevModel *, double2 *, double2 *, double *, int);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t);
@@ -51,6 +51,7 @@ struct PassList {
     std::vector<int> grid;
     std::vector<int> smem;
     std::vector<int> threads;
+    std::vector<int> nt;   // tiles per loop iteration (2: one-vector full-tile passes)
 };
 
 // Everything one call needs on one device.
@@ -122,8 +123,11 @@ struct Builder {
     std::vector<int> row_nblk;
     explicit Builder(const Model &mm) : m(mm) {}
 
-    // rows: 0 none, 1 one row per distinct param (reverse), 2 one energy row
-    PassList add(const std::vector<HostPass> &passes, int rows, bool last_only_energy)
+    // rows: 0 none, 1 one row per distinct param (reverse), 2 one energy row.
+    // dual: forward passes of a U-only model over full tiles take two tiles
+    // per loop iteration, on half the workgroups.
+    PassList add(const std::vector<HostPass> &passes, int rows, bool last_only_energy,
+                 bool dual = false)
     {
         PassList pl;
         for (size_t pi = 0; pi < passes.size(); ++pi) {
@@ -152,7 +156,8 @@ struct Builder {
             P.flags = hp.flags;
             P.op_begin = (int)ops.size();
             const uint64_t ntiles = (uint64_t)1 << nf;
-            const int grid = (int)std::min<uint64_t>(ntiles, kGridMax);
+            const bool two = dual && !m.general && P.k >= kRegBits && nf >= 1;
+            const int grid = (int)std::min<uint64_t>(two ? ntiles / 2 : ntiles, kGridMax);
             std::map<int, int> red_of;
             P.red_base = (int)row_param.size();
             if (rows == 2 && (!last_only_energy || (hp.flags & PF_HAM_LAST))) {
@@ -296,6 +301,7 @@ struct Builder {
                 phases.push_back(D);
             }
             pl.pass.push_back(P);
+            pl.nt.push_back(two ? 2 : 1);
             pl.grid.push_back(grid);
             pl.smem.push_back(0);
             pl.threads.push_back(1 << P.tbits);
@@ -367,7 +373,7 @@ hubbard_status upload_program(hubbard_model *h, DeviceState &ds, Program &pr)
 {
     const Model &m = h->m;
     Builder b(m);
-    pr.fwd = b.add(pr.h_fwd, 0, false);
+    pr.fwd = b.add(pr.h_fwd, 0, false, true);
     pr.ham = b.add(pr.h_ham, pr.kind == PROG_GRAD ? 2 : 0, true);
     pr.rev = b.add(pr.h_rev, 1, false);
     pr.exp = b.add(pr.h_exp, 2, false);
@@ -449,14 +455,15 @@ hubbard_status ensure_model(hubbard_model *h, int dev, DeviceState &ds)
     std::call_once(attr_once, [] {
         int lim = max_smem_per_block();
         const void *fns[] = {
-            (const void *)k_pass<M_FWD, false, true>,  (const void *)k_pass<M_REV, false, true>,
-            (const void *)k_pass<M_HAM, false, true>,  (const void *)k_pass<M_EXP, false, true>,
-            (const void *)k_pass<M_FWD, true, true>,   (const void *)k_pass<M_REV, true, true>,
-            (const void *)k_pass<M_HAM, true, true>,   (const void *)k_pass<M_EXP, true, true>,
-            (const void *)k_pass<M_FWD, false, false>, (const void *)k_pass<M_REV, false, false>,
-            (const void *)k_pass<M_HAM, false, false>, (const void *)k_pass<M_EXP, false, false>,
-            (const void *)k_pass<M_FWD, true, false>,  (const void *)k_pass<M_REV, true, false>,
-            (const void *)k_pass<M_HAM, true, false>,  (const void *)k_pass<M_EXP, true, false>};
+            (const void *)k_pass<M_FWD, false, true, 1>,  (const void *)k_pass<M_REV, false, true, 1>,
+            (const void *)k_pass<M_HAM, false, true, 1>,  (const void *)k_pass<M_EXP, false, true, 1>,
+            (const void *)k_pass<M_FWD, true, true, 1>,   (const void *)k_pass<M_REV, true, true, 1>,
+            (const void *)k_pass<M_HAM, true, true, 1>,   (const void *)k_pass<M_EXP, true, true, 1>,
+            (const void *)k_pass<M_FWD, false, false, 1>, (const void *)k_pass<M_REV, false, false, 1>,
+            (const void *)k_pass<M_HAM, false, false, 1>, (const void *)k_pass<M_EXP, false, false, 1>,
+            (const void *)k_pass<M_FWD, true, false, 1>,  (const void *)k_pass<M_REV, true, false, 1>,
+            (const void *)k_pass<M_HAM, true, false, 1>,  (const void *)k_pass<M_EXP, true, false, 1>,
+            (const void *)k_pass<M_FWD, false, true, 2>};
         for (const void *f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     });
@@ -562,20 +569,29 @@ void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, c
         const bool timed = launch_mark(h, MODE, s, false);
         // tiles of >= 16 amplitudes fill every register of every thread
         const bool full = pl.pass[i].k >= kRegBits;
-#define HV_LAUNCH(GEN, FULL)                                                                    \
-    hipLaunchKernelGGL((k_pass<MODE, GEN, FULL>), dim3(pl.grid[i]), dim3(pl.threads[i]),        \
+        const bool two = pl.nt[i] == 2;
+#define HV_LAUNCH(GEN, FULL, NT)                                                                \
+    hipLaunchKernelGGL((k_pass<MODE, GEN, FULL, NT>), dim3(pl.grid[i]), dim3(pl.threads[i]),    \
                        pl.smem[i], s, pl.pass[i], pr.d_phases, pr.d_ops, pr.d_vb, theta,        \
                        ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax)
+        if constexpr (MODE == M_FWD) {
+            if (two) {   // only planned for U-only models
+                HV_LAUNCH(false, true, 2);
+                if (timed)
+                    launch_mark(h, MODE, s, true);
+                continue;
+            }
+        }
         if (pr.general) {
             if (full)
-                HV_LAUNCH(true, true);
+                HV_LAUNCH(true, true, 1);
             else
-                HV_LAUNCH(true, false);
+                HV_LAUNCH(true, false, 1);
         } else {
             if (full)
-                HV_LAUNCH(false, true);
+                HV_LAUNCH(false, true, 1);
             else
-                HV_LAUNCH(false, false);
+                HV_LAUNCH(false, false, 1);
         }
 #undef HV_LAUNCH
         if (timed)
@@ -866,7 +882,7 @@ hubbard_status hubbard_workspace_size(hubbard_t h, int32_t n_layers, int32_t op,
         return fail(HUBBARD_ERR_NOMEM, ex.what());
     }
     Builder b(h->m);
-    b.add(pr.h_fwd, 0, false);
+    b.add(pr.h_fwd, 0, false, true);
     b.add(pr.h_ham, op == HUBBARD_OP_ENERGY_GRAD ? 2 : 0, true);
     b.add(pr.h_rev, 1, false);
     b.add(pr.h_exp, 2, false);

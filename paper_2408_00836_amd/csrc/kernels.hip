@@ -94,10 +94,13 @@ __device__ __forceinline__ void rotate(double2 &x, double2 &y, double c, double 
 // folded into sn and t once per op; the register part is a wave-uniform bit
 // of the op's flip mask (precomputed from the phase layout), applied by one
 // XOR of the sign bit -- no loads and no branches per pair.
+template <int NT>
 struct PairCtx {
-    double cs, sn, t;      // rotation (cos, thread-signed sin); thread-signed (-t)
+    double cs;             // cos of the rotation
+    double sn[NT];         // sin, times the thread part of the sign, per tile
+    double t[NT];          // (-t_b) times the thread part of the sign, per tile
     uint32_t flip;         // bit j: register j's part of the sign is odd
-    double acc;            // reduction of the op (register part of the sign applied)
+    double acc[NT];        // reduction of the op (register part of the sign applied)
 };
 
 __device__ __forceinline__ double flip_sign(double x, uint32_t bit)
@@ -105,58 +108,65 @@ __device__ __forceinline__ double flip_sign(double x, uint32_t bit)
     return __longlong_as_double(__double_as_longlong(x) ^ ((long long)bit << 63));
 }
 
-template <int MODE, int NV, int J, int JJ>
-__device__ __forceinline__ void pair_op(double2 (&v)[NV][kRegs], PairCtx &x)
+// One register pair (J, JJ) of a hopping term.  Register sets: forward and
+// expectation passes hold NT tiles of one vector (set t = tile t); reverse
+// and H passes hold one tile of two vectors (set 0 = psi, set 1 = lambda or
+// phi).
+template <int MODE, int NT, int NS, int J, int JJ>
+__device__ __forceinline__ void pair_op(double2 (&v)[NS][kRegs], PairCtx<NT> &x)
 {
     const uint32_t fb = (x.flip >> J) & 1u;   // wave-uniform
     if constexpr (MODE == 0) {            // forward gate
-        rotate(v[0][J], v[0][JJ], x.cs, flip_sign(x.sn, fb));
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            rotate(v[t][J], v[t][JJ], x.cs, flip_sign(x.sn[t], fb));
     } else if constexpr (MODE == 1) {     // reverse: reduce, then un-apply
-        const double w =
-            im_conj_mul(v[NV - 1][J], v[0][JJ]) + im_conj_mul(v[NV - 1][JJ], v[0][J]);
-        x.acc += flip_sign(w, fb);
-        const double ss = flip_sign(x.sn, fb);
+        const double w = im_conj_mul(v[1][J], v[0][JJ]) + im_conj_mul(v[1][JJ], v[0][J]);
+        x.acc[0] += flip_sign(w, fb);
+        const double ss = flip_sign(x.sn[0], fb);
         rotate(v[0][J], v[0][JJ], x.cs, ss);
-        rotate(v[NV - 1][J], v[NV - 1][JJ], x.cs, ss);
+        rotate(v[1][J], v[1][JJ], x.cs, ss);
     } else if constexpr (MODE == 2) {     // phi += (-t) s (swap) psi
-        const double w = flip_sign(x.t, fb);
-        v[NV - 1][J].x += w * v[0][JJ].x;
-        v[NV - 1][J].y += w * v[0][JJ].y;
-        v[NV - 1][JJ].x += w * v[0][J].x;
-        v[NV - 1][JJ].y += w * v[0][J].y;
+        const double w = flip_sign(x.t[0], fb);
+        v[1][J].x += w * v[0][JJ].x;
+        v[1][J].y += w * v[0][JJ].y;
+        v[1][JJ].x += w * v[0][J].x;
+        v[1][JJ].y += w * v[0][J].y;
     } else {                              // expectation
-        x.acc += flip_sign(re_conj_mul(v[0][J], v[0][JJ]), fb);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            x.acc[t] += flip_sign(re_conj_mul(v[t][J], v[t][JJ]), fb);
     }
 }
 
-template <int MODE, int NV, int A, int B, int X>
-__device__ __forceinline__ void pair_at(double2 (&v)[NV][kRegs], PairCtx &x)
+template <int MODE, int NT, int NS, int A, int B, int X>
+__device__ __forceinline__ void pair_at(double2 (&v)[NS][kRegs], PairCtx<NT> &x)
 {
     constexpr int C = (A != 0 && B != 0) ? 0 : ((A != 1 && B != 1) ? 1 : 2);
     constexpr int D = 6 - A - B - C;   // the fourth register bit
     constexpr int J = (1 << A) | ((X & 1) << C) | (((X >> 1) & 1) << D);
-    pair_op<MODE, NV, J, J ^ ((1 << A) | (1 << B))>(v, x);
+    pair_op<MODE, NT, NS, J, J ^ ((1 << A) | (1 << B))>(v, x);
 }
 
-template <int MODE, int NV, int A, int B>
-__device__ __forceinline__ void pairs4(double2 (&v)[NV][kRegs], PairCtx &x)
+template <int MODE, int NT, int NS, int A, int B>
+__device__ __forceinline__ void pairs4(double2 (&v)[NS][kRegs], PairCtx<NT> &x)
 {
-    pair_at<MODE, NV, A, B, 0>(v, x);
-    pair_at<MODE, NV, A, B, 1>(v, x);
-    pair_at<MODE, NV, A, B, 2>(v, x);
-    pair_at<MODE, NV, A, B, 3>(v, x);
+    pair_at<MODE, NT, NS, A, B, 0>(v, x);
+    pair_at<MODE, NT, NS, A, B, 1>(v, x);
+    pair_at<MODE, NT, NS, A, B, 2>(v, x);
+    pair_at<MODE, NT, NS, A, B, 3>(v, x);
 }
 
-template <int MODE, int NV>
-__device__ __forceinline__ void hop_regs(int pair, double2 (&v)[NV][kRegs], PairCtx &x)
+template <int MODE, int NT, int NS>
+__device__ __forceinline__ void hop_regs(int pair, double2 (&v)[NS][kRegs], PairCtx<NT> &x)
 {
     switch (pair) {
-    case 0: pairs4<MODE, NV, 0, 1>(v, x); break;
-    case 1: pairs4<MODE, NV, 0, 2>(v, x); break;
-    case 2: pairs4<MODE, NV, 0, 3>(v, x); break;
-    case 3: pairs4<MODE, NV, 1, 2>(v, x); break;
-    case 4: pairs4<MODE, NV, 1, 3>(v, x); break;
-    default: pairs4<MODE, NV, 2, 3>(v, x); break;
+    case 0: pairs4<MODE, NT, NS, 0, 1>(v, x); break;
+    case 1: pairs4<MODE, NT, NS, 0, 2>(v, x); break;
+    case 2: pairs4<MODE, NT, NS, 0, 3>(v, x); break;
+    case 3: pairs4<MODE, NT, NS, 1, 2>(v, x); break;
+    case 4: pairs4<MODE, NT, NS, 1, 3>(v, x); break;
+    default: pairs4<MODE, NT, NS, 2, 3>(v, x); break;
     }
 }
 
@@ -203,15 +213,15 @@ __device__ __forceinline__ RegLayout reg_layout(const DevPhase &ph)
 // If the wave bits stay fixed (cross == false) every wave reads back exactly
 // the slots it wrote, in program order, so no workgroup barrier is needed;
 // every LDS slot a wave touches between cross-wave exchanges is its own.
-template <int NV, bool FULL>
-__device__ __forceinline__ void relayout(double2 (&v)[NV][kRegs], char *xbuf, uint32_t xf,
+template <int NS, bool FULL>
+__device__ __forceinline__ void relayout(double2 (&v)[NS][kRegs], char *xbuf, uint32_t xf,
                                          const RegLayout &from, uint32_t xt, const RegLayout &to,
                                          bool cross, uint32_t valid)
 {
 #pragma unroll
-    for (int w = 0; w < NV; ++w) {
+    for (int w = 0; w < NS; ++w) {
         if (cross && w > 0)
-            __syncthreads();   // the previous vector's reads are done everywhere
+            __syncthreads();   // the previous set's reads are done everywhere
 #pragma unroll
         for (int j = 0; j < kRegs; ++j)
             if (FULL || ((valid >> j) & 1u))
@@ -274,6 +284,15 @@ __device__ __forceinline__ double block_sum(double x, double *wsum)
     return tot;
 }
 
+// A value the optimiser must treat as freshly computed here (an empty asm
+// that claims to modify it), so that work derived from it stays where it is
+// written instead of being hoisted into long-lived registers.
+__device__ __forceinline__ uint32_t opaque(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Global-index bits of a tile-local index x: tile bits 0..c-1 are global bits
 // 0..c-1, the others are deposited over hi_mask (the tile's bits, ascending).
 __device__ __forceinline__ uint32_t tile_global(uint32_t x, int c, uint32_t hi_mask)
@@ -293,7 +312,10 @@ __device__ __forceinline__ uint32_t tile_advance(uint32_t base, uint32_t step_de
 // One pass over the tiles [tile0, 2^nfree) with stride tstep.  FULL: all
 // threads own amplitudes and all 16 registers hold one (tiles of >= 16
 // amplitudes launched with exactly 2^tbits threads): no per-register guards.
-template <int MODE, bool GEN, bool FULL>
+// NT = 2 (forward and expectation passes only): every iteration takes the
+// tiles tl and tl + tstep, which needs 2^nfree to be a multiple of 2 tstep;
+// the op stream is then decoded once for two tiles.
+template <int MODE, bool GEN, bool FULL, int NT>
 __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__restrict__ phases,
                                          const DevOp *__restrict__ ops,
                                          const DevVBond *__restrict__ vb,
@@ -302,7 +324,9 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                                          double2 *__restrict__ v1, char *smem, uint64_t tile0,
                                          uint64_t tstep, const Sink &sink)
 {
-    constexpr int NV = (MODE == M_FWD || MODE == M_EXP) ? 1 : 2;
+    constexpr int NV = (MODE == M_FWD || MODE == M_EXP) ? 1 : 2;   // vectors per tile
+    constexpr int NS = NT * NV;                                     // register sets
+    static_assert(NS <= 2 && (NT == 1 || NV == 1), "at most two register sets");
     const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // a batch workgroup may be wider than this pass's 2^tbits threads: the
     // extra threads keep zero registers and only join the barriers
@@ -366,7 +390,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     const uint32_t valid = FULL ? 0xFFFFu : ph[0].valid;
     const uint32_t step_dep = pdep32((uint32_t)tstep, P.free_mask);
     double eacc = 0.0;
-    double2 v[NV][kRegs];
+    double2 v[NS][kRegs];
 
     // the thread's part of phase q's layout: global bits and slot offset
     auto thread_part = [&](int q) __attribute__((always_inline)) {
@@ -378,111 +402,140 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
 
     // Registers of a tile smaller than 16 amplitudes that hold nothing are
     // zero, so they add nothing to any reduction.
-    auto load_tile = [&](double2 (&dst)[NV][kRegs], uint32_t base) __attribute__((always_inline)) {
-        const uint32_t gb = base | tp0.x;
+    auto load_tiles = [&](double2 (&dst)[NS][kRegs], const uint32_t (&bs)[NT])
+                          __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < kRegs; ++j) {
-            if constexpr (!FULL) {
-                dst[0][j] = make_double2(0.0, 0.0);
-                if constexpr (NV == 2)
-                    dst[NV - 1][j] = make_double2(0.0, 0.0);
-            }
-            if (FULL || (act && ((valid >> j) & 1u))) {
-                const uint64_t g = gb | L0.goff(j);
-                dst[0][j] = v0[g];
-                if constexpr (NV == 2) {
-                    if (!ham_first)
-                        dst[NV - 1][j] = v1[g];
-                    else if constexpr (FULL)
-                        dst[NV - 1][j] = make_double2(0.0, 0.0);
+        for (int t = 0; t < NT; ++t) {
+            const uint32_t gb = bs[t] | tp0.x;
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                if constexpr (!FULL) {
+                    dst[t * NV][j] = make_double2(0.0, 0.0);
+                    if constexpr (NV == 2)
+                        dst[1][j] = make_double2(0.0, 0.0);
+                }
+                if (FULL || (act && ((valid >> j) & 1u))) {
+                    const uint64_t g = gb | L0.goff(j);
+                    dst[t * NV][j] = v0[g];
+                    if constexpr (NV == 2) {
+                        if (!ham_first)
+                            dst[1][j] = v1[g];
+                        else if constexpr (FULL)
+                            dst[1][j] = make_double2(0.0, 0.0);
+                    }
                 }
             }
         }
     };
-    // One-vector passes prefetch the next tile into a second register set
-    // while the current one is computed (the registers are there: occupancy
-    // is bounded by LDS, not by VGPRs, for these kernels).
-    constexpr bool PREFETCH = (NV == 1);
-    double2 nxt[NV][kRegs];
-    uint32_t base = pdep32((uint32_t)tile0, P.free_mask);
+    // One-vector, one-tile passes prefetch the next tile into a second
+    // register set while the current one is computed.
+    constexpr bool PREFETCH = (NS == 1);
+    double2 nxt[NS][kRegs];
+    uint32_t bases[NT];
+    bases[0] = pdep32((uint32_t)tile0, P.free_mask);
+#pragma unroll
+    for (int t = 1; t < NT; ++t)
+        bases[t] = tile_advance(bases[t - 1], step_dep, P.free_mask);
     if (PREFETCH && tile0 < ntiles)
-        load_tile(nxt, base);
+        load_tiles(nxt, bases);
 
-    for (uint64_t tl = tile0; tl < ntiles; tl += tstep) {
-        const uint32_t nbase = tile_advance(base, step_dep, P.free_mask);
+    for (uint64_t tl = tile0; tl < ntiles; tl += NT * tstep) {
+        uint32_t nbases[NT];
+        nbases[0] = tile_advance(bases[NT - 1], step_dep, P.free_mask);
+#pragma unroll
+        for (int t = 1; t < NT; ++t)
+            nbases[t] = tile_advance(nbases[t - 1], step_dep, P.free_mask);
         if constexpr (PREFETCH) {
 #pragma unroll
             for (int j = 0; j < kRegs; ++j)
                 v[0][j] = nxt[0][j];
             if (tl + tstep < ntiles)
-                load_tile(nxt, nbase);
+                load_tiles(nxt, nbases);
         } else {
-            load_tile(v, base);
+            load_tiles(v, bases);
         }
         uint2 tp = tp0;
         RegLayout L = L0;
-        uint32_t gthr = base | tp.x;
+        uint32_t gthr[NT];   // the thread's global bits in each tile
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            gthr[t] = bases[t] | tp.x;
         for (int q = 0; q < P.n_phases; ++q) {
             const DevPhase &phq = ph[q];
             if (q > 0) {
                 const uint2 tn = thread_part(q);
                 const RegLayout Ln = reg_layout(phq);
-                relayout<NV, FULL>(v, xbuf, tp.y, L, tn.y, Ln, phq.cross != 0,
+                relayout<NS, FULL>(v, xbuf, tp.y, L, tn.y, Ln, phq.cross != 0,
                                    act ? valid : 0u);
                 tp = tn;
                 L = Ln;
-                gthr = base | tp.x;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    gthr[t] = bases[t] | tp.x;
             }
             for (int o = phq.op_begin; o < phq.op_end; ++o) {
                 const DevOp &op = ops[P.op_begin + o];
                 double racc = 0.0;   // this op's reduction (thread part)
                 if (op.kind == OP_DIAG) {
 #pragma unroll
-                    for (int j = 0; j < kRegs; ++j) {
-                        if (!FULL && !((valid >> j) & 1u))
-                            continue;
-                        const uint32_t g = gthr | L.goff(j);
-                        if constexpr (MODE == M_FWD || MODE == M_REV) {
-                            double2 phs;
-                            if constexpr (!GEN) {
-                                const uint32_t dbl = g & (g >> M->ns) & op.umask;
-                                phs = dtab[op.dtab * kDiagTab + __popc(dbl)];
-                            } else {
-                                double s, c;
-                                sincos(theta[op.param] * diag_value<GEN>(op, g, M, vb), &s, &c);
-                                phs = make_double2(c, -sign * s);
-                            }
-                            if constexpr (MODE == M_REV) {
+                    for (int t = 0; t < NT; ++t) {
+                        // recomputed per op: hoisted out of the op loop, the
+                        // 16 indices would only occupy (or spill) registers
+                        const uint32_t gt = opaque(gthr[t]);
+#pragma unroll
+                        for (int j = 0; j < kRegs; ++j) {
+                            if (!FULL && !((valid >> j) & 1u))
+                                continue;
+                            const uint32_t g = gt | L.goff(j);
+                            double2 &a = v[t * NV][j];
+                            if constexpr (MODE == M_FWD || MODE == M_REV) {
+                                double2 phs;
+                                if constexpr (!GEN) {
+                                    const uint32_t dbl = g & (g >> M->ns) & op.umask;
+                                    phs = dtab[op.dtab * kDiagTab + __popc(dbl)];
+                                } else {
+                                    double s, c;
+                                    sincos(theta[op.param] * diag_value<GEN>(op, g, M, vb), &s,
+                                           &c);
+                                    phs = make_double2(c, -sign * s);
+                                }
+                                if constexpr (MODE == M_REV) {
+                                    const double d = diag_value<GEN>(op, g, M, vb);
+                                    racc += d * im_conj_mul(v[1][j], a);
+                                    v[1][j] = cmul(v[1][j], phs);
+                                }
+                                a = cmul(a, phs);
+                            } else if constexpr (MODE == M_HAM) {
                                 const double d = diag_value<GEN>(op, g, M, vb);
-                                racc += d * im_conj_mul(v[NV - 1][j], v[0][j]);
-                                v[NV - 1][j] = cmul(v[NV - 1][j], phs);
+                                v[1][j].x += d * a.x;
+                                v[1][j].y += d * a.y;
+                            } else {
+                                eacc += diag_value<GEN>(op, g, M, vb) * (a.x * a.x + a.y * a.y);
                             }
-                            v[0][j] = cmul(v[0][j], phs);
-                        } else if constexpr (MODE == M_HAM) {
-                            const double d = diag_value<GEN>(op, g, M, vb);
-                            v[NV - 1][j].x += d * v[0][j].x;
-                            v[NV - 1][j].y += d * v[0][j].y;
-                        } else {
-                            const double2 a = v[0][j];
-                            eacc += diag_value<GEN>(op, g, M, vb) * (a.x * a.x + a.y * a.y);
                         }
                     }
                 } else {
-                    PairCtx x;
-                    // thread and tile part of the Jordan-Wigner sign
-                    const bool podd = (__popc(gthr & op.between) & 1u) != 0;
+                    PairCtx<NT> x;
                     x.flip = op.flip;
-                    x.t = podd ? op.t : -op.t;   // (-t) times the thread part of the sign
-                    x.acc = 0.0;
+                    double cs = 0.0, sn = 0.0;
                     if constexpr (MODE == M_FWD || MODE == M_REV) {
-                        const double2 cs = opc[o];
-                        x.cs = cs.x;
-                        x.sn = podd ? -cs.y : cs.y;
-                    } else {
-                        x.cs = x.sn = 0.0;
+                        const double2 c2 = opc[o];
+                        cs = c2.x;
+                        sn = c2.y;
                     }
-                    hop_regs<MODE, NV>(op.pair, v, x);
-                    racc = x.t * x.acc;   // (-t) s summed, thread part of s applied
+                    x.cs = cs;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        // thread and tile part of the Jordan-Wigner sign
+                        const bool podd = (__popc(gthr[t] & op.between) & 1u) != 0;
+                        x.t[t] = podd ? op.t : -op.t;   // (-t) times that part of the sign
+                        x.sn[t] = podd ? -sn : sn;
+                        x.acc[t] = 0.0;
+                    }
+                    hop_regs<MODE, NT, NS>(op.pair, v, x);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        racc += x.t[t] * x.acc[t];   // (-t) s summed
                     if constexpr (MODE == M_EXP)
                         eacc += 2.0 * racc;
                 }
@@ -504,19 +557,25 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
         // ---- store from the last phase's layout
         if constexpr (MODE != M_EXP) {
 #pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                if (FULL || (act && ((valid >> j) & 1u))) {
-                    const uint64_t g = gthr | L.goff(j);
-                    if constexpr (MODE == M_FWD || MODE == M_REV)
-                        v0[g] = v[0][j];
-                    if constexpr (NV == 2)
-                        v1[g] = v[NV - 1][j];
-                    if (MODE == M_HAM && ham_last)
-                        eacc += re_conj_mul(v[0][j], v[NV - 1][j]);
+            for (int t = 0; t < NT; ++t) {
+                const uint32_t gt = opaque(gthr[t]);
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) {
+                    if (FULL || (act && ((valid >> j) & 1u))) {
+                        const uint64_t g = gt | L.goff(j);
+                        if constexpr (MODE == M_FWD || MODE == M_REV)
+                            v0[g] = v[t * NV][j];
+                        if constexpr (NV == 2)
+                            v1[g] = v[1][j];
+                        if (MODE == M_HAM && ham_last)
+                            eacc += re_conj_mul(v[0][j], v[1][j]);
+                    }
                 }
             }
         }
-        base = nbase;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            bases[t] = nbases[t];
     }
     __syncthreads();
     if (MODE == M_EXP || (MODE == M_HAM && n_red > 0)) {
@@ -554,7 +613,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     __syncthreads();
 }
 
-template <int MODE, bool GEN, bool FULL>
+template <int MODE, bool GEN, bool FULL, int NT>
 __global__ void __launch_bounds__(512)
 k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__ ops,
        const DevVBond *__restrict__ vb, const double *__restrict__ theta,
@@ -563,8 +622,8 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
 {
     extern __shared__ __align__(16) char smem[];
     Sink sink{partial, stride, (int)blockIdx.x, nullptr, nullptr, nullptr};
-    run_pass<MODE, GEN, FULL>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x, gridDim.x,
-                              sink);
+    run_pass<MODE, GEN, FULL, NT>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x,
+                                  gridDim.x, sink);
 }
 
 // Persistent batch kernel: each workgroup claims whole instances from a
@@ -600,28 +659,28 @@ k_batch(const DevInstance *__restrict__ inst, const DevPass *__restrict__ passes
         const DevPass *ps = passes + I.pass_begin;
         for (int p = 0; p < I.n_fwd; ++p) {
             if (I.general)
-                run_pass<M_FWD, true, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_FWD, true, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                       smem, 0, 1, sink);
             else
-                run_pass<M_FWD, false, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_FWD, false, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                        smem, 0, 1, sink);
         }
         ps += I.n_fwd;
         for (int p = 0; p < I.n_ham; ++p) {
             if (I.general)
-                run_pass<M_HAM, true, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_HAM, true, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                       smem, 0, 1, sink);
             else
-                run_pass<M_HAM, false, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_HAM, false, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                        smem, 0, 1, sink);
         }
         ps += I.n_ham;
         for (int p = 0; p < I.n_rev; ++p) {
             if (I.general)
-                run_pass<M_REV, true, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_REV, true, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                       smem, 0, 1, sink);
             else
-                run_pass<M_REV, false, false>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                run_pass<M_REV, false, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
                                        smem, 0, 1, sink);
         }
     }
@@ -633,27 +692,23 @@ __global__ void k_fill_u32(unsigned int *p, unsigned int v, int n)
         p[i] = v;
 }
 
-#define HV_INSTANTIATE(MODE, GEN, FULL)                                                    \
-    template __global__ void k_pass<MODE, GEN, FULL>(DevPass, const DevPhase *, const DevOp *, \
-                                                     const DevVBond *, const double *,         \
-                                                     const DevModel *, double2 *, double2 *,   \
-                                                     double *, int);
-HV_INSTANTIATE(M_FWD, false, true)
-HV_INSTANTIATE(M_REV, false, true)
-HV_INSTANTIATE(M_HAM, false, true)
-HV_INSTANTIATE(M_EXP, false, true)
-HV_INSTANTIATE(M_FWD, true, true)
-HV_INSTANTIATE(M_REV, true, true)
-HV_INSTANTIATE(M_HAM, true, true)
-HV_INSTANTIATE(M_EXP, true, true)
-HV_INSTANTIATE(M_FWD, false, false)
-HV_INSTANTIATE(M_REV, false, false)
-HV_INSTANTIATE(M_HAM, false, false)
-HV_INSTANTIATE(M_EXP, false, false)
-HV_INSTANTIATE(M_FWD, true, false)
-HV_INSTANTIATE(M_REV, true, false)
-HV_INSTANTIATE(M_HAM, true, false)
-HV_INSTANTIATE(M_EXP, true, false)
+#define HV_INSTANTIATE(MODE, GEN, FULL, NT)                                                   \
+    template __global__ void k_pass<MODE, GEN, FULL, NT>(                                       \
+        DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,             \
+        const DevModel *, double2 *, double2 *, double *, int);
+#define HV_INSTANTIATE_ALL(GEN, FULL)                                                           \
+    HV_INSTANTIATE(M_FWD, GEN, FULL, 1)                                                         \
+    HV_INSTANTIATE(M_REV, GEN, FULL, 1)                                                         \
+    HV_INSTANTIATE(M_HAM, GEN, FULL, 1)                                                         \
+    HV_INSTANTIATE(M_EXP, GEN, FULL, 1)
+HV_INSTANTIATE_ALL(false, true)
+HV_INSTANTIATE_ALL(true, true)
+HV_INSTANTIATE_ALL(false, false)
+HV_INSTANTIATE_ALL(true, false)
+// two tiles per iteration: forward passes over full tiles, U-only models
+// (the general diagonal's per-amplitude sincos needs the registers)
+HV_INSTANTIATE(M_FWD, false, true, 2)
+#undef HV_INSTANTIATE_ALL
 #undef HV_INSTANTIATE
 
 // ------------------------------------------------------------ misc kernels --
