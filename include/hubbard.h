@@ -160,23 +160,29 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
 
 /* Batched energy and gradient of many independent instances (different
  * lattices, sizes, U, disorder, V and layer counts; each its own parameters)
- * in one persistent launch: every workgroup claims whole instances, largest
- * first, and runs the instance's circuit, H|psi> and adjoint sweep itself.
+ * with no host work per call: a fixed sequence of launches on `stream` -- the
+ * start states of all instances, then, for each position j of the forward, H
+ * and reverse schedules, one launch that runs pass j of every instance that
+ * has one (a large instance's tiles spread over many workgroups), then one
+ * reduction of the partial sums into E and the gradients, in a fixed order
+ * (results are reproducible run to run).
  *   hs[i]           instance handles (n >= 1)
  *   theta_dev       all parameters, instance i's n_layers[i]*params_per_layer
  *                   values starting at theta_dev + theta_off[i] (device)
  *   theta_off, n_layers  host arrays of n entries
  *   E_dev[i]        energy of instance i (device, n doubles)
  *   grad_dev        gradient of instance i at grad_dev + theta_off[i] (device)
- *   ws_dev          hubbard_batch_workspace_size bytes (device): a work counter
- *                   and each instance's psi and lambda
- * The first call with a given set of pointers and sizes plans the batch and
- * uploads its tables (it must not be under graph capture); later calls only
- * launch two kernels (a counter reset and the batch kernel) and may be
- * captured into a graph and replayed with new theta values in place.
+ *   ws_dev          hubbard_batch_workspace_size bytes (device): each
+ *                   instance's psi and lambda, then the partial sums
+ * The first call with a given set of handles, layer counts, offsets, theta
+ * and workspace pointers plans the batch and uploads its tables (it must not
+ * be under graph capture); later calls only launch kernels, allocate
+ * nothing, and may be captured into a graph and replayed with new theta
+ * values in place.
  * Errors: HUBBARD_ERR_ARG, HUBBARD_ERR_SIZE (workspace), HUBBARD_ERR_STATE
  * (first call under capture), HUBBARD_ERR_DEVICE. */
-hubbard_status hubbard_batch_workspace_size(const hubbard_t *hs, int32_t n, size_t *bytes);
+hubbard_status hubbard_batch_workspace_size(const hubbard_t *hs, int32_t n,
+                                            const int32_t *n_layers, size_t *bytes);
 hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *theta_dev,
                                  const int64_t *theta_off, const int32_t *n_layers,
                                  double *E_dev, double *grad_dev, void *ws_dev, size_t ws_bytes,

@@ -85,7 +85,7 @@ def lib() -> ctypes.CDLL:
             "hubbard_get_tiles": ([vp, P(i32)], st),
             "hubbard_tune": ([vp, i32, vp, vp, ctypes.c_size_t, vp, i32, P(i32), i32, P(i32),
                               P(ctypes.c_float)], st),
-            "hubbard_batch_workspace_size": ([P(vp), i32, P(ctypes.c_size_t)], st),
+            "hubbard_batch_workspace_size": ([P(vp), i32, P(i32), P(ctypes.c_size_t)], st),
             "energy_grad_batch": ([P(vp), i32, vp, P(i64), P(i32), vp, vp, vp, ctypes.c_size_t,
                                    vp], st),
             "hubbard_phase_ms": ([vp, P(ctypes.c_float), P(ctypes.c_float),
@@ -240,9 +240,12 @@ def _handles(hs):
     return arr
 
 
-def hubbard_batch_workspace_size(hs) -> int:
+def hubbard_batch_workspace_size(hs, n_layers) -> int:
+    lay = np.ascontiguousarray(n_layers, dtype=np.int32)
     b = ctypes.c_size_t()
-    _check(lib().hubbard_batch_workspace_size(_handles(hs), len(hs), ctypes.byref(b)))
+    _check(lib().hubbard_batch_workspace_size(_handles(hs), len(hs),
+                                              lay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                              ctypes.byref(b)))
     return b.value
 
 

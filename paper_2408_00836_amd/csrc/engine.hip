@@ -22,8 +22,11 @@ template <int MODE, bool GEN, bool FULL, int NT>
 __global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,
                        const DevModel *, double2 *, double2 *, double *, int);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t);
-__global__ void k_batch(const DevInstance *, const DevPass *, int, unsigned int *);
-__global__ void k_fill_u32(unsigned int *, unsigned int, int);
+__global__ void k_batch_init(const DevInstance *);
+template <int MODE>
+__global__ void k_batch_pass(const DevInstance *, const DevPass *, const DevWork *, double *);
+__global__ void k_reduce_seg(const double *, const int32_t *, const int64_t *, const int32_t *,
+                             const double *, const int64_t *, int, double *, double *);
 __global__ void k_reduce(const double *, int, const int32_t *, const int32_t *, const int32_t *,
                          const double *, double *, double *, int);
 }  // namespace hv
@@ -69,8 +72,9 @@ struct Program {
     double *d_scale = nullptr;
     int n_rows = 0, n_out = 0;
     size_t partial_bytes = 0;
-    // host copies (introspection)
+    // host copies (introspection, batch layout)
     std::vector<HostPass> h_fwd, h_ham, h_rev, h_exp;
+    std::vector<int> row_param;   // per reduction row: parameter, or -1 for the energy
     ~Program()
     {
         (void)hipFree(d_ops);
@@ -369,10 +373,9 @@ void plan_program(hubbard_model *h, int kind, int layers, int smem_limit, Progra
         pr.h_exp = plan_hamiltonian(m, h->fwd_tc);
 }
 
-hubbard_status upload_program(hubbard_model *h, DeviceState &ds, Program &pr)
+// Device-form pass lists of a planned program (no device work).
+void build_lists(Builder &b, Program &pr)
 {
-    const Model &m = h->m;
-    Builder b(m);
     pr.fwd = b.add(pr.h_fwd, 0, false, true);
     pr.ham = b.add(pr.h_ham, pr.kind == PROG_GRAD ? 2 : 0, true);
     pr.rev = b.add(pr.h_rev, 1, false);
@@ -381,6 +384,14 @@ hubbard_status upload_program(hubbard_model *h, DeviceState &ds, Program &pr)
     set_smem(pr.ham, false);
     set_smem(pr.rev, false);
     set_smem(pr.exp, true);
+    pr.row_param.assign(b.row_param.begin(), b.row_param.end());
+}
+
+hubbard_status upload_program(hubbard_model *h, DeviceState &ds, Program &pr)
+{
+    const Model &m = h->m;
+    Builder b(m);
+    build_lists(b, pr);
     int lim = max_smem_per_block();
     for (const PassList *l : {&pr.fwd, &pr.ham, &pr.rev, &pr.exp})
         if (max_of(*l) > lim)
@@ -652,140 +663,253 @@ void mark(hubbard_model *h, int i, hipStream_t s)
 
 // ================================================================ batch
 
+// Work items per instance pass: enough to spread a large instance over many
+// workgroups, few enough that each item streams several tiles.
+constexpr int kBatchItems = 64;
+
+struct BatchLaunch {
+    int mode;               // M_FWD, M_HAM or M_REV
+    int item0, n_items;     // work items [item0, item0 + n_items)
+    int threads, smem;
+};
+
+// Host layout of a batched evaluation, derived from the instances' programs
+// only: every instance's passes in one array, the work items of each launch
+// (launch j of a schedule runs pass j of every instance that has one), the
+// workspace offsets, and for every output (energies first, then gradient
+// entries) the segments of partial sums that the final reduction adds.
+struct BatchLayout {
+    std::vector<DevPass> passes;
+    std::vector<DevWork> work;
+    std::vector<BatchLaunch> launches;
+    std::vector<int32_t> seg_ptr{0}, seg_cnt;
+    std::vector<int64_t> seg_off;
+    std::vector<double> scale;
+    std::vector<int64_t> out_idx;
+    std::vector<size_t> voff;   // byte offset of instance i's psi (lambda follows)
+    size_t partial_at = 0;      // byte offset of the partial sums
+    size_t n_partial = 0;       // doubles
+    size_t ws_bytes = 0;
+};
+
+hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
+                            const std::vector<const Program *> &progs, BatchLayout &L)
+{
+    const int lim = max_smem_per_block();
+    size_t at = 0;
+    L.voff.resize(n);
+    for (int i = 0; i < n; ++i) {
+        L.voff[i] = at;
+        at += 2 * align256(vec_bytes(hs[i]));
+    }
+    L.partial_at = at;
+    // outputs: E of every instance, then each instance's gradient
+    std::vector<size_t> gbase(n);
+    size_t n_out = n;
+    for (int i = 0; i < n; ++i) {
+        gbase[i] = n_out;
+        n_out += (size_t)progs[i]->layers * hs[i]->m.params_per_layer();
+    }
+    std::vector<std::vector<std::pair<int64_t, int32_t>>> segs(n_out);
+    L.scale.assign(n_out, 2.0);
+    L.out_idx.resize(n_out);
+    for (int i = 0; i < n; ++i) {
+        L.scale[i] = 1.0;
+        L.out_idx[i] = i;
+        const size_t P = (size_t)progs[i]->layers * hs[i]->m.params_per_layer();
+        for (size_t p = 0; p < P; ++p)
+            L.out_idx[gbase[i] + p] = toff[i] + (int64_t)p;
+    }
+    // pass arrays: per instance its forward, H and reverse passes
+    std::vector<size_t> pbase(n);
+    for (int i = 0; i < n; ++i) {
+        pbase[i] = L.passes.size();
+        for (const PassList *pl : {&progs[i]->fwd, &progs[i]->ham, &progs[i]->rev})
+            L.passes.insert(L.passes.end(), pl->pass.begin(), pl->pass.end());
+    }
+    const int modes[3] = {M_FWD, M_HAM, M_REV};
+    for (int ph = 0; ph < 3; ++ph) {
+        size_t longest = 0;
+        for (int i = 0; i < n; ++i) {
+            const PassList &pl = ph == 0 ? progs[i]->fwd : ph == 1 ? progs[i]->ham : progs[i]->rev;
+            longest = std::max(longest, pl.pass.size());
+        }
+        for (size_t j = 0; j < longest; ++j) {
+            BatchLaunch bl;
+            bl.mode = modes[ph];
+            bl.item0 = (int)L.work.size();
+            bl.threads = 64;
+            std::vector<const DevPass *> used;
+            for (int i = 0; i < n; ++i) {
+                const Program &pr = *progs[i];
+                const PassList &pl = ph == 0 ? pr.fwd : ph == 1 ? pr.ham : pr.rev;
+                if (j >= pl.pass.size())
+                    continue;
+                const DevPass &P = pl.pass[j];
+                const size_t off = (ph == 0 ? 0 : ph == 1 ? pr.fwd.pass.size()
+                                                           : pr.fwd.pass.size() + pr.ham.pass.size());
+                const uint64_t ntiles = (uint64_t)1 << P.nfree;
+                const uint32_t items = (uint32_t)std::min<uint64_t>(ntiles, kBatchItems);
+                const uint32_t per = (uint32_t)(ntiles / items);
+                const int nred = P.n_red;
+                const size_t part0 = L.n_partial;
+                L.n_partial += (size_t)nred * items;
+                for (int r = 0; r < nred; ++r) {
+                    const int prm = pr.row_param[P.red_base + r];
+                    const size_t o = prm < 0 ? (size_t)i : gbase[i] + (size_t)prm;
+                    segs[o].push_back({(int64_t)(part0 + (size_t)r * items), (int32_t)items});
+                }
+                for (uint32_t b = 0; b < items; ++b) {
+                    DevWork w;
+                    std::memset(&w, 0, sizeof(w));
+                    w.inst = i;
+                    w.pass = (int32_t)(pbase[i] + off + j);
+                    w.tile0 = b * per;
+                    w.tile1 = (b + 1) * per;
+                    w.part = (int64_t)(part0 + b);
+                    w.stride = (int32_t)items;
+                    L.work.push_back(w);
+                }
+                bl.threads = std::max(bl.threads, 1 << P.tbits);
+                used.push_back(&P);
+            }
+            bl.n_items = (int)L.work.size() - bl.item0;
+            bl.smem = 0;
+            for (const DevPass *P : used)
+                bl.smem = std::max(bl.smem, (int)smem_plan(P->k, P->n_ops, P->n_diag, P->n_red,
+                                                           P->n_phases, bl.threads, P->nfree == 0)
+                                                .total);
+            if (bl.smem > lim)
+                return fail(HUBBARD_ERR_ARG,
+                            "a batch instance needs more LDS than a workgroup may use");
+            if (bl.n_items > 0)
+                L.launches.push_back(bl);
+        }
+    }
+    for (size_t o = 0; o < n_out; ++o) {
+        for (const auto &sg : segs[o]) {
+            L.seg_off.push_back(sg.first);
+            L.seg_cnt.push_back(sg.second);
+        }
+        L.seg_ptr.push_back((int32_t)L.seg_off.size());
+    }
+    L.ws_bytes = L.partial_at + align256(std::max<size_t>(L.n_partial, 1) * sizeof(double));
+    return HUBBARD_OK;
+}
+
+// Host-only programs of a batch (plans and pass lists, no device tables).
+hubbard_status batch_host_programs(const hubbard_t *hs, int n, const int32_t *layers,
+                                   std::vector<std::unique_ptr<Program>> &own,
+                                   std::vector<const Program *> &progs)
+{
+    for (int i = 0; i < n; ++i) {
+        std::unique_ptr<Program> pr(new Program());
+        try {
+            plan_program(hs[i], PROG_GRAD, layers[i], max_smem_per_block(), *pr);
+            Builder b(hs[i]->m);
+            build_lists(b, *pr);
+        } catch (const std::exception &ex) {
+            return fail(HUBBARD_ERR_NOMEM, std::string("planning: ") + ex.what());
+        }
+        progs.push_back(pr.get());
+        own.push_back(std::move(pr));
+    }
+    return HUBBARD_OK;
+}
+
 struct BatchProgram {
-    std::vector<std::unique_ptr<Program>> progs;
+    BatchLayout L;
     DevInstance *d_inst = nullptr;
     DevPass *d_passes = nullptr;
-    int n = 0, grid = 1, threads = 64, smem = 0;
-    size_t ws_need = 0;
+    DevWork *d_work = nullptr;
+    int32_t *d_seg_ptr = nullptr, *d_seg_cnt = nullptr;
+    int64_t *d_seg_off = nullptr, *d_out_idx = nullptr;
+    double *d_scale = nullptr;
+    int n = 0, init_y = 1;
     ~BatchProgram()
     {
         (void)hipFree(d_inst);
         (void)hipFree(d_passes);
+        (void)hipFree(d_work);
+        (void)hipFree(d_seg_ptr);
+        (void)hipFree(d_seg_cnt);
+        (void)hipFree(d_seg_off);
+        (void)hipFree(d_out_idx);
+        (void)hipFree(d_scale);
     }
 };
 
 std::mutex g_batch_mu;
 std::map<std::string, std::unique_ptr<BatchProgram>> g_batches;
 
-size_t batch_ws_bytes(const hubbard_t *hs, int n)
-{
-    size_t need = 256;   // work counter
-    for (int i = 0; i < n; ++i)
-        need += 2 * align256(vec_bytes(hs[i]));
-    return need;
-}
-
 hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, const int64_t *toff,
-                           const int32_t *layers, double *E, double *grad, char *ws,
-                           BatchProgram &bp)
+                           const int32_t *layers, char *ws, BatchProgram &bp)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return fail(HUBBARD_ERR_DEVICE, "no current device");
-    const int lim = max_smem_per_block();
     bp.n = n;
-    bp.ws_need = batch_ws_bytes(hs, n);
+    // the instances' device programs (cached per handle, device and layer count)
+    std::vector<const Program *> progs(n);
     std::vector<DevInstance> insts(n);
-    std::vector<DevPass> allp;
-    std::vector<double> cost(n);
-    // per-instance vectors in the workspace, in argument order
-    std::vector<size_t> voff(n);
-    size_t at = 256;
+    uint64_t max_dim = 1;
     for (int i = 0; i < n; ++i) {
-        voff[i] = at;
-        at += 2 * align256(vec_bytes(hs[i]));
-    }
-    int threads = 64;
-    for (int i = 0; i < n; ++i) {
-        hubbard_model *h = hs[i];
-        std::unique_ptr<Program> pr(new Program());
-        {
-            std::lock_guard<std::mutex> lk(h->mu);
-            DeviceState &ds = h->dev[dev];
-            hubbard_status st = ensure_model(h, dev, ds);
-            if (st != HUBBARD_OK)
-                return st;
-            try {
-                plan_program(h, PROG_GRAD, layers[i], lim, *pr);
-            } catch (const std::exception &ex) {
-                return fail(HUBBARD_ERR_NOMEM, std::string("planning: ") + ex.what());
-            }
-            st = upload_program(h, ds, *pr);
-            if (st != HUBBARD_OK)
-                return st;
-            DevInstance &I = insts[i];
-            std::memset(&I, 0, sizeof(I));
-            I.model = ds.d_model;
-        }
+        Program *pr;
+        DeviceState *ds;
+        hubbard_status st = get_program(hs[i], PROG_GRAD, layers[i], &pr, &ds);
+        if (st != HUBBARD_OK)
+            return st;
+        progs[i] = pr;
         DevInstance &I = insts[i];
-        I.n_fwd = (int)pr->fwd.pass.size();
-        I.n_ham = (int)pr->ham.pass.size();
-        I.n_rev = (int)pr->rev.pass.size();
+        std::memset(&I, 0, sizeof(I));
         I.general = pr->general ? 1 : 0;
-        I.n_params = layers[i] * h->m.params_per_layer();
-        I.dim = (uint64_t)1 << h->m.nq;
-        I.neel = h->m.neel;
+        I.dim = (uint64_t)1 << hs[i]->m.nq;
+        I.neel = hs[i]->m.neel;
         I.phases = pr->d_phases;
         I.ops = pr->d_ops;
         I.vb = pr->d_vb;
-        I.row_param = pr->d_row_param;
+        I.model = ds->d_model;
         I.theta = theta + toff[i];
-        I.grad = grad + toff[i];
-        I.E = E + i;
-        I.psi = ws + voff[i];
-        I.lam = ws + voff[i] + align256(vec_bytes(h));
-        I.pass_begin = (int)allp.size();
-        int tb = 0;
-        for (const PassList *l : {&pr->fwd, &pr->ham, &pr->rev})
-            for (const DevPass &P : l->pass) {
-                allp.push_back(P);
-                tb = std::max(tb, P.tbits);
-            }
-        I.tbits = tb;
-        threads = std::max(threads, 1 << tb);
-        cost[i] = (double)I.dim * (I.n_fwd + I.n_ham + 2.0 * I.n_rev) + 1.0;
-        bp.progs.push_back(std::move(pr));
+        max_dim = std::max(max_dim, I.dim);
     }
-    // LDS: the widest pass of any instance, with this launch's block size
-    int smem = 0;
-    for (const DevPass &P : allp) {
-        const int nred = P.n_red > 0 ? P.n_red : 1;
-        smem = std::max(smem, (int)smem_plan(P.k, P.n_ops, P.n_diag, nred, P.n_phases, threads,
-                                             P.nfree == 0)
-                                  .total);
+    hubbard_status st = batch_layout(hs, n, toff, progs, bp.L);
+    if (st != HUBBARD_OK)
+        return st;
+    for (int i = 0; i < n; ++i) {
+        insts[i].psi = ws + bp.L.voff[i];
+        insts[i].lam = ws + bp.L.voff[i] + align256(vec_bytes(hs[i]));
     }
-    smem += 16;   // the batch kernel's work-claim word
-    if (smem > lim)
-        return fail(HUBBARD_ERR_ARG, "a batch instance needs more LDS than a workgroup may use");
-    bp.threads = threads;
-    bp.smem = smem;
-    // largest instances first: they are claimed first from the work counter
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i)
-        order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    std::vector<DevInstance> sorted(n);
-    for (int i = 0; i < n; ++i)
-        sorted[i] = insts[order[i]];
-    int cus = 0, per_cu = 0;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lim) != hipSuccess)
-        return fail(HUBBARD_ERR_DEVICE, "setting the batch kernel's LDS limit");
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch, threads,
-                                                     smem) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    bp.grid = std::max(1, std::min(n, std::max(cus, 1) * per_cu));
-    hipError_t e = hipMalloc((void **)&bp.d_inst, std::max<size_t>(16, n * sizeof(DevInstance)));
+    bp.init_y = (int)std::min<uint64_t>(64, (max_dim + 255) / 256);
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        const int lim = max_smem_per_block();
+        const void *fns[] = {(const void *)k_batch_pass<M_FWD>, (const void *)k_batch_pass<M_HAM>,
+                             (const void *)k_batch_pass<M_REV>};
+        for (const void *f : fns)
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    });
+    auto up = [](void **dst, const void *src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+        if (e == hipSuccess && bytes)
+            e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        return e;
+    };
+    const BatchLayout &L = bp.L;
+    hipError_t e = up((void **)&bp.d_inst, insts.data(), insts.size() * sizeof(DevInstance));
     if (e == hipSuccess)
-        e = hipMemcpy(bp.d_inst, sorted.data(), n * sizeof(DevInstance), hipMemcpyHostToDevice);
+        e = up((void **)&bp.d_passes, L.passes.data(), L.passes.size() * sizeof(DevPass));
     if (e == hipSuccess)
-        e = hipMalloc((void **)&bp.d_passes, std::max<size_t>(16, allp.size() * sizeof(DevPass)));
-    if (e == hipSuccess && !allp.empty())
-        e = hipMemcpy(bp.d_passes, allp.data(), allp.size() * sizeof(DevPass),
-                      hipMemcpyHostToDevice);
+        e = up((void **)&bp.d_work, L.work.data(), L.work.size() * sizeof(DevWork));
+    if (e == hipSuccess)
+        e = up((void **)&bp.d_seg_ptr, L.seg_ptr.data(), L.seg_ptr.size() * sizeof(int32_t));
+    if (e == hipSuccess)
+        e = up((void **)&bp.d_seg_cnt, L.seg_cnt.data(), L.seg_cnt.size() * sizeof(int32_t));
+    if (e == hipSuccess)
+        e = up((void **)&bp.d_seg_off, L.seg_off.data(), L.seg_off.size() * sizeof(int64_t));
+    if (e == hipSuccess)
+        e = up((void **)&bp.d_out_idx, L.out_idx.data(), L.out_idx.size() * sizeof(int64_t));
+    if (e == hipSuccess)
+        e = up((void **)&bp.d_scale, L.scale.data(), L.scale.size() * sizeof(double));
     if (e != hipSuccess)
         return fail(HUBBARD_ERR_DEVICE, std::string("uploading batch: ") + hipGetErrorString(e));
     return HUBBARD_OK;
@@ -1007,14 +1131,25 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
     return run_reduce(*pr, partial, E_dev, grad_dev, s);
 }
 
-hubbard_status hubbard_batch_workspace_size(const hubbard_t *hs, int32_t n, size_t *bytes)
+hubbard_status hubbard_batch_workspace_size(const hubbard_t *hs, int32_t n,
+                                            const int32_t *n_layers, size_t *bytes)
 {
-    if (!hs || n < 1 || !bytes)
+    if (!hs || n < 1 || !n_layers || !bytes)
         return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_batch_workspace_size");
     for (int i = 0; i < n; ++i)
-        if (!hs[i])
-            return fail(HUBBARD_ERR_ARG, "NULL handle in batch");
-    *bytes = batch_ws_bytes(hs, n);
+        if (!hs[i] || n_layers[i] < 0)
+            return fail(HUBBARD_ERR_ARG, "bad instance " + std::to_string(i) + " in batch");
+    std::vector<std::unique_ptr<Program>> own;
+    std::vector<const Program *> progs;
+    hubbard_status st = batch_host_programs(hs, n, n_layers, own, progs);
+    if (st != HUBBARD_OK)
+        return st;
+    std::vector<int64_t> toff(n, 0);
+    BatchLayout L;
+    st = batch_layout(hs, n, toff.data(), progs, L);
+    if (st != HUBBARD_OK)
+        return st;
+    *bytes = L.ws_bytes;
     return HUBBARD_OK;
 }
 
@@ -1029,13 +1164,10 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
         if (!hs[i] || n_layers[i] < 0 || theta_off[i] < 0)
             return fail(HUBBARD_ERR_ARG, "bad instance " + std::to_string(i) + " in batch");
     }
-    if (ws_bytes < batch_ws_bytes(hs, n))
-        return fail(HUBBARD_ERR_SIZE, "workspace too small for energy_grad_batch");
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::string key = std::to_string(dev) + ":" + std::to_string((uintptr_t)theta_dev) + ":" +
-                      std::to_string((uintptr_t)E_dev) + ":" + std::to_string((uintptr_t)grad_dev) +
-                      ":" + std::to_string((uintptr_t)ws_dev);
+                      std::to_string((uintptr_t)ws_dev);
     for (int i = 0; i < n; ++i)
         key += ":" + std::to_string((uintptr_t)hs[i]) + "/" + std::to_string(n_layers[i]) + "/" +
                std::to_string(theta_off[i]);
@@ -1050,22 +1182,36 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
                 return fail(HUBBARD_ERR_STATE, "first call of a batch must happen outside graph "
                                                "capture (it uploads the batch tables)");
             std::unique_ptr<BatchProgram> nb(new BatchProgram());
-            hubbard_status st = build_batch(hs, n, theta_dev, theta_off, n_layers, E_dev,
-                                            grad_dev, (char *)ws_dev, *nb);
+            hubbard_status st = build_batch(hs, n, theta_dev, theta_off, n_layers,
+                                            (char *)ws_dev, *nb);
             if (st != HUBBARD_OK)
                 return st;
             it = g_batches.emplace(key, std::move(nb)).first;
         }
         bp = it->second.get();
     }
-    unsigned int *counter = (unsigned int *)ws_dev;
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 0u, 1);
-    hipLaunchKernelGGL(k_batch, dim3(bp->grid), dim3(bp->threads), bp->smem, s, bp->d_inst,
-                       bp->d_passes, bp->n, counter);
+    const BatchLayout &L = bp->L;
+    if (ws_bytes < L.ws_bytes)
+        return fail(HUBBARD_ERR_SIZE, "workspace too small for energy_grad_batch");
+    double *partial = (double *)((char *)ws_dev + L.partial_at);
+    hipLaunchKernelGGL(k_batch_init, dim3(n, bp->init_y), dim3(256), 0, s, bp->d_inst);
+    for (const BatchLaunch &bl : L.launches) {
+        const DevWork *w = bp->d_work + bl.item0;
+        if (bl.mode == M_FWD)
+            hipLaunchKernelGGL(k_batch_pass<M_FWD>, dim3(bl.n_items), dim3(bl.threads), bl.smem,
+                               s, bp->d_inst, bp->d_passes, w, partial);
+        else if (bl.mode == M_HAM)
+            hipLaunchKernelGGL(k_batch_pass<M_HAM>, dim3(bl.n_items), dim3(bl.threads), bl.smem,
+                               s, bp->d_inst, bp->d_passes, w, partial);
+        else
+            hipLaunchKernelGGL(k_batch_pass<M_REV>, dim3(bl.n_items), dim3(bl.threads), bl.smem,
+                               s, bp->d_inst, bp->d_passes, w, partial);
+    }
+    hipLaunchKernelGGL(k_reduce_seg, dim3((unsigned)L.scale.size()), dim3(256), 0, s, partial,
+                       bp->d_seg_ptr, bp->d_seg_off, bp->d_seg_cnt, bp->d_scale, bp->d_out_idx, n,
+                       E_dev, grad_dev);
     return check_launch("batch");
 }
-
-// ------------------------------------------------------- introspection --
 
 hubbard_status hubbard_plan_dump(hubbard_t h, int32_t n_layers, int32_t which, int32_t *buf,
                                  int64_t cap, int64_t *len)

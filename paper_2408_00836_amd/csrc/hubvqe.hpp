@@ -110,24 +110,30 @@ struct DevPass {
     int32_t pad2[2];
 };
 
-// One instance of a batched energy+gradient launch: its passes (forward, H,
-// reverse) live at pass_begin in the batch's pass array; every pointer is a
-// device pointer.  row_param maps the instance's reduction rows to outputs
-// (-1: the energy, p >= 0: gradient entry p).
+// One instance of a batched energy+gradient evaluation: its model tables,
+// parameters and state vectors (every pointer is a device pointer).
 struct DevInstance {
-    int32_t n_fwd, n_ham, n_rev, general;
-    int32_t pass_begin, n_params;
-    int32_t tbits, pad;
+    int32_t general;        // diagonal has eps or V terms
+    int32_t pad;
     uint64_t dim, neel;
     const struct DevPhase *phases;
     const struct DevOp *ops;
     const struct DevVBond *vb;
     const struct DevModel *model;
-    const int32_t *row_param;
     const double *theta;
     void *psi, *lam;
-    double *E, *grad;
 };
+
+// One work item of a batched pass launch: tiles [tile0, tile1) of pass
+// `pass` of instance `inst`; its reduction row r goes to
+// partial[part + r * stride].
+struct DevWork {
+    int32_t inst, pass;
+    uint32_t tile0, tile1;
+    int64_t part;
+    int32_t stride, pad;
+};
+static_assert(sizeof(DevWork) == 32, "DevWork layout");
 
 // Model constants in device memory.
 struct DevModel {

@@ -256,14 +256,12 @@ __device__ __forceinline__ double quad_sum(double x)
     return x;
 }
 
-// Where a pass's reduction rows go: the partial array of the two-stage
-// reduction (row r, block b at partial[(red_base + r) * stride + b]), or, for
-// a batched instance, straight into its outputs (row_param != nullptr).
+// Where a workgroup's reduction rows go: row r of the pass at
+// base[r * stride] (a column of the partial array that a second-stage
+// reduction sums in a fixed order).
 struct Sink {
-    double *partial;
-    int stride, block;
-    const int32_t *row_param;
-    double *E, *grad;
+    double *base;     // row 0 of this workgroup's partial column
+    int64_t stride;   // distance between rows
 };
 
 // Sum of x over the workgroup, valid in thread 0 (fixed shuffle tree, then
@@ -309,12 +307,12 @@ __device__ __forceinline__ uint32_t tile_advance(uint32_t base, uint32_t step_de
     return (uint32_t)((((uint64_t)(base | ~free_mask)) + step_dep) & free_mask);
 }
 
-// One pass over the tiles [tile0, 2^nfree) with stride tstep.  FULL: all
+// One pass over the tiles [tile0, tile_end) with stride tstep.  FULL: all
 // threads own amplitudes and all 16 registers hold one (tiles of >= 16
 // amplitudes launched with exactly 2^tbits threads): no per-register guards.
-// NT = 2 (forward and expectation passes only): every iteration takes the
-// tiles tl and tl + tstep, which needs 2^nfree to be a multiple of 2 tstep;
-// the op stream is then decoded once for two tiles.
+// NT = 2 (forward passes only): every iteration takes the tiles tl and
+// tl + tstep, which needs tile_end - tile0 to be a multiple of 2 tstep; the
+// op stream is then decoded once for two tiles.
 template <int MODE, bool GEN, bool FULL, int NT>
 __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__restrict__ phases,
                                          const DevOp *__restrict__ ops,
@@ -322,7 +320,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                                          const double *__restrict__ theta,
                                          const DevModel *__restrict__ M, double2 *__restrict__ v0,
                                          double2 *__restrict__ v1, char *smem, uint64_t tile0,
-                                         uint64_t tstep, const Sink &sink)
+                                         uint64_t tstep, uint64_t tile_end, const Sink &sink)
 {
     constexpr int NV = (MODE == M_FWD || MODE == M_EXP) ? 1 : 2;   // vectors per tile
     constexpr int NS = NT * NV;                                     // register sets
@@ -386,7 +384,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     __syncthreads();
     double *wsum = red + n_red * R;
 
-    const uint64_t ntiles = (uint64_t)1 << P.nfree;
+    const uint64_t ntiles = tile_end;
     const uint32_t valid = FULL ? 0xFFFFu : ph[0].valid;
     const uint32_t step_dep = pdep32((uint32_t)tstep, P.free_mask);
     double eacc = 0.0;
@@ -597,18 +595,8 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     }
     if (tid == 0) {
         const int rstride = (MODE == M_EXP || MODE == M_HAM || single) ? 1 : R;
-        for (int r = 0; r < n_red; ++r) {
-            const double val = red[r * rstride];
-            if (sink.row_param) {
-                const int prm = sink.row_param[P.red_base + r];
-                if (prm < 0)
-                    sink.E[0] = val;
-                else
-                    sink.grad[prm] += 2.0 * val;
-            } else {
-                sink.partial[(size_t)(P.red_base + r) * sink.stride + sink.block] = val;
-            }
-        }
+        for (int r = 0; r < n_red; ++r)
+            sink.base[r * sink.stride] = red[r * rstride];
     }
     __syncthreads();
 }
@@ -621,75 +609,82 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
        double *__restrict__ partial, int stride)
 {
     extern __shared__ __align__(16) char smem[];
-    Sink sink{partial, stride, (int)blockIdx.x, nullptr, nullptr, nullptr};
+    const Sink sink{partial + (size_t)P.red_base * stride + blockIdx.x, stride};
     run_pass<MODE, GEN, FULL, NT>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x,
-                                  gridDim.x, sink);
+                                  gridDim.x, (uint64_t)1 << P.nfree, sink);
 }
 
-// Persistent batch kernel: each workgroup claims whole instances from a
-// work counter (instances are listed largest first) and runs the instance's
-// initial state, forward passes, H passes and reverse passes itself, looping
-// over all tiles of every pass, so no synchronisation between workgroups is
-// needed.  Results go straight into the instance's E and gradient.  The
-// counter must be zero at launch (k_fill_u32 before this kernel).
+// ------------------------------------------------------------------ batch --
+// A batched evaluation is a sequence of launches: the start states of all
+// instances, then one launch per pass index of the forward, H and reverse
+// schedules, each running that pass of every instance that has one, with
+// each instance's tiles split into work items over many workgroups, and a
+// final reduction of the partial rows.  No workgroup waits for another.
+
+__global__ void k_batch_init(const DevInstance *__restrict__ inst)
+{
+    const DevInstance I = inst[blockIdx.x];
+    double2 *psi = (double2 *)I.psi;
+    const uint64_t stride = (uint64_t)gridDim.y * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; b < I.dim; b += stride)
+        psi[b] = make_double2(b == I.neel ? 1.0 : 0.0, 0.0);
+}
+
+template <int MODE>
 __global__ void __launch_bounds__(512)
-k_batch(const DevInstance *__restrict__ inst, const DevPass *__restrict__ passes, int n_inst,
-        unsigned int *__restrict__ counter)
+k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ passes,
+             const DevWork *__restrict__ work, double *__restrict__ partial)
 {
-    extern __shared__ __align__(16) char smem_all[];
-    int *claim = (int *)smem_all;   // first 16 bytes; the passes use the rest
-    char *smem = smem_all + 16;
-    const int T = blockDim.x, tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0)
-            *claim = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int i = *claim;
-        __syncthreads();
-        if (i >= n_inst)
-            break;
-        const DevInstance I = inst[i];
-        double2 *psi = (double2 *)I.psi, *lam = (double2 *)I.lam;
-        for (uint64_t b = tid; b < I.dim; b += T)
-            psi[b] = make_double2(b == I.neel ? 1.0 : 0.0, 0.0);
-        for (int p = tid; p < I.n_params; p += T)
-            I.grad[p] = 0.0;
-        __syncthreads();
-        Sink sink{nullptr, 0, 0, I.row_param, I.E, I.grad};
-        const DevPass *ps = passes + I.pass_begin;
-        for (int p = 0; p < I.n_fwd; ++p) {
-            if (I.general)
-                run_pass<M_FWD, true, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                      smem, 0, 1, sink);
-            else
-                run_pass<M_FWD, false, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                       smem, 0, 1, sink);
-        }
-        ps += I.n_fwd;
-        for (int p = 0; p < I.n_ham; ++p) {
-            if (I.general)
-                run_pass<M_HAM, true, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                      smem, 0, 1, sink);
-            else
-                run_pass<M_HAM, false, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                       smem, 0, 1, sink);
-        }
-        ps += I.n_ham;
-        for (int p = 0; p < I.n_rev; ++p) {
-            if (I.general)
-                run_pass<M_REV, true, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                      smem, 0, 1, sink);
-            else
-                run_pass<M_REV, false, false, 1>(ps[p], I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                       smem, 0, 1, sink);
-        }
-    }
+    extern __shared__ __align__(16) char smem[];
+    const DevWork w = work[blockIdx.x];
+    const DevInstance I = inst[w.inst];
+    const DevPass P = passes[w.pass];
+    const Sink sink{partial + w.part, w.stride};
+    double2 *psi = (double2 *)I.psi, *lam = (double2 *)I.lam;
+    if (I.general)
+        run_pass<MODE, true, false, 1>(P, I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                                       smem, w.tile0, 1, w.tile1, sink);
+    else
+        run_pass<MODE, false, false, 1>(P, I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
+                                        smem, w.tile0, 1, w.tile1, sink);
 }
+template __global__ void k_batch_pass<M_FWD>(const DevInstance *, const DevPass *,
+                                              const DevWork *, double *);
+template __global__ void k_batch_pass<M_HAM>(const DevInstance *, const DevPass *,
+                                              const DevWork *, double *);
+template __global__ void k_batch_pass<M_REV>(const DevInstance *, const DevPass *,
+                                              const DevWork *, double *);
 
-__global__ void k_fill_u32(unsigned int *p, unsigned int v, int n)
+// out = scale[o] * sum over segments seg_ptr[o] .. seg_ptr[o+1] of the
+// seg_cnt[s] partials starting at seg_off[s], in a fixed order; output o goes
+// to E[out_idx[o]] for o < n_e and to grad[out_idx[o]] otherwise.
+__global__ void __launch_bounds__(256)
+k_reduce_seg(const double *__restrict__ partial, const int32_t *__restrict__ seg_ptr,
+             const int64_t *__restrict__ seg_off, const int32_t *__restrict__ seg_cnt,
+             const double *__restrict__ scale, const int64_t *__restrict__ out_idx, int n_e,
+             double *__restrict__ E, double *__restrict__ grad)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        p[i] = v;
+    __shared__ double sm[256];
+    const int o = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
+    double acc = 0.0;
+    for (int sg = seg_ptr[o]; sg < seg_ptr[o + 1]; ++sg) {
+        const double *p = partial + seg_off[sg];
+        for (int b = tid; b < seg_cnt[sg]; b += T)
+            acc += p[b];
+    }
+    sm[tid] = acc;
+    for (int st = T >> 1; st > 0; st >>= 1) {
+        __syncthreads();
+        if (tid < st)
+            sm[tid] += sm[tid + st];
+    }
+    if (tid == 0) {
+        const double v = scale[o] * sm[0];
+        if (o < n_e)
+            E[out_idx[o]] = v;
+        else
+            grad[out_idx[o]] = v;
+    }
 }
 
 #define HV_INSTANTIATE(MODE, GEN, FULL, NT)                                                   \

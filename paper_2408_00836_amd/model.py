@@ -158,8 +158,9 @@ class EnergyGrad(torch.autograd.Function):
 
 
 class Batch:
-    """Many independent instances evaluated (energy + adjoint gradient) in one
-    persistent launch.  Parameters of instance i live at
+    """Many independent instances evaluated (energy + adjoint gradient) by one
+    fixed launch sequence (one launch per schedule position for all instances
+    together, then one reduction).  Parameters of instance i live at
     theta[offsets[i] : offsets[i] + n_params[i]] of one device vector; the
     gradient uses the same layout.
 
@@ -180,7 +181,8 @@ class Batch:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         hs = [m.handle for m in self.models]
-        self.ws = torch.empty(abi.hubbard_batch_workspace_size(hs), dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(abi.hubbard_batch_workspace_size(hs, self.layers), dtype=torch.uint8,
+                              device=dev)
         self.E = torch.empty(len(self.models), dtype=torch.float64, device=dev)
         self.grad = torch.empty(max(self.total, 1), dtype=torch.float64, device=dev)
         self.theta = torch.zeros(max(self.total, 1), dtype=torch.float64, device=dev)
