@@ -62,6 +62,49 @@ def traffic_bytes(kernel, workload):
     return float(val) if val else None
 
 
+def batch_bench(torch, dev, reps=3):
+    """The batched path on 256 uneven instances (8-20 qubits, own U, disorder,
+    V and 2-10 layers each): one energy+gradient evaluation of all instances
+    as an eager launch sequence and as a graph replay, against one
+    energy_grad call per instance on the same GPU (the plain form)."""
+    import numpy as np
+    from paper_2408_00836_amd import workloads as W
+    from paper_2408_00836_amd.model import Batch, Hubbard
+    ws = W.batch(256)
+    models = [Hubbard(w.nx, w.ny, **w.kwargs()) for w in ws]
+    b = Batch(models, [w.layers for w in ws])
+    theta = torch.tensor(np.concatenate([w.theta for w in ws]), dtype=torch.float64, device=dev)
+    ths = [theta[o:o + w.n_params].contiguous() for o, w in zip(b.offsets, ws)]
+
+    def best_of(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    t_eager = best_of(lambda: b.energy_grad(theta))
+    b.capture(theta)
+    t_graph = best_of(lambda: b.replay(theta))
+
+    def per_instance():
+        for m, th in zip(models, ths):
+            m.energy_grad(th)
+    t_calls = best_of(per_instance)
+    n = len(ws)
+    return {"workload": "256 uneven instances: chains of 4-10 sites, 2x2..3x3 (8-20 qubits), "
+                        "U~U(1,8), t/eps disorder, V=0.5 on odd instances, 2-10 layers",
+            "evals_per_s": n / t_graph, "ms_per_batch_graph": t_graph * 1e3,
+            "ms_per_batch_eager": t_eager * 1e3, "ms_per_instance_calls": t_calls * 1e3,
+            "evals_per_s_instance_calls": n / t_calls, "speedup_vs_instance_calls": t_calls / t_graph,
+            "qubits": sorted({w.n_qubits for w in ws})}
+
+
 def copy_reference(torch, dev, gib=8, reps=3):
     """Bandwidth of a plain device copy (torch elementwise kernel, `gib` GiB
     read + `gib` GiB written): the practical HBM ceiling for an in-place
@@ -140,6 +183,7 @@ def main():
     ap.add_argument("--config", default="c5", choices=["c5", "c3", "c2", "c1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -247,6 +291,13 @@ def main():
     copy = copy_reference(torch, dev)
     log(f"[bench] plain copy: {copy['GBs']:.0f} GB/s")
 
+    batch = None
+    if not args.no_batch:
+        log("[bench] batch of 256 uneven instances")
+        batch = batch_bench(torch, dev)
+        log(f"[bench] batch: {batch['ms_per_batch_graph']:.1f} ms per batch (graph), "
+            f"{batch['ms_per_instance_calls']:.1f} ms as one call per instance")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (bounded sample)")
@@ -277,6 +328,7 @@ def main():
                                                     "hamiltonian": ham_ms / args.steps,
                                                     "reverse": rev_ms / args.steps}),
         "copy_reference": copy,
+        "batch": batch,
         "hpsi": {"ms": h_ms, "algorithmic_GBs": h_gbs, "frac": h_gbs / HBM_PEAK_GBS,
                  "passes": n_ham},
         "fd_plain": fd,

@@ -213,16 +213,21 @@ struct Builder {
                     o.dtab = n_diag++;
                     o.umask = h.umask;
                     o.emask = h.emask;
+                    // V bonds in classes of equal site offset and equal V
                     o.v_begin = (int)vb.size();
                     for (int b : h.vbonds) {
-                        DevVBond v;
-                        std::memset(&v, 0, sizeof(v));
-                        v.q[0] = m.qubit(m.bi[b], 0);
-                        v.q[1] = m.qubit(m.bi[b], 1);
-                        v.q[2] = m.qubit(m.bj[b], 0);
-                        v.q[3] = m.qubit(m.bj[b], 1);
-                        v.V = m.V[b];
-                        vb.push_back(v);
+                        const int delta = m.bj[b] - m.bi[b];
+                        size_t c = (size_t)o.v_begin;
+                        while (c < vb.size() && !(vb[c].delta == delta && vb[c].V == m.V[b]))
+                            ++c;
+                        if (c == vb.size()) {
+                            DevVBond v;
+                            std::memset(&v, 0, sizeof(v));
+                            v.delta = delta;
+                            v.V = m.V[b];
+                            vb.push_back(v);
+                        }
+                        vb[c].src |= 1u << m.bi[b];
                     }
                     o.v_end = (int)vb.size();
                 }
@@ -326,13 +331,13 @@ int max_smem_per_block()
     return v;
 }
 
-void set_smem(PassList &pl, bool force_red1)
+void set_smem(PassList &pl, bool force_red1, bool general)
 {
     for (size_t i = 0; i < pl.pass.size(); ++i) {
         const DevPass &P = pl.pass[i];
         int nred = force_red1 ? 1 : P.n_red;
         pl.smem[i] = (int)smem_plan(P.k, P.n_ops, P.n_diag, nred, P.n_phases, pl.threads[i],
-                                    P.nfree == 0)
+                                    P.nfree == 0, general)
                          .total;
     }
 }
@@ -363,8 +368,8 @@ void plan_program(hubbard_model *h, int kind, int layers, int smem_limit, Progra
         // check LDS fit of the two-vector kernels; shrink the tile if needed
         Builder b(m);
         PassList ph = b.add(pr.h_ham, 2, true), pv = b.add(pr.h_rev, 1, false);
-        set_smem(ph, false);
-        set_smem(pv, false);
+        set_smem(ph, false, m.general);
+        set_smem(pv, false, m.general);
         if (std::max(max_of(ph), max_of(pv)) <= smem_limit || tc2.k <= 6)
             break;
         tc2.k -= 1;
@@ -380,10 +385,10 @@ void build_lists(Builder &b, Program &pr)
     pr.ham = b.add(pr.h_ham, pr.kind == PROG_GRAD ? 2 : 0, true);
     pr.rev = b.add(pr.h_rev, 1, false);
     pr.exp = b.add(pr.h_exp, 2, false);
-    set_smem(pr.fwd, false);
-    set_smem(pr.ham, false);
-    set_smem(pr.rev, false);
-    set_smem(pr.exp, true);
+    set_smem(pr.fwd, false, pr.general);
+    set_smem(pr.ham, false, pr.general);
+    set_smem(pr.rev, false, pr.general);
+    set_smem(pr.exp, true, pr.general);
     pr.row_param.assign(b.row_param.begin(), b.row_param.end());
 }
 
@@ -486,16 +491,8 @@ hubbard_status ensure_model(hubbard_model *h, int dev, DeviceState &ds)
     dm.ns = m.ns;
     dm.general = m.general ? 1 : 0;
     dm.U = m.U;
-    for (int byte = 0; byte < 4; ++byte)
-        for (int v = 0; v < 256; ++v) {
-            double s = 0.0;
-            for (int j = 0; j < 8; ++j) {
-                int q = byte * 8 + j;
-                if (((v >> j) & 1) && q < m.nq)
-                    s += m.eps[q < m.ns ? q : q - m.ns];
-            }
-            dm.eps_byte[byte][v] = s;
-        }
+    for (int q = 0; q < kMaxQubits; ++q)
+        dm.eps_q[q] = q < m.nq ? m.eps[q < m.ns ? q : q - m.ns] : 0.0;
     hipError_t e = hipMalloc((void **)&ds.d_model, sizeof(DevModel));
     if (e == hipSuccess)
         e = hipMemcpy(ds.d_model, &dm, sizeof(DevModel), hipMemcpyHostToDevice);
@@ -777,7 +774,8 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
             bl.smem = 0;
             for (const DevPass *P : used)
                 bl.smem = std::max(bl.smem, (int)smem_plan(P->k, P->n_ops, P->n_diag, P->n_red,
-                                                           P->n_phases, bl.threads, P->nfree == 0)
+                                                           P->n_phases, bl.threads, P->nfree == 0,
+                                                           true)
                                                 .total);
             if (bl.smem > lim)
                 return fail(HUBBARD_ERR_ARG,

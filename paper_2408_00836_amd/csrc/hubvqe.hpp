@@ -84,12 +84,17 @@ struct DevPhase {
 };
 static_assert(sizeof(DevPhase) == 64, "DevPhase layout");
 
-// A V bond as the device reads it: qubits (i up, i dn, j up, j dn) and V_b.
+// A class of V bonds of one diagonal op, as the device reads it: the bonds
+// (i, i + delta) for every site i set in src, all with the same V.  With the
+// site occupation bit sets U (spin up) and D (spin down), the class adds
+// V * sum over its bonds of n_i n_j = V * (popc(U & U') + popc(U & D') +
+// popc(D & U') + popc(D & D')), X' = X shifted down by delta, masked by src.
 struct DevVBond {
-    int32_t q[4];
+    uint32_t src;
+    int32_t delta;
     double V;
-    double pad;
 };
+static_assert(sizeof(DevVBond) == 16, "DevVBond layout");
 
 // Pass descriptor, passed by value as a kernel argument.
 struct DevPass {
@@ -141,7 +146,7 @@ struct DevModel {
     int32_t general;        // 0: D = U * (#doubly occupied sites) only
     int32_t pad;
     double U;
-    double eps_byte[4][256];  // sum of eps over set qubits of each index byte
+    double eps_q[kMaxQubits];   // on-site energy of each qubit's site (0 beyond n)
 };
 
 // LDS carve-up shared by host (launch size) and device: one tile-sized
@@ -150,7 +155,7 @@ struct DevModel {
 // per-op rotation coefficients, diagonal phase tables and reduction rows.
 constexpr int kMaxWaves = 8;   // 512 threads
 struct SmemPlan {
-    uint32_t xbuf, ltab, wtab, opc, dtab, red, rows, total;
+    uint32_t xbuf, ltab, wtab, opc, dtab, etab, cis, red, rows, total;
 };
 
 // Reduction rows: a pass over many tiles keeps one accumulator per row and
@@ -162,8 +167,14 @@ __host__ __device__ inline uint32_t red_rows_per(int threads, bool single_tile)
     return single_tile ? 1u : (threads >= 4 ? (uint32_t)threads / 4u : (uint32_t)threads);
 }
 
+// General diagonal (eps or V terms): per diag op eight nibble tables of the
+// eps sum over its qubits, and one table of 2^kCisBits unit phases shared by
+// all ops of the pass.
+constexpr int kCisBits = 8;
+
 __host__ __device__ inline SmemPlan smem_plan(int k, int n_ops, int n_diag, int n_red,
-                                              int n_phases, int threads, bool single_tile)
+                                              int n_phases, int threads, bool single_tile,
+                                              bool general)
 {
     SmemPlan s;
     uint32_t at = 0;
@@ -177,6 +188,10 @@ __host__ __device__ inline SmemPlan smem_plan(int k, int n_ops, int n_diag, int 
     at += (uint32_t)n_ops * 16u;
     s.dtab = at;
     at += (uint32_t)n_diag * kDiagTab * 16u;
+    s.etab = at;
+    s.cis = at + (general ? (uint32_t)n_diag * 8u * 16u * 8u : 0u);
+    if (general && n_diag > 0)
+        at = s.cis + (1u << kCisBits) * 16u;
     s.red = at;
     s.rows = red_rows_per(threads, single_tile);
     at += (uint32_t)n_red * s.rows * 8u;

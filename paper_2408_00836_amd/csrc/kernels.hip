@@ -45,25 +45,51 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t x, uint32_t mask)
 }
 
 // Diagonal sub-term value D_sub(g); GEN: the model has eps or V terms.
+// etab: the op's eight nibble tables of its eps sum (LDS); vb: its V bond
+// classes (see DevVBond).
 template <bool GEN>
 __device__ __forceinline__ double diag_value(const DevOp &op, uint32_t g, const DevModel *M,
-                                             const DevVBond *vb)
+                                             const DevVBond *vb, const double *etab)
 {
-    uint32_t up = g & op.umask;
-    uint32_t dn = (uint32_t)((uint64_t)g >> M->ns) & op.umask;
-    double d = M->U * (double)__popc(up & dn);
+    const uint32_t dn = (uint32_t)((uint64_t)g >> M->ns);
+    double d = M->U * (double)__popc(g & dn & op.umask);
     if constexpr (GEN) {
-        uint32_t e = g & op.emask;
-        d += M->eps_byte[0][e & 255u] + M->eps_byte[1][(e >> 8) & 255u] +
-             M->eps_byte[2][(e >> 16) & 255u] + M->eps_byte[3][(e >> 24) & 255u];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            d += etab[k * 16 + ((g >> (4 * k)) & 15u)];
+        const uint32_t smask = (1u << M->ns) - 1u;
+        const uint32_t U = g & smask, D = dn & smask;
         for (int v = op.v_begin; v < op.v_end; ++v) {
-            const DevVBond &B = vb[v];
-            int ni = (int)((g >> B.q[0]) & 1u) + (int)((g >> B.q[1]) & 1u);
-            int nj = (int)((g >> B.q[2]) & 1u) + (int)((g >> B.q[3]) & 1u);
-            d += B.V * (double)(ni * nj);
+            const DevVBond B = vb[v];
+            const uint32_t Us = B.delta >= 0 ? U >> B.delta : U << -B.delta;
+            const uint32_t Ds = B.delta >= 0 ? D >> B.delta : D << -B.delta;
+            const int cnt = __popc(U & Us & B.src) + __popc(U & Ds & B.src) +
+                            __popc(D & Us & B.src) + __popc(D & Ds & B.src);
+            d += B.V * (double)cnt;
         }
     }
     return d;
+}
+
+// exp(-i x) for the general diagonal: x = k h + r with h = 2 pi / 2^kCisBits
+// (Cody-Waite reduction with a two-part h whose leading part has 36
+// significant bits, exact for |k| < 2^17), the phase of k h from the LDS
+// table cis[k mod 2^kCisBits] = (cos kh, sin kh), and cos r, sin r by their
+// Taylor series (|r| <= pi / 2^kCisBits, truncation below 1e-19).
+__device__ __forceinline__ double2 cis_neg(double x, const double2 *cis)
+{
+    constexpr double kInvH = 0x1.45f306dc9c883p+5;    // 2^kCisBits / (2 pi), kCisBits = 8
+    constexpr double kHHi = 0x1.921fb54440000p-6;     // 2 pi / 2^kCisBits, leading part
+    constexpr double kHLo = 0x1.68c234c4c6629p-45;    // remainder
+    const double k = rint(x * kInvH);
+    double r = fma(-k, kHHi, x);
+    r = fma(-k, kHLo, r);
+    const double2 t = cis[(int)k & ((1 << kCisBits) - 1)];
+    const double r2 = r * r;
+    const double c = fma(r2, fma(r2, fma(r2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    const double sr = r * fma(r2, fma(r2, fma(r2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    // cos x = cos kh cos r - sin kh sin r, sin x = sin kh cos r + cos kh sin r
+    return make_double2(t.x * c - t.y * sr, -(t.y * c + t.x * sr));
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
@@ -333,12 +359,14 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     const bool ham_last = (MODE == M_HAM) && (P.flags & PF_HAM_LAST);
     const int n_red = (MODE == M_EXP) ? 1 : P.n_red;
     const bool single = (P.nfree == 0);
-    const SmemPlan sp = smem_plan(P.k, P.n_ops, P.n_diag, n_red, P.n_phases, T, single);
+    const SmemPlan sp = smem_plan(P.k, P.n_ops, P.n_diag, n_red, P.n_phases, T, single, GEN);
     char *xbuf = smem + sp.xbuf;
     uint2 *ltab = (uint2 *)(smem + sp.ltab);
     uint2 *wtab = (uint2 *)(smem + sp.wtab);
     double2 *opc = (double2 *)(smem + sp.opc);
     double2 *dtab = (double2 *)(smem + sp.dtab);
+    double *etab = (double *)(smem + sp.etab);
+    double2 *cis = (double2 *)(smem + sp.cis);
     double *red = (double *)(smem + sp.red);
     const int R = (int)sp.rows;            // accumulators per reduction row
     const bool quad = !single && T >= 4;   // rows hold sums over four lanes
@@ -375,6 +403,29 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                         sincos(theta[op.param] * (M->U * (double)m), &s, &c);
                         dtab[op.dtab * kDiagTab + m] = make_double2(c, -sign * s);
                     }
+                }
+            } else if (P.n_diag > 0) {
+                for (int m = tid; m < (1 << kCisBits); m += T) {
+                    double s, c;
+                    sincospi((double)m / (double)(1 << (kCisBits - 1)), &s, &c);
+                    cis[m] = make_double2(c, s);
+                }
+            }
+        }
+        if constexpr (GEN) {
+            // eps sum of each diag op over its qubits, per index nibble
+            for (int o = 0; o < P.n_ops; ++o) {
+                const DevOp &op = ops[P.op_begin + o];
+                if (op.kind != OP_DIAG)
+                    continue;
+                for (int t = tid; t < 128; t += T) {
+                    const int k = t >> 4;
+                    const uint32_t v = (uint32_t)(t & 15) & ((op.emask >> (4 * k)) & 15u);
+                    double e = 0.0;
+                    for (int j = 0; j < 4; ++j)
+                        if ((v >> j) & 1u)
+                            e += M->eps_q[4 * k + j];
+                    etab[op.dtab * 128 + t] = e;
                 }
             }
         }
@@ -475,6 +526,9 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                 const DevOp &op = ops[P.op_begin + o];
                 double racc = 0.0;   // this op's reduction (thread part)
                 if (op.kind == OP_DIAG) {
+                    double th_op = 0.0;
+                    if constexpr (GEN && (MODE == M_FWD || MODE == M_REV))
+                        th_op = theta[op.param];
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         // recomputed per op: hoisted out of the op loop, the
@@ -488,27 +542,29 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                             double2 &a = v[t * NV][j];
                             if constexpr (MODE == M_FWD || MODE == M_REV) {
                                 double2 phs;
+                                double d = 0.0;
                                 if constexpr (!GEN) {
                                     const uint32_t dbl = g & (g >> M->ns) & op.umask;
                                     phs = dtab[op.dtab * kDiagTab + __popc(dbl)];
+                                    if constexpr (MODE == M_REV)
+                                        d = M->U * (double)__popc(dbl);
                                 } else {
-                                    double s, c;
-                                    sincos(theta[op.param] * diag_value<GEN>(op, g, M, vb), &s,
-                                           &c);
-                                    phs = make_double2(c, -sign * s);
+                                    d = diag_value<GEN>(op, g, M, vb, etab + op.dtab * 128);
+                                    phs = cis_neg(sign * th_op * d, cis);
                                 }
                                 if constexpr (MODE == M_REV) {
-                                    const double d = diag_value<GEN>(op, g, M, vb);
                                     racc += d * im_conj_mul(v[1][j], a);
                                     v[1][j] = cmul(v[1][j], phs);
                                 }
                                 a = cmul(a, phs);
                             } else if constexpr (MODE == M_HAM) {
-                                const double d = diag_value<GEN>(op, g, M, vb);
+                                const double d =
+                                    diag_value<GEN>(op, g, M, vb, etab + op.dtab * 128);
                                 v[1][j].x += d * a.x;
                                 v[1][j].y += d * a.y;
                             } else {
-                                eacc += diag_value<GEN>(op, g, M, vb) * (a.x * a.x + a.y * a.y);
+                                eacc += diag_value<GEN>(op, g, M, vb, etab + op.dtab * 128) *
+                                        (a.x * a.x + a.y * a.y);
                             }
                         }
                     }

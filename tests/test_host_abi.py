@@ -237,3 +237,25 @@ def test_workspace_sizes():
             assert 2 * vec <= g < 2 * vec + (64 << 20)
         finally:
             abi.hubbard_destroy(h)
+
+
+def test_batch_workspace_size():
+    ws = workloads.batch(12)
+    hs = [abi.hubbard_create(w.nx, w.ny, w.periodic_x, w.periodic_y, w.t, w.U, w.V, w.eps)
+          for w in ws]
+    try:
+        layers = [w.layers for w in ws]
+        vecs = sum(2 * (((1 << w.n_qubits) * 16 + 255) // 256 * 256) for w in ws)
+        b = abi.hubbard_batch_workspace_size(hs, layers)
+        # psi and lambda of every instance, then the partial sums: at most one
+        # row per parameter and reverse pass, each of at most 64 items
+        assert vecs < b <= vecs + 256 + 8 * 64 * sum(
+            w.n_params * 64 + 1 for w in ws)
+        assert b == abi.hubbard_batch_workspace_size(hs, layers)   # deterministic
+        more = abi.hubbard_batch_workspace_size(hs, [L + 2 for L in layers])
+        assert more > b   # more layers, more reduction rows
+        with pytest.raises(abi.HubbardError):
+            abi.hubbard_batch_workspace_size(hs, [-1] + layers[1:])
+    finally:
+        for h in hs:
+            abi.hubbard_destroy(h)
