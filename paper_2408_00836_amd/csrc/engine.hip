@@ -9,8 +9,9 @@
 #include <map>
 #include <memory>
 #include <mutex>
-#include <string>
 #include <stdexcept>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hubbard.h"
@@ -112,6 +113,9 @@ struct hubbard_model {
     // of the last call, and the kernel mode of each
     std::vector<hipEvent_t> kev;
     std::vector<int> kmode;
+    // forward schedules already planned, by (layers, k, c, lookahead, depth)
+    std::mutex plan_mu;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<HostPass>> fwd_plans;
 };
 
 namespace {
@@ -350,6 +354,24 @@ int max_of(const PassList &pl)
     return m;
 }
 
+// Forward schedule for a layer count and tile configuration, planned once per
+// handle (the lookahead search makes planning cost a fraction of a second at
+// 32 qubits, and workspace queries and uploads ask for the same plans).
+std::vector<HostPass> cached_forward(hubbard_model *h, int layers, const TileConfig &tc)
+{
+    const auto key = std::make_tuple(layers, tc.k, tc.c, tc.lookahead, tc.depth);
+    {
+        std::lock_guard<std::mutex> lk(h->plan_mu);
+        auto it = h->fwd_plans.find(key);
+        if (it != h->fwd_plans.end())
+            return it->second;
+    }
+    std::vector<HostPass> plan = plan_forward(h->m, layers, tc);
+    std::lock_guard<std::mutex> lk(h->plan_mu);
+    h->fwd_plans.emplace(key, plan);
+    return plan;
+}
+
 // Builds host plans only (no device work): used by introspection and upload.
 void plan_program(hubbard_model *h, int kind, int layers, int smem_limit, Program &pr)
 {
@@ -358,13 +380,13 @@ void plan_program(hubbard_model *h, int kind, int layers, int smem_limit, Progra
     pr.layers = layers;
     pr.general = m.general;
     if (kind != PROG_HAM)
-        pr.h_fwd = plan_forward(m, layers, h->fwd_tc);
+        pr.h_fwd = cached_forward(h, layers, h->fwd_tc);
     TileConfig tc2 = h->rev_tc;
     for (;;) {
         if (kind == PROG_HAM || kind == PROG_GRAD)
             pr.h_ham = plan_hamiltonian(m, tc2);
         if (kind == PROG_GRAD)
-            pr.h_rev = reversed_passes(plan_forward(m, layers, tc2));
+            pr.h_rev = reversed_passes(cached_forward(h, layers, tc2));
         // check LDS fit of the two-vector kernels; shrink the tile if needed
         Builder b(m);
         PassList ph = b.add(pr.h_ham, 2, true), pv = b.add(pr.h_rev, 1, false);

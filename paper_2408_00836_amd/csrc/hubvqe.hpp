@@ -245,8 +245,10 @@ struct HostPass {
 };
 
 struct TileConfig {
-    int k = 12;     // tile bits
-    int c = 4;      // minimum contiguous low bits in every tile
+    int k = 12;          // tile bits
+    int c = 4;           // minimum contiguous low bits in every tile
+    int lookahead = 4;   // forward planner: candidates kept per lookahead level
+    int depth = 3;       // forward planner: passes of lookahead
 };
 
 // Forward circuit (layers of Eq. (7)) as elementary ops, then fused passes.

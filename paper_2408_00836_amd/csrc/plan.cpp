@@ -15,6 +15,7 @@
 // gate only waits for the sub-terms on its own sites.
 #include <algorithm>
 #include <cstdint>
+#include <functional>
 #include <tuple>
 #include <vector>
 
@@ -222,37 +223,76 @@ std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig 
     std::vector<char> done(ops.size(), 0);
     size_t first = 0;
     const size_t window = 480;
-    while (first < ops.size()) {
+    // candidate passes from the current state: one closure per seed (no
+    // seed, and the qubits of each ready hop), best first
+    auto candidates = [&](const std::vector<char> &dn, size_t from, size_t max_seeds) {
         std::vector<int> active;
-        for (size_t i = first; i < ops.size() && active.size() < window; ++i)
-            if (!done[i])
+        for (size_t i = from; i < ops.size() && active.size() < window; ++i)
+            if (!dn[i])
                 active.push_back((int)i);
-        // Seeds: no seed, and the qubits of each ready hop.
         std::vector<uint32_t> seeds{0u};
-        {
-            uint32_t bg = 0, bd = 0;
-            for (int i : active) {
-                const HostOp &o = ops[i];
-                if (o.kind == OP_DIAG) {
-                    if (o.qmask & bg)
-                        bd |= o.qmask;
-                    continue;
-                }
-                if (!((o.qmask & bg) || (o.qmask & bd)))
-                    seeds.push_back(o.qmask);
-                bg |= o.qmask;
-                if (seeds.size() > 48)
-                    break;
-            }
-        }
-        Closure best;
-        best.hops = -1;
-        for (uint32_t sd : seeds) {
-            Closure cl = grow(ops, active, done, C | sd, k);
-            if (cl.inc.empty())
+        uint32_t bg = 0, bd = 0;
+        for (int i : active) {
+            const HostOp &o = ops[i];
+            if (o.kind == OP_DIAG) {
+                if (o.qmask & bg)
+                    bd |= o.qmask;
                 continue;
-            if (cl.hops > best.hops || (cl.hops == best.hops && cl.inc.size() > best.inc.size()))
-                best = cl;
+            }
+            if (!((o.qmask & bg) || (o.qmask & bd)))
+                seeds.push_back(o.qmask);
+            bg |= o.qmask;
+            if (seeds.size() > max_seeds)
+                break;
+        }
+        std::vector<Closure> out;
+        for (uint32_t sd : seeds) {
+            Closure cl = grow(ops, active, dn, C | sd, k);
+            if (!cl.inc.empty())
+                out.push_back(std::move(cl));
+        }
+        std::stable_sort(out.begin(), out.end(), [](const Closure &a, const Closure &b) {
+            return a.hops > b.hops || (a.hops == b.hops && a.inc.size() > b.inc.size());
+        });
+        return out;
+    };
+    while (first < ops.size()) {
+        std::vector<Closure> cands = candidates(done, first, 48);
+        // Lookahead: among the best few candidates keep the one that, with
+        // the best follow-up passes (searched `depth` deep over the same
+        // number of candidates), applies the most hops in total.
+        std::function<int(const std::vector<char> &, size_t, int)> future =
+            [&](const std::vector<char> &dn0, size_t from, int depth) -> int {
+            size_t f = from;
+            while (f < ops.size() && dn0[f])
+                ++f;
+            if (depth == 0 || f >= ops.size())
+                return 0;
+            std::vector<Closure> nc = candidates(dn0, f, 24);
+            int bestv = 0;
+            const size_t bw = std::min<size_t>(nc.size(), (size_t)tc.lookahead);
+            for (size_t ci = 0; ci < bw; ++ci) {
+                std::vector<char> dn = dn0;
+                for (int i : nc[ci].inc)
+                    dn[i] = 1;
+                bestv = std::max(bestv, nc[ci].hops + future(dn, f, depth - 1));
+            }
+            return bestv;
+        };
+        Closure best = cands.front();
+        if (tc.lookahead > 0 && cands.size() > 1) {
+            int best_score = -1;
+            const size_t beam = std::min<size_t>(cands.size(), (size_t)tc.lookahead);
+            for (size_t ci = 0; ci < beam; ++ci) {
+                std::vector<char> dn = done;
+                for (int i : cands[ci].inc)
+                    dn[i] = 1;
+                const int score = cands[ci].hops + future(dn, first, tc.depth);
+                if (score > best_score) {
+                    best_score = score;
+                    best = cands[ci];
+                }
+            }
         }
         HostPass p;
         p.tile = finish_tile(best.S, n, k);

@@ -44,6 +44,7 @@ class Hubbard:
         self.params_per_layer = q["params_per_layer"]
         self.neel_index = q["neel_index"]
         self._ws = {}
+        self._ws_bytes = {}   # (layers, op) -> bytes, per tile configuration
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -70,11 +71,15 @@ class Hubbard:
     def set_tiles(self, fwd_k: int, rev_k: int, c: int) -> None:
         abi.hubbard_set_tiles(self.handle, fwd_k, rev_k, c)
         self._ws.clear()
+        self._ws_bytes.clear()
 
     def workspace(self, layers: int, op: int, device=None) -> torch.Tensor:
         """Device workspace of at least hubbard_workspace_size bytes; an existing
         larger buffer of this model is reused (psi sits at its start)."""
-        nbytes = abi.hubbard_workspace_size(self.handle, layers, op)
+        key = (layers, op)
+        nbytes = self._ws_bytes.get(key)
+        if nbytes is None:
+            nbytes = self._ws_bytes[key] = abi.hubbard_workspace_size(self.handle, layers, op)
         dev = torch.device(device or "cuda")
         if dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())

@@ -69,6 +69,7 @@ def autotune(model, theta: torch.Tensor, *, general: bool, proxy_layers: int | N
     table = abi.hubbard_tune(model.handle, Lt, th.data_ptr(), ws.data_ptr(), ws.numel(),
                              torch.cuda.current_stream().cuda_stream, reps)
     best = abi.hubbard_get_tiles(model.handle)
+    model.set_tiles(*best)   # the tuner leaves the winner set; drop cached sizes
     ent = {"best": list(best), "timed_layers": Lt,
            "table": [dict(fwd_k=a, rev_k=b, c=c, ms=ms) for a, b, c, ms in table]}
     if save:
