@@ -104,6 +104,37 @@ typedef struct {
  * than 32 qubits or a non-finite coefficient; HUBBARD_ERR_NOMEM. */
 hubbard_status hubbard_create(const hubbard_desc *desc, hubbard_t *out);
 
+/* The same model on an arbitrary graph of sites (Eq. (2)/(15)/(16) with any
+ * set of bonds, e.g. other lattices or boundary conditions).  All pointers
+ * are host pointers, read during hubbard_create_graph only.
+ *   n_sites         1 <= n_sites <= 16 (qubit q = site + n_sites * spin)
+ *   n_bonds         0 <= n_bonds <= 64
+ *   bond_i, bond_j  the sites of each bond (distinct, in range; an unordered
+ *                   pair may appear once); this is the bond order of t_bond,
+ *                   V_bond and bond_group
+ *   t_bond, V_bond, eps_site, U   as in hubbard_desc (NULL: t = 1, V = 0,
+ *                   eps = 0)
+ *   bond_group      group ids >= 0, each group a matching, applied in
+ *                   increasing id (NULL: in bond order each bond joins the
+ *                   lowest group that has neither of its sites yet)
+ *   site_spin       start state: site s holds one electron of spin
+ *                   site_spin[s] (0 up, 1 down); NULL: up on even sites,
+ *                   down on odd ones
+ * Errors: HUBBARD_ERR_ARG (a bad or repeated bond, a non-matching group, a
+ * bad spin, a non-finite coefficient), HUBBARD_ERR_NOMEM. */
+typedef struct {
+    int32_t n_sites, n_bonds;
+    const int32_t *bond_i, *bond_j;
+    const double *t_bond;
+    double U;
+    const double *V_bond;
+    const double *eps_site;
+    const int32_t *bond_group;
+    const int32_t *site_spin;
+} hubbard_graph_desc;
+
+hubbard_status hubbard_create_graph(const hubbard_graph_desc *desc, hubbard_t *out);
+
 /* Release the handle and its device tables (synchronises nothing; the caller
  * must not destroy a handle with work still queued on a stream). */
 void hubbard_destroy(hubbard_t h);

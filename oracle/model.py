@@ -47,6 +47,7 @@ class OracleModel:
     eps: np.ndarray      # on-site energy per site
     U: float
     interleaved: bool = False
+    site_spin: Optional[list] = None   # graph models: start spin per site (0 up, 1 down)
 
     @property
     def nsites(self) -> int:
@@ -80,8 +81,13 @@ class OracleModel:
         return site + self.nsites * spin
 
     def neel_sites(self):
-        """(up_sites, down_sites) of the checkerboard start state."""
+        """(up_sites, down_sites) of the checkerboard start state (graph
+        models: of their stated start spins)."""
         up, dn = [], []
+        if self.site_spin is not None:
+            for s, sp in enumerate(self.site_spin):
+                (dn if sp else up).append(s)
+            return up, dn
         for x in range(self.nx):
             for y in range(self.ny):
                 (up if (x + y) % 2 == 0 else dn).append(x * self.ny + y)
@@ -164,3 +170,57 @@ def make_model(nx: int, ny: int, *, periodic_x: bool = False, periodic_y: bool =
         raise ValueError("t and V need one value per bond, eps one per site")
     return OracleModel(nx, ny, bool(periodic_x), bool(periodic_y), bonds, cls,
                        t_arr, V_arr, e_arr, float(U), bool(interleaved))
+
+
+def greedy_matchings(bonds):
+    """Default groups of a graph: in bond order, each bond joins the lowest
+    group in which neither of its sites is used yet (so every group is a
+    matching)."""
+    used, out = [], []
+    for i, j in bonds:
+        g = 0
+        while g < len(used) and (i in used[g] or j in used[g]):
+            g += 1
+        if g == len(used):
+            used.append(set())
+        used[g] |= {i, j}
+        out.append(g)
+    return out
+
+
+def make_graph_model(n_sites: int, bonds, *, t: Optional[Sequence[float]] = None,
+                     U: float = 0.0, V: Optional[Sequence[float]] = None,
+                     eps: Optional[Sequence[float]] = None,
+                     groups: Optional[Sequence[int]] = None,
+                     site_spin: Optional[Sequence[int]] = None,
+                     interleaved: bool = False) -> OracleModel:
+    """Hubbard model of Eq. (2)/(15)/(16) on an arbitrary graph: the sites
+    0..n_sites-1, one hopping term and one V term per listed bond (unordered,
+    each once).  Start state: one electron per site with spin site_spin[s]
+    (default: up on even sites, down on odd ones)."""
+    if n_sites < 1:
+        raise ValueError("at least one site")
+    bonds = [(int(i), int(j)) for i, j in bonds]
+    seen = set()
+    for i, j in bonds:
+        if not (0 <= i < n_sites and 0 <= j < n_sites) or i == j:
+            raise ValueError(f"bad bond ({i}, {j})")
+        key = (min(i, j), max(i, j))
+        if key in seen:
+            raise ValueError(f"bond ({i}, {j}) listed twice")
+        seen.add(key)
+    cls = greedy_matchings(bonds) if groups is None else [int(g) for g in groups]
+    if len(cls) != len(bonds):
+        raise ValueError("one group id per bond")
+    check_matchings(bonds, cls)
+    spins = [s % 2 for s in range(n_sites)] if site_spin is None else [int(x) for x in site_spin]
+    if len(spins) != n_sites or any(x not in (0, 1) for x in spins):
+        raise ValueError("site_spin needs one 0/1 entry per site")
+    nb = len(bonds)
+    t_arr = np.ones(nb) if t is None else np.asarray(t, dtype=np.float64).copy()
+    V_arr = np.zeros(nb) if V is None else np.asarray(V, dtype=np.float64).copy()
+    e_arr = np.zeros(n_sites) if eps is None else np.asarray(eps, dtype=np.float64).copy()
+    if t_arr.shape != (nb,) or V_arr.shape != (nb,) or e_arr.shape != (n_sites,):
+        raise ValueError("t and V need one value per bond, eps one per site")
+    return OracleModel(1, n_sites, False, False, bonds, cls, t_arr, V_arr, e_arr, float(U),
+                       bool(interleaved), spins)

@@ -26,7 +26,7 @@ HUBBARD_OP_ENERGY_GRAD = 1
 
 # Every symbol the headers in include/ declare.
 EXPORTED = [
-    "hubbard_create", "hubbard_destroy", "hubbard_query", "hubbard_bonds",
+    "hubbard_create", "hubbard_create_graph", "hubbard_destroy", "hubbard_query", "hubbard_bonds",
     "hubbard_last_error", "hubbard_workspace_size", "hubbard_init_neel",
     "ansatz_apply", "hamiltonian_apply", "energy", "energy_grad",
     "hubbard_plan_dump", "hubbard_set_tiles", "hubbard_set_timing", "hubbard_phase_ms",
@@ -53,6 +53,19 @@ class hubbard_desc(ctypes.Structure):
     ]
 
 
+class hubbard_graph_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_sites", ctypes.c_int32), ("n_bonds", ctypes.c_int32),
+        ("bond_i", ctypes.POINTER(ctypes.c_int32)), ("bond_j", ctypes.POINTER(ctypes.c_int32)),
+        ("t_bond", ctypes.POINTER(ctypes.c_double)),
+        ("U", ctypes.c_double),
+        ("V_bond", ctypes.POINTER(ctypes.c_double)),
+        ("eps_site", ctypes.POINTER(ctypes.c_double)),
+        ("bond_group", ctypes.POINTER(ctypes.c_int32)),
+        ("site_spin", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
 _lib = None
 
 
@@ -69,6 +82,7 @@ def lib() -> ctypes.CDLL:
         P = ctypes.POINTER
         sig = {
             "hubbard_create": ([P(hubbard_desc), P(vp)], st),
+            "hubbard_create_graph": ([P(hubbard_graph_desc), P(vp)], st),
             "hubbard_destroy": ([vp], None),
             "hubbard_query": ([vp, P(i32), P(i32), P(i32), P(i32), P(u64)], st),
             "hubbard_bonds": ([vp, P(i32), P(i32), P(i32)], st),
@@ -133,6 +147,34 @@ def hubbard_create(nx: int, ny: int, periodic_x: bool = False, periodic_y: bool 
         d.bond_group = g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     h = ctypes.c_void_p()
     _check(lib().hubbard_create(ctypes.byref(d), ctypes.byref(h)))
+    return h.value
+
+
+def hubbard_create_graph(n_sites: int, bonds, t_bond=None, U: float = 0.0, V_bond=None,
+                         eps_site=None, bond_group=None, site_spin=None) -> int:
+    """Model on an arbitrary graph: `bonds` is a sequence of (i, j) site pairs.
+    Returns the opaque handle (an int)."""
+    keep = []
+    d = hubbard_graph_desc()
+    b = np.asarray(list(bonds), dtype=np.int32).reshape(-1, 2)
+    d.n_sites, d.n_bonds = int(n_sites), int(b.shape[0])
+    bi, bj = np.ascontiguousarray(b[:, 0]), np.ascontiguousarray(b[:, 1])
+    keep += [bi, bj]
+    d.bond_i = bi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.bond_j = bj.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.U = float(U)
+    for field, arr in (("t_bond", t_bond), ("V_bond", V_bond), ("eps_site", eps_site)):
+        if arr is not None:
+            a, p = _dptr(arr)
+            keep.append(a)
+            setattr(d, field, p)
+    for field, arr in (("bond_group", bond_group), ("site_spin", site_spin)):
+        if arr is not None:
+            g = np.ascontiguousarray(arr, dtype=np.int32)
+            keep.append(g)
+            setattr(d, field, g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    h = ctypes.c_void_p()
+    _check(lib().hubbard_create_graph(ctypes.byref(d), ctypes.byref(h)))
     return h.value
 
 

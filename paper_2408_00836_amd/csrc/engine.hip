@@ -962,6 +962,28 @@ hubbard_status hubbard_create(const hubbard_desc *d, hubbard_t *out)
     return HUBBARD_OK;
 }
 
+hubbard_status hubbard_create_graph(const hubbard_graph_desc *d, hubbard_t *out)
+{
+    if (!d || !out)
+        return fail(HUBBARD_ERR_ARG, "desc and out must not be NULL");
+    *out = nullptr;
+    hubbard_model *h = nullptr;
+    try {
+        h = new hubbard_model();
+    } catch (...) {
+        return fail(HUBBARD_ERR_NOMEM, "allocating handle");
+    }
+    std::string err = build_graph_model(d->n_sites, d->n_bonds, d->bond_i, d->bond_j, d->t_bond,
+                                        d->U, d->V_bond, d->eps_site, d->bond_group,
+                                        d->site_spin, h->m);
+    if (!err.empty()) {
+        delete h;
+        return fail(HUBBARD_ERR_ARG, err);
+    }
+    *out = h;
+    return HUBBARD_OK;
+}
+
 void hubbard_destroy(hubbard_t h)
 {
     if (!h)

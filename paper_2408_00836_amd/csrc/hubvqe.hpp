@@ -217,6 +217,9 @@ struct Model {
 // Build and validate a model; returns an empty string or an error message.
 std::string build_model(int nx, int ny, int px, int py, const double *t, double U,
                         const double *V, const double *eps, const int32_t *groups, Model &m);
+std::string build_graph_model(int n_sites, int n_bonds, const int32_t *bi, const int32_t *bj,
+                              const double *t, double U, const double *V, const double *eps,
+                              const int32_t *groups, const int32_t *site_spin, Model &m);
 
 // One elementary operation of the forward circuit or of H.
 struct HostOp {

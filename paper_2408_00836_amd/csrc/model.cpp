@@ -58,30 +58,18 @@ std::vector<RawBond> lattice_bonds(int nx, int ny, bool px, bool py)
 
 }  // namespace
 
-std::string build_model(int nx, int ny, int px, int py, const double *t, double U,
-                        const double *V, const double *eps, const int32_t *groups, Model &m)
+namespace {
+
+// Groups, per-bond and per-site constants, validation and start state shared
+// by the lattice and the graph forms.  spin[s]: start spin of site s.
+std::string finish_model(const std::vector<RawBond> &raw, const double *t, double U,
+                         const double *V, const double *eps, const int32_t *groups,
+                         const std::vector<int> &spin, Model &m)
 {
-    if (nx < 1 || ny < 1)
-        return "nx and ny must be >= 1";
-    if ((long)nx * ny > kMaxSites)
-        return "at most 16 sites (32 qubits)";
-    if (px && nx < 3)
-        return "periodic_x needs nx >= 3";
-    if (py && ny < 3)
-        return "periodic_y needs ny >= 3";
     if (!std::isfinite(U))
         return "U must be finite";
-
-    m = Model();
-    m.nx = nx;
-    m.ny = ny;
-    m.px = px ? 1 : 0;
-    m.py = py ? 1 : 0;
-    m.ns = nx * ny;
     m.nq = 2 * m.ns;
     m.U = U;
-
-    std::vector<RawBond> raw = lattice_bonds(nx, ny, px != 0, py != 0);
     m.nb = (int)raw.size();
     if (m.nb > kMaxBonds)
         return "too many bonds";
@@ -140,15 +128,79 @@ std::string build_model(int nx, int ny, int px, int py, const double *t, double 
         if (m.eps[i] != 0.0)
             m.general = true;
     }
-    // Checkerboard start (Sec. 2.1): spin up where x+y is even, down otherwise.
     m.neel = 0;
-    for (int x = 0; x < nx; ++x)
-        for (int y = 0; y < ny; ++y) {
-            int site = x * ny + y;
-            int spin = ((x + y) & 1) ? 1 : 0;
-            m.neel |= (uint64_t)1 << m.qubit(site, spin);
-        }
+    for (int site = 0; site < m.ns; ++site)
+        m.neel |= (uint64_t)1 << m.qubit(site, spin[site]);
     return "";
+}
+
+}  // namespace
+
+std::string build_model(int nx, int ny, int px, int py, const double *t, double U,
+                        const double *V, const double *eps, const int32_t *groups, Model &m)
+{
+    if (nx < 1 || ny < 1)
+        return "nx and ny must be >= 1";
+    if ((long)nx * ny > kMaxSites)
+        return "at most 16 sites (32 qubits)";
+    if (px && nx < 3)
+        return "periodic_x needs nx >= 3";
+    if (py && ny < 3)
+        return "periodic_y needs ny >= 3";
+    m = Model();
+    m.nx = nx;
+    m.ny = ny;
+    m.px = px ? 1 : 0;
+    m.py = py ? 1 : 0;
+    m.ns = nx * ny;
+    // Checkerboard start (Sec. 2.1): spin up where x+y is even, down otherwise.
+    std::vector<int> spin(m.ns);
+    for (int x = 0; x < nx; ++x)
+        for (int y = 0; y < ny; ++y)
+            spin[x * ny + y] = ((x + y) & 1) ? 1 : 0;
+    return finish_model(lattice_bonds(nx, ny, px != 0, py != 0), t, U, V, eps, groups, spin, m);
+}
+
+std::string build_graph_model(int n_sites, int n_bonds, const int32_t *bi, const int32_t *bj,
+                              const double *t, double U, const double *V, const double *eps,
+                              const int32_t *groups, const int32_t *site_spin, Model &m)
+{
+    if (n_sites < 1 || n_sites > kMaxSites)
+        return "n_sites must be in [1, 16] (at most 32 qubits)";
+    if (n_bonds < 0 || n_bonds > kMaxBonds)
+        return "n_bonds must be in [0, 64]";
+    if (n_bonds > 0 && (!bi || !bj))
+        return "bond_i and bond_j are required when n_bonds > 0";
+    std::vector<RawBond> raw;
+    std::set<std::pair<int, int>> seen;
+    // default groups: in bond order, the lowest group whose bonds use neither site
+    std::vector<std::set<int>> used;
+    for (int b = 0; b < n_bonds; ++b) {
+        const int i = bi[b], j = bj[b];
+        if (i < 0 || i >= n_sites || j < 0 || j >= n_sites || i == j)
+            return "bond " + std::to_string(b) + " has a bad site";
+        if (!seen.insert({std::min(i, j), std::max(i, j)}).second)
+            return "bond " + std::to_string(b) + " is listed twice";
+        size_t g = 0;
+        while (g < used.size() && (used[g].count(i) || used[g].count(j)))
+            ++g;
+        if (g == used.size())
+            used.emplace_back();
+        used[g].insert(i);
+        used[g].insert(j);
+        raw.push_back({i, j, (int)g});
+    }
+    std::vector<int> spin(n_sites);
+    for (int s = 0; s < n_sites; ++s) {
+        spin[s] = site_spin ? site_spin[s] : (s & 1);
+        if (spin[s] != 0 && spin[s] != 1)
+            return "site_spin entries must be 0 (up) or 1 (down)";
+    }
+    m = Model();
+    m.nx = 1;
+    m.ny = n_sites;
+    m.ns = n_sites;
+    return finish_model(raw, t, U, V, eps, groups, spin, m);
 }
 
 }  // namespace hv

@@ -33,8 +33,9 @@ class Hubbard:
     """One Hubbard model instance (Eq. (1)/(2)/(15)/(16)) and its HVA circuit."""
 
     def __init__(self, nx: int, ny: int, *, periodic_x: bool = False, periodic_y: bool = False,
-                 t=None, U: float = 0.0, V=None, eps=None, groups=None):
-        self.handle = abi.hubbard_create(nx, ny, periodic_x, periodic_y, t, U, V, eps, groups)
+                 t=None, U: float = 0.0, V=None, eps=None, groups=None, _handle=None):
+        self.handle = (_handle if _handle is not None else
+                       abi.hubbard_create(nx, ny, periodic_x, periodic_y, t, U, V, eps, groups))
         self.nx, self.ny = nx, ny
         self.periodic_x, self.periodic_y = bool(periodic_x), bool(periodic_y)
         q = abi.hubbard_query(self.handle)
@@ -45,6 +46,13 @@ class Hubbard:
         self.neel_index = q["neel_index"]
         self._ws = {}
         self._ws_bytes = {}   # (layers, op) -> bytes, per tile configuration
+
+    @classmethod
+    def graph(cls, n_sites: int, bonds, *, t=None, U: float = 0.0, V=None, eps=None,
+              groups=None, site_spin=None) -> "Hubbard":
+        """The model on an arbitrary graph of sites (see hubbard_create_graph)."""
+        h = abi.hubbard_create_graph(n_sites, bonds, t, U, V, eps, groups, site_spin)
+        return cls(1, n_sites, _handle=h)
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -259,3 +259,50 @@ def test_batch_workspace_size():
     finally:
         for h in hs:
             abi.hubbard_destroy(h)
+
+
+def test_create_graph_matches_lattice_form():
+    from oracle.model import make_model as om_make
+    m = om_make(4, 4, periodic_x=True, periodic_y=True)
+    spins = [((s // 4) + (s % 4)) % 2 for s in range(16)]
+    h1 = abi.hubbard_create(4, 4, True, True, None, 8.0)
+    h2 = abi.hubbard_create_graph(16, m.bonds, None, 8.0, bond_group=m.bond_class,
+                                  site_spin=spins)
+    try:
+        assert abi.hubbard_query(h1) == abi.hubbard_query(h2)
+        for which in (0, 1, 2):
+            assert abi.hubbard_plan_dump(h1, 3, which) == abi.hubbard_plan_dump(h2, 3, which)
+    finally:
+        abi.hubbard_destroy(h1)
+        abi.hubbard_destroy(h2)
+
+
+def test_create_graph_defaults_agree_with_oracle():
+    from oracle.model import make_graph_model
+    bonds = [(0, 5), (1, 2), (2, 5), (0, 3), (3, 4), (1, 4), (0, 2)]
+    om = make_graph_model(6, bonds, U=2.0)
+    h = abi.hubbard_create_graph(6, bonds, None, 2.0)
+    try:
+        q = abi.hubbard_query(h)
+        assert q["neel_index"] == om.neel_index()
+        assert q["params_per_layer"] == om.params_per_layer
+        bi, bj, grp = abi.hubbard_bonds(h)
+        assert list(zip(bi, bj)) == bonds
+        assert [g + 1 for g in grp] == om.bond_slot()   # hubbard_bonds slots are 0-based
+    finally:
+        abi.hubbard_destroy(h)
+
+
+@pytest.mark.parametrize("n,bonds,kw,msg", [
+    (0, [], {}, "n_sites"),
+    (17, [], {}, "n_sites"),
+    (3, [(0, 3)], {}, "bad site"),
+    (3, [(1, 1)], {}, "bad site"),
+    (3, [(0, 1), (1, 0)], {}, "twice"),
+    (3, [(0, 1), (1, 2)], {"bond_group": [0, 0]}, "matching"),
+    (3, [(0, 1)], {"site_spin": [0, 2, 1]}, "site_spin"),
+    (3, [(0, 1)], {"t_bond": [float("nan")]}, "finite"),
+])
+def test_create_graph_rejects_invalid(n, bonds, kw, msg):
+    with pytest.raises(abi.HubbardError, match=msg):
+        abi.hubbard_create_graph(n, bonds, **kw)

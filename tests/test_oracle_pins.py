@@ -340,3 +340,52 @@ def test_golden_values(oracle_lib):
     for key in ("two_site_U4", "two_site_U8"):
         U = gold[key]["U"]
         assert abs(gold[key]["E0"] - (U / 2 - np.sqrt(U * U / 4 + 4))) < 1e-12
+
+
+# ---------------------------------------------------------- graph models --
+
+GRAPH = dict(n=6, bonds=[(0, 5), (1, 2), (2, 5), (0, 3), (3, 4), (1, 4), (0, 2), (3, 5)])
+GRAPH5 = dict(n=5, bonds=[(0, 4), (1, 2), (2, 4), (0, 3), (3, 4), (1, 3), (0, 2)])
+
+
+def test_graph_free_fermion_spectrum(oracle_lib):
+    """A non-bipartite graph with long bonds (triangles, pairs five sites apart):
+    at U = V = 0 the sector spectrum is the sums of single-particle levels of
+    h, which pins the Jordan-Wigner signs of arbitrary (i, j) terms."""
+    from oracle.model import make_graph_model
+    nb = len(GRAPH["bonds"])
+    m = make_graph_model(GRAPH["n"], GRAPH["bonds"], t=1 + 0.2 * RNG.standard_normal(nb),
+                         eps=RNG.uniform(-0.5, 0.5, GRAPH["n"]))
+    up, dn = m.neel_sites()
+    got = oracle_sector_spectrum(m, len(up), len(dn))
+    want = free_sector_spectrum(m, len(up), len(dn))
+    assert got.shape == want.shape
+    assert np.max(np.abs(got - want)) < 1e-11
+
+
+def test_graph_dense_circuit(oracle_lib):
+    """Circuit energy and gradient on a graph model against the independent
+    Kronecker-product construction."""
+    from oracle.model import make_graph_model
+    rng = np.random.default_rng(77)
+    nb = len(GRAPH5["bonds"])
+    m = make_graph_model(GRAPH5["n"], GRAPH5["bonds"], t=1 + 0.1 * rng.standard_normal(nb),
+                         U=3.0, V=np.full(nb, 0.4), eps=rng.uniform(-0.3, 0.3, GRAPH5["n"]),
+                         site_spin=[0, 0, 1, 1, 0])
+    th = rng.uniform(-np.pi / 8, np.pi / 8, 2 * m.params_per_layer)
+    dc = od.DenseCircuit(m)
+    assert np.max(np.abs(oc.ansatz(m, th, 2) - dc.state(th, 2))) < 1e-12
+    E, g = oc.energy_grad(m, th, 2)
+    assert abs(E - dc.energy(th, 2)) < 1e-12 * max(1, abs(E))
+    assert np.max(np.abs(g - dc.grad(th, 2))) < 1e-11
+
+
+def test_graph_form_of_a_chain_is_the_chain(oracle_lib):
+    from oracle.model import make_graph_model
+    m = make_model(1, 6, U=4.0, V=np.full(5, 0.3))
+    gm = make_graph_model(6, m.bonds, U=4.0, V=np.full(5, 0.3), groups=m.bond_class)
+    assert gm.neel_index() == m.neel_index()
+    th = np.random.default_rng(5).uniform(-0.3, 0.3, 2 * m.params_per_layer)
+    E1, g1 = oc.energy_grad(m, th, 2)
+    E2, g2 = oc.energy_grad(gm, th, 2)
+    assert E1 == E2 and np.array_equal(g1, g2)
