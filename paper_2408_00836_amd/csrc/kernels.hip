@@ -333,6 +333,17 @@ __device__ __forceinline__ uint32_t tile_advance(uint32_t base, uint32_t step_de
     return (uint32_t)((((uint64_t)(base | ~free_mask)) + step_dep) & free_mask);
 }
 
+// Element offset of amplitude g of a vector stored in blocks of 2^ilv
+// amplitudes with a gap of one block after each (ilv = 32: plain contiguous
+// storage); a second vector may fill the gaps.  Inserting a zero bit is
+// linear: the offset of a | b (disjoint bits) is the OR of their offsets, so
+// a thread's part is mapped once per tile and a register's part, uniform
+// over the wave, on the scalar unit.
+__device__ __forceinline__ uint64_t vec_offset(uint64_t g, uint32_t ilv)
+{
+    return g + ((g >> ilv) << ilv);
+}
+
 // One pass over the tiles [tile0, tile_end) with stride tstep.  FULL: all
 // threads own amplitudes and all 16 registers hold one (tiles of >= 16
 // amplitudes launched with exactly 2^tbits threads): no per-register guards.
@@ -346,7 +357,8 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                                          const double *__restrict__ theta,
                                          const DevModel *__restrict__ M, double2 *__restrict__ v0,
                                          double2 *__restrict__ v1, char *smem, uint64_t tile0,
-                                         uint64_t tstep, uint64_t tile_end, const Sink &sink)
+                                         uint64_t tstep, uint64_t tile_end, uint32_t ilv,
+                                         const Sink &sink)
 {
     constexpr int NV = (MODE == M_FWD || MODE == M_EXP) ? 1 : 2;   // vectors per tile
     constexpr int NS = NT * NV;                                     // register sets
@@ -455,7 +467,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                           __attribute__((always_inline)) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const uint32_t gb = bs[t] | tp0.x;
+            const uint64_t ga = vec_offset(bs[t] | tp0.x, ilv);
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) {
                 if constexpr (!FULL) {
@@ -464,7 +476,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                         dst[1][j] = make_double2(0.0, 0.0);
                 }
                 if (FULL || (act && ((valid >> j) & 1u))) {
-                    const uint64_t g = gb | L0.goff(j);
+                    const uint64_t g = ga | vec_offset(L0.goff(j), ilv);
                     dst[t * NV][j] = v0[g];
                     if constexpr (NV == 2) {
                         if (!ham_first)
@@ -612,11 +624,11 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
         if constexpr (MODE != M_EXP) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const uint32_t gt = opaque(gthr[t]);
+                const uint64_t ga = vec_offset(opaque(gthr[t]), ilv);
 #pragma unroll
                 for (int j = 0; j < kRegs; ++j) {
                     if (FULL || (act && ((valid >> j) & 1u))) {
-                        const uint64_t g = gt | L.goff(j);
+                        const uint64_t g = ga | vec_offset(L.goff(j), ilv);
                         if constexpr (MODE == M_FWD || MODE == M_REV)
                             v0[g] = v[t * NV][j];
                         if constexpr (NV == 2)
@@ -662,12 +674,12 @@ __global__ void __launch_bounds__(512)
 k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__ ops,
        const DevVBond *__restrict__ vb, const double *__restrict__ theta,
        const DevModel *__restrict__ M, double2 *__restrict__ v0, double2 *__restrict__ v1,
-       double *__restrict__ partial, int stride)
+       double *__restrict__ partial, int stride, uint32_t ilv)
 {
     extern __shared__ __align__(16) char smem[];
     const Sink sink{partial + (size_t)P.red_base * stride + blockIdx.x, stride};
     run_pass<MODE, GEN, FULL, NT>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x,
-                                  gridDim.x, (uint64_t)1 << P.nfree, sink);
+                                  gridDim.x, (uint64_t)1 << P.nfree, ilv, sink);
 }
 
 // ------------------------------------------------------------------ batch --
@@ -699,10 +711,10 @@ k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ p
     double2 *psi = (double2 *)I.psi, *lam = (double2 *)I.lam;
     if (I.general)
         run_pass<MODE, true, false, 1>(P, I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                       smem, w.tile0, 1, w.tile1, sink);
+                                       smem, w.tile0, 1, w.tile1, 32u, sink);
     else
         run_pass<MODE, false, false, 1>(P, I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                        smem, w.tile0, 1, w.tile1, sink);
+                                        smem, w.tile0, 1, w.tile1, 32u, sink);
 }
 template __global__ void k_batch_pass<M_FWD>(const DevInstance *, const DevPass *,
                                               const DevWork *, double *);
@@ -746,7 +758,7 @@ k_reduce_seg(const double *__restrict__ partial, const int32_t *__restrict__ seg
 #define HV_INSTANTIATE(MODE, GEN, FULL, NT)                                                   \
     template __global__ void k_pass<MODE, GEN, FULL, NT>(                                       \
         DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,             \
-        const DevModel *, double2 *, double2 *, double *, int);
+        const DevModel *, double2 *, double2 *, double *, int, uint32_t);
 #define HV_INSTANTIATE_ALL(GEN, FULL)                                                           \
     HV_INSTANTIATE(M_FWD, GEN, FULL, 1)                                                         \
     HV_INSTANTIATE(M_REV, GEN, FULL, 1)                                                         \
@@ -764,11 +776,11 @@ HV_INSTANTIATE(M_FWD, false, true, 2)
 
 // ------------------------------------------------------------ misc kernels --
 
-__global__ void k_init_basis(double2 *__restrict__ psi, uint64_t dim, uint64_t b0)
+__global__ void k_init_basis(double2 *__restrict__ psi, uint64_t dim, uint64_t b0, uint32_t ilv)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += stride)
-        psi[i] = make_double2(i == b0 ? 1.0 : 0.0, 0.0);
+        psi[vec_offset(i, ilv)] = make_double2(i == b0 ? 1.0 : 0.0, 0.0);
 }
 
 // out[o] = scale[o] * sum over rows row_idx[row_ptr[o] .. row_ptr[o+1]) of the

@@ -146,7 +146,9 @@ class Hubbard:
         return E, grad
 
     def workspace_views(self, layers: int):
-        """(psi, lambda) views into the energy_grad workspace after a call."""
+        """Two plain vector buffers carved out of the energy_grad workspace
+        (scratch for ansatz/apply_h at the benchmark size; energy_grad stores
+        its own psi and lambda there in a layout of its own)."""
         ws = self.workspace(layers, abi.HUBBARD_OP_ENERGY_GRAD, "cuda")
         vb = ((self.dim * 16 + 255) // 256) * 256
         psi = ws[: self.dim * 16].view(torch.complex128)
