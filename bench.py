@@ -238,21 +238,26 @@ def main():
     E_val = E.item()
 
     # per-launch averages (events around each launch, on the launch stream)
-    # and algorithmic bytes: a forward pass reads and writes psi once, a
-    # reverse pass psi and lambda
+    # and algorithmic bytes, averaged over the launches of a step: a forward
+    # pass reads and writes psi once (the first only writes: it starts from
+    # |b0>), a reverse pass psi and lambda (the last only reads them)
     gen = "true" if w.general else "false"   # the diagonal's kernel variant
     vec = 16.0 * dim
     kernels = {}
     # the first H pass reads psi and writes phi, later ones also read phi
     ham_vec = (2.0 + 3.0 * (n_ham - 1)) / max(n_ham, 1)
-    for mode, nvec in (("forward", 2), ("reverse", 4), ("hamiltonian", ham_vec)):
+    fwd_vec = (2.0 * n_fwd - 1.0) / max(n_fwd, 1)
+    rev_vec = (4.0 * n_rev - 2.0) / max(n_rev, 1)
+    for mode, nvec in (("forward", fwd_vec), ("reverse", rev_vec), ("hamiltonian", ham_vec)):
         tot, cnt = kt[mode]
         if cnt == 0:
             continue
         avg = tot / cnt
-        # kernel template: <mode, general diagonal, full tiles, tiles per iteration>
+        # kernel template: <mode, general diagonal, full tiles, tiles per
+        # iteration, from the start state> (the first forward pass of a step
+        # is the one launch of the <..., true> variant)
         nt = 2 if (mode == "forward" and not w.general) else 1
-        kernels[mode] = {"kernel": f"hv::k_pass<{abi.KERNEL_MODES[mode]}, {gen}, true, {nt}>",
+        kernels[mode] = {"kernel": f"hv::k_pass<{abi.KERNEL_MODES[mode]}, {gen}, true, {nt}, false>",
                          "avg_ms": avg, "launches_per_step": cnt // args.steps,
                          "bytes_per_launch": nvec * vec,
                          "GBs": nvec * vec / (avg * 1e-3) / 1e9}

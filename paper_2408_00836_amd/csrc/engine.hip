@@ -19,7 +19,7 @@
 #include "hubvqe.hpp"
 
 namespace hv {
-template <int MODE, bool GEN, bool FULL, int NT>
+template <int MODE, bool GEN, bool FULL, int NT, bool START = false>
 __global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,
                        const DevModel *, double2 *, double2 *, double *, int, uint32_t);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t, uint32_t);
@@ -514,7 +514,12 @@ hubbard_status ensure_model(hubbard_model *h, int dev, DeviceState &ds)
             (const void *)k_pass<M_HAM, false, false, 1>, (const void *)k_pass<M_EXP, false, false, 1>,
             (const void *)k_pass<M_FWD, true, false, 1>,  (const void *)k_pass<M_REV, true, false, 1>,
             (const void *)k_pass<M_HAM, true, false, 1>,  (const void *)k_pass<M_EXP, true, false, 1>,
-            (const void *)k_pass<M_FWD, false, true, 2>};
+            (const void *)k_pass<M_FWD, false, true, 2>,
+            (const void *)k_pass<M_FWD, false, true, 1, true>,
+            (const void *)k_pass<M_FWD, true, true, 1, true>,
+            (const void *)k_pass<M_FWD, false, false, 1, true>,
+            (const void *)k_pass<M_FWD, true, false, 1, true>,
+            (const void *)k_pass<M_FWD, false, true, 2, true>};
         for (const void *f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     });
@@ -525,6 +530,7 @@ hubbard_status ensure_model(hubbard_model *h, int dev, DeviceState &ds)
     dm.n = m.nq;
     dm.ns = m.ns;
     dm.general = m.general ? 1 : 0;
+    dm.b0 = (uint32_t)m.neel;
     dm.U = m.U;
     for (int q = 0; q < kMaxQubits; ++q)
         dm.eps_q[q] = q < m.nq ? m.eps[q < m.ns ? q : q - m.ns] : 0.0;
@@ -611,23 +617,52 @@ struct VecLayout {
     uint32_t ilv = kPlainVec;
 };
 
+// first_flags / last_flags: PassFlags added to the first / last pass of the
+// list for this launch (PF_FROM_START, PF_NO_STORE).
 template <int MODE>
 void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, const double *theta,
                  const double2 *a, const double2 *b, double *partial, hipStream_t s,
-                 hubbard_model *h, VecLayout vl = VecLayout())
+                 hubbard_model *h, VecLayout vl = VecLayout(), int32_t first_flags = 0,
+                 int32_t last_flags = 0)
 {
     for (size_t i = 0; i < pl.pass.size(); ++i) {
+        DevPass P = pl.pass[i];
+        if (i == 0)
+            P.flags |= first_flags;
+        if (i + 1 == pl.pass.size())
+            P.flags |= last_flags;
         const bool timed = launch_mark(h, MODE, s, false);
         // tiles of >= 16 amplitudes fill every register of every thread
         const bool full = pl.pass[i].k >= kRegBits;
         const bool two = pl.nt[i] == 2;
-#define HV_LAUNCH(GEN, FULL, NT)                                                                \
-    hipLaunchKernelGGL((k_pass<MODE, GEN, FULL, NT>), dim3(pl.grid[i]), dim3(pl.threads[i]),    \
-                       pl.smem[i], s, pl.pass[i], pr.d_phases, pr.d_ops, pr.d_vb, theta,        \
+#define HV_LAUNCH(GEN, FULL, NT, ST)                                                            \
+    hipLaunchKernelGGL((k_pass<MODE, GEN, FULL, NT, ST>), dim3(pl.grid[i]), dim3(pl.threads[i]),\
+                       pl.smem[i], s, P, pr.d_phases, pr.d_ops, pr.d_vb, theta,                 \
                        ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax, vl.ilv)
         if constexpr (MODE == M_FWD) {
+            // the first pass from the start state has kernels of its own
+            const bool st = (P.flags & PF_FROM_START) != 0;
             if (two) {   // only planned for U-only models
-                HV_LAUNCH(false, true, 2);
+                if (st)
+                    HV_LAUNCH(false, true, 2, true);
+                else
+                    HV_LAUNCH(false, true, 2, false);
+                if (timed)
+                    launch_mark(h, MODE, s, true);
+                continue;
+            }
+            if (st) {
+                if (pr.general) {
+                    if (full)
+                        HV_LAUNCH(true, true, 1, true);
+                    else
+                        HV_LAUNCH(true, false, 1, true);
+                } else {
+                    if (full)
+                        HV_LAUNCH(false, true, 1, true);
+                    else
+                        HV_LAUNCH(false, false, 1, true);
+                }
                 if (timed)
                     launch_mark(h, MODE, s, true);
                 continue;
@@ -635,14 +670,14 @@ void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, c
         }
         if (pr.general) {
             if (full)
-                HV_LAUNCH(true, true, 1);
+                HV_LAUNCH(true, true, 1, false);
             else
-                HV_LAUNCH(true, false, 1);
+                HV_LAUNCH(true, false, 1, false);
         } else {
             if (full)
-                HV_LAUNCH(false, true, 1);
+                HV_LAUNCH(false, true, 1, false);
             else
-                HV_LAUNCH(false, false, 1);
+                HV_LAUNCH(false, false, 1, false);
         }
 #undef HV_LAUNCH
         if (timed)
@@ -650,11 +685,14 @@ void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, c
     }
 }
 
+// from_start: psi is not read; the first pass starts from |b0> (the caller
+// then skips the init kernel).  Needs at least one forward pass.
 hubbard_status run_forward(const Program &pr, const DeviceState &ds, const double *theta,
                            double2 *psi, hipStream_t s, hubbard_model *h = nullptr,
-                           VecLayout vl = VecLayout())
+                           VecLayout vl = VecLayout(), bool from_start = false)
 {
-    launch_list<M_FWD>(pr, ds, pr.fwd, theta, psi, nullptr, nullptr, s, h, vl);
+    launch_list<M_FWD>(pr, ds, pr.fwd, theta, psi, nullptr, nullptr, s, h, vl,
+                       from_start ? PF_FROM_START : 0);
     return check_launch("forward pass");
 }
 
@@ -1164,12 +1202,14 @@ hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers, do
     hipStream_t s = (hipStream_t)stream;
     double2 *psi = (double2 *)ws_dev;
     double *partial = (double *)((char *)ws_dev + vb);
-    if ((st = run_init(h, psi, s)) != HUBBARD_OK)
+    // the first forward pass starts from |b0> itself (no init pass)
+    const bool from_start = !pr->fwd.pass.empty();
+    if (!from_start && (st = run_init(h, psi, s)) != HUBBARD_OK)
         return st;
     h->ev_used = 0;
     h->kmode.clear();
     mark(h, 0, s);
-    if ((st = run_forward(*pr, *ds, theta_dev, psi, s, h)) != HUBBARD_OK)
+    if ((st = run_forward(*pr, *ds, theta_dev, psi, s, h, VecLayout(), from_start)) != HUBBARD_OK)
         return st;
     mark(h, 1, s);
     launch_list<M_EXP>(*pr, *ds, pr->exp, nullptr, psi, nullptr, partial, s, h);
@@ -1199,18 +1239,22 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
     double2 *lam = vl.ilv == kPlainVec ? (double2 *)((char *)ws_dev + vb)
                                        : psi + ((size_t)1 << vl.ilv);
     double *partial = (double *)((char *)ws_dev + 2 * vb);
-    if ((st = run_init(h, psi, s, vl)) != HUBBARD_OK)
+    // the first forward pass starts from |b0> itself (no init pass), and the
+    // last reverse pass stores nothing: only its reductions are needed
+    const bool from_start = !pr->fwd.pass.empty();
+    if (!from_start && (st = run_init(h, psi, s, vl)) != HUBBARD_OK)
         return st;
     h->ev_used = 0;
     h->kmode.clear();
     mark(h, 0, s);
-    if ((st = run_forward(*pr, *ds, theta_dev, psi, s, h, vl)) != HUBBARD_OK)
+    if ((st = run_forward(*pr, *ds, theta_dev, psi, s, h, vl, from_start)) != HUBBARD_OK)
         return st;
     mark(h, 1, s);
     if ((st = run_ham(*pr, *ds, psi, lam, partial, s, h, vl)) != HUBBARD_OK)
         return st;
     mark(h, 2, s);
-    launch_list<M_REV>(*pr, *ds, pr->rev, theta_dev, psi, lam, partial, s, h, vl);
+    launch_list<M_REV>(*pr, *ds, pr->rev, theta_dev, psi, lam, partial, s, h, vl, 0,
+                       PF_NO_STORE);
     if ((st = check_launch("reverse pass")) != HUBBARD_OK)
         return st;
     mark(h, 3, s);

@@ -32,6 +32,9 @@ enum OpKind : int32_t {
 enum PassFlags : int32_t {
     PF_HAM_FIRST = 1,   // H pass: phi <- D psi + terms (else phi += terms)
     PF_HAM_LAST = 2,    // H pass: also reduce Re <psi|phi> into row 0
+    // set per launch, not planned:
+    PF_FROM_START = 4,  // forward pass: the input is the start state |b0>, not read
+    PF_NO_STORE = 8,    // reverse pass: the vectors are not needed afterwards
 };
 
 // One device operation inside a pass (64 bytes).  The fields a hopping term
@@ -144,7 +147,7 @@ static_assert(sizeof(DevWork) == 32, "DevWork layout");
 struct DevModel {
     int32_t n, ns;
     int32_t general;        // 0: D = U * (#doubly occupied sites) only
-    int32_t pad;
+    uint32_t b0;            // index of the start state (Neel configuration)
     double U;
     double eps_q[kMaxQubits];   // on-site energy of each qubit's site (0 beyond n)
 };

@@ -350,7 +350,7 @@ __device__ __forceinline__ uint64_t vec_offset(uint64_t g, uint32_t ilv)
 // NT = 2 (forward passes only): every iteration takes the tiles tl and
 // tl + tstep, which needs tile_end - tile0 to be a multiple of 2 tstep; the
 // op stream is then decoded once for two tiles.
-template <int MODE, bool GEN, bool FULL, int NT>
+template <int MODE, bool GEN, bool FULL, int NT, bool START = false>
 __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__restrict__ phases,
                                          const DevOp *__restrict__ ops,
                                          const DevVBond *__restrict__ vb,
@@ -460,6 +460,10 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     };
     const uint2 tp0 = thread_part(0);
     const RegLayout L0 = reg_layout(ph[0]);
+    // START (forward only): the input is |b0>; nothing is read
+    constexpr bool from_start = (MODE == M_FWD) && START;
+    const bool no_store = (MODE == M_REV) && (P.flags & PF_NO_STORE);
+    const uint32_t b0 = M->b0;
 
     // Registers of a tile smaller than 16 amplitudes that hold nothing are
     // zero, so they add nothing to any reduction.
@@ -467,6 +471,16 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                           __attribute__((always_inline)) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
+            if constexpr (from_start) {   // |b0>: one amplitude 1, the others 0
+                const uint32_t gt = bs[t] | tp0.x;
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j)
+                    dst[t][j] = make_double2(
+                        (FULL || (act && ((valid >> j) & 1u))) && (gt | L0.goff(j)) == b0 ? 1.0
+                                                                                           : 0.0,
+                        0.0);
+                continue;
+            }
             const uint64_t ga = vec_offset(bs[t] | tp0.x, ilv);
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) {
@@ -623,7 +637,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
         // ---- store from the last phase's layout
         if constexpr (MODE != M_EXP) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
+            for (int t = 0; t < NT && !no_store; ++t) {
                 const uint64_t ga = vec_offset(opaque(gthr[t]), ilv);
 #pragma unroll
                 for (int j = 0; j < kRegs; ++j) {
@@ -669,7 +683,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     __syncthreads();
 }
 
-template <int MODE, bool GEN, bool FULL, int NT>
+template <int MODE, bool GEN, bool FULL, int NT, bool START>
 __global__ void __launch_bounds__(512)
 k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__ ops,
        const DevVBond *__restrict__ vb, const double *__restrict__ theta,
@@ -678,7 +692,7 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
 {
     extern __shared__ __align__(16) char smem[];
     const Sink sink{partial + (size_t)P.red_base * stride + blockIdx.x, stride};
-    run_pass<MODE, GEN, FULL, NT>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x,
+    run_pass<MODE, GEN, FULL, NT, START>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x,
                                   gridDim.x, (uint64_t)1 << P.nfree, ilv, sink);
 }
 
@@ -755,22 +769,24 @@ k_reduce_seg(const double *__restrict__ partial, const int32_t *__restrict__ seg
     }
 }
 
-#define HV_INSTANTIATE(MODE, GEN, FULL, NT)                                                   \
-    template __global__ void k_pass<MODE, GEN, FULL, NT>(                                       \
+#define HV_INSTANTIATE(MODE, GEN, FULL, NT, ST)                                               \
+    template __global__ void k_pass<MODE, GEN, FULL, NT, ST>(                                   \
         DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,             \
         const DevModel *, double2 *, double2 *, double *, int, uint32_t);
 #define HV_INSTANTIATE_ALL(GEN, FULL)                                                           \
-    HV_INSTANTIATE(M_FWD, GEN, FULL, 1)                                                         \
-    HV_INSTANTIATE(M_REV, GEN, FULL, 1)                                                         \
-    HV_INSTANTIATE(M_HAM, GEN, FULL, 1)                                                         \
-    HV_INSTANTIATE(M_EXP, GEN, FULL, 1)
+    HV_INSTANTIATE(M_FWD, GEN, FULL, 1, false)                                                  \
+    HV_INSTANTIATE(M_FWD, GEN, FULL, 1, true)                                                   \
+    HV_INSTANTIATE(M_REV, GEN, FULL, 1, false)                                                  \
+    HV_INSTANTIATE(M_HAM, GEN, FULL, 1, false)                                                  \
+    HV_INSTANTIATE(M_EXP, GEN, FULL, 1, false)
 HV_INSTANTIATE_ALL(false, true)
 HV_INSTANTIATE_ALL(true, true)
 HV_INSTANTIATE_ALL(false, false)
 HV_INSTANTIATE_ALL(true, false)
 // two tiles per iteration: forward passes over full tiles, U-only models
 // (the general diagonal's per-amplitude sincos needs the registers)
-HV_INSTANTIATE(M_FWD, false, true, 2)
+HV_INSTANTIATE(M_FWD, false, true, 2, false)
+HV_INSTANTIATE(M_FWD, false, true, 2, true)
 #undef HV_INSTANTIATE_ALL
 #undef HV_INSTANTIATE
 
