@@ -71,6 +71,54 @@ __device__ __forceinline__ double diag_value(const DevOp &op, uint32_t g, const 
     return d;
 }
 
+// The general diagonal sub-term D_sub at the 16 registers of a thread:
+// g_j = gt | goff(j).  The eps sum is additive over disjoint bits, so the
+// thread's part is looked up once and each register bit's part once; the V
+// classes are the outer loop, so that no loop runs inside the unrolled
+// register loop.
+template <typename Layout>
+__device__ __forceinline__ void diag_values(const DevOp &op, uint32_t gt, const Layout &L,
+                                            const DevModel *M, const DevVBond *vb,
+                                            const double *etab, double (&dv)[kRegs])
+{
+    const uint32_t ns = M->ns;
+    double et = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        et += etab[k * 16 + ((gt >> (4 * k)) & 15u)];
+    double er[kRegBits];
+#pragma unroll
+    for (int i = 0; i < kRegBits; ++i) {
+        const uint32_t b = L.gb[i];   // one global bit, or 0 (phantom register bit)
+        const int p = b ? __builtin_ctz(b) : 0;
+        er[i] = b ? etab[(p >> 2) * 16 + (1u << (p & 3))] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {
+        double e = et;
+#pragma unroll
+        for (int i = 0; i < kRegBits; ++i)
+            if ((j >> i) & 1)
+                e += er[i];
+        const uint32_t g = gt | L.goff(j);
+        dv[j] = M->U * (double)__popc(g & (g >> ns) & op.umask) + e;
+    }
+    const uint32_t smask = (1u << ns) - 1u;
+    for (int c = op.v_begin; c < op.v_end; ++c) {
+        const DevVBond B = vb[c];
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            const uint32_t g = gt | L.goff(j);
+            const uint32_t U = g & smask, D = (g >> ns) & smask;
+            const uint32_t Us = B.delta >= 0 ? U >> B.delta : U << -B.delta;
+            const uint32_t Ds = B.delta >= 0 ? D >> B.delta : D << -B.delta;
+            const int cnt = __popc(U & Us & B.src) + __popc(U & Ds & B.src) +
+                            __popc(D & Us & B.src) + __popc(D & Ds & B.src);
+            dv[j] += B.V * (double)cnt;
+        }
+    }
+}
+
 // exp(-i x) for the general diagonal: x = k h + r with h = 2 pi / 2^kCisBits
 // (Cody-Waite reduction with a two-part h whose leading part has 36
 // significant bits, exact for |k| < 2^17), the phase of k h from the LDS
@@ -560,6 +608,13 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                         // recomputed per op: hoisted out of the op loop, the
                         // 16 indices would only occupy (or spill) registers
                         const uint32_t gt = opaque(gthr[t]);
+                        // general diagonal: D_sub at each register, computed
+                        // together (the expectation passes keep the per-register
+                        // form, which needs fewer registers there)
+                        constexpr bool DV = GEN && MODE != M_EXP;
+                        double dv[kRegs];
+                        if constexpr (DV)
+                            diag_values(op, gt, L, M, vb, etab + op.dtab * 128, dv);
 #pragma unroll
                         for (int j = 0; j < kRegs; ++j) {
                             if (!FULL && !((valid >> j) & 1u))
@@ -575,7 +630,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                                     if constexpr (MODE == M_REV)
                                         d = M->U * (double)__popc(dbl);
                                 } else {
-                                    d = diag_value<GEN>(op, g, M, vb, etab + op.dtab * 128);
+                                    d = dv[j];
                                     phs = cis_neg(sign * th_op * d, cis);
                                 }
                                 if constexpr (MODE == M_REV) {
@@ -585,7 +640,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                                 a = cmul(a, phs);
                             } else if constexpr (MODE == M_HAM) {
                                 const double d =
-                                    diag_value<GEN>(op, g, M, vb, etab + op.dtab * 128);
+                                    GEN ? dv[j] : diag_value<GEN>(op, g, M, vb, etab + op.dtab * 128);
                                 v[1][j].x += d * a.x;
                                 v[1][j].y += d * a.y;
                             } else {
