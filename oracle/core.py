@@ -67,6 +67,8 @@ def lib():
         L.orc_apply_slot.argtypes = [P(_Model), ci, cd, vp]
         L.orc_generator_apply.argtypes = [P(_Model), ci, vp, vp]
         L.orc_ham_apply.argtypes = [P(_Model), vp, vp]
+        L.orc_ham_row.argtypes = [P(_Model), cu64, vp, vp]
+        L.orc_ham_row.restype = ci
         L.orc_inner.argtypes = [ci, vp, vp, P(cd), P(cd)]
         L.orc_ansatz.argtypes = [P(_Model), vp, ci, cu64, vp]
         L.orc_expectation.argtypes = [P(_Model), vp, vp]
@@ -141,6 +143,17 @@ def ham_apply(m: OracleModel, psi: np.ndarray) -> np.ndarray:
     out = _vec(m)
     lib().orc_ham_apply(ctypes.byref(_cmodel(m)), _ptr(np.ascontiguousarray(psi)), _ptr(out))
     return out
+
+
+def ham_row(m: OracleModel, b: int):
+    """Row b of H as (columns, coefficients): (H psi)_b = sum coef * psi[col].
+    Works at any size (32 qubits included): it touches only the row."""
+    cm = _cmodel(m)
+    cap = 1 + 2 * len(m.bonds)
+    cols = np.zeros(cap, dtype=np.uint64)
+    coefs = np.zeros(cap, dtype=np.float64)
+    k = lib().orc_ham_row(ctypes.byref(cm), int(b), _ptr(cols), _ptr(coefs))
+    return cols[:k], coefs[:k]
 
 
 def inner(a: np.ndarray, b: np.ndarray) -> complex:

@@ -237,6 +237,32 @@ void orc_ham_apply(const orc_model *m, const cplx *psi, cplx *out)
     }
 }
 
+/* Row b of H (Eq. (1) with the terms of Eq. (2), (15), (16)): H|b'> has
+ * amplitude <b|H|b'> at b, so (H psi)_b = sum over the row of coef * psi[col].
+ * The row holds the diagonal D(b) at col = b and, for every bond and spin
+ * whose two qubits differ in occupation, -t_b times the Jordan-Wigner sign at
+ * col = b ^ (2^p + 2^q).  cols/coefs need room for 1 + 2 * nbonds entries;
+ * returns the number written. */
+int orc_ham_row(const orc_model *m, uint64_t b, uint64_t *cols, double *coefs)
+{
+    int k = 0;
+    cols[k] = b;
+    coefs[k] = diag_value(m, b);
+    k++;
+    for (int e = 0; e < m->nbonds; e++) {
+        for (int spin = 0; spin < 2; spin++) {
+            int p = qubit_of(m, m->bond_i[e], spin);
+            int q = qubit_of(m, m->bond_j[e], spin);
+            if (bit(b, p) != bit(b, q)) {
+                cols[k] = b ^ (((uint64_t)1 << p) | ((uint64_t)1 << q));
+                coefs[k] = -m->t[e] * jw_sign(b, p, q);
+                k++;
+            }
+        }
+    }
+    return k;
+}
+
 /* <a|b> = sum_b conj(a_b) b_b, compensated, chunk-deterministic. */
 void orc_inner(int n, const cplx *a, const cplx *b, double *re, double *im)
 {

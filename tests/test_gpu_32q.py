@@ -12,7 +12,9 @@ size:
     four 4-site ring states, each from the 8-qubit oracle; E and the U/h
     gradients are sums over rows;
   * at the benchmark's own theta: E(th) = E(-th), grad odd, norm 1, adjoint vs
-    central finite differences of the GPU energy.
+    central finite differences of the GPU energy;
+  * H|psi> of a seeded random vector (torch's generator, not the library):
+    sampled outputs against single rows of H from the oracle.
 """
 import sys
 
@@ -180,3 +182,29 @@ def test_symmetry_norm_and_fd_32q(c5):
         tm[k] -= h
         fd = (m.energy(tp).item() - m.energy(tm).item()) / (2 * h)
         assert abs(fd - g1[k]) < GRAD_TOL, (k, fd, g1[k])
+
+
+def test_hamiltonian_apply_sampled_32q(c5):
+    w, m, om = c5
+    psi, out = m.workspace_views(w.layers)   # the buffers bench.py times H|psi> on
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    say("[32q] random psi (64 GiB), hamiltonian_apply")
+    torch.view_as_real(psi).normal_(generator=gen)
+    m.apply_h(psi, out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    idx = sector_samples(rng, 100)
+    idx += [int(b) for b in rng.integers(0, 1 << 32, 100, dtype=np.uint64)]
+    idx += [0, (1 << 32) - 1, om.neel_index()]
+    rows = [oc.ham_row(om, b) for b in idx]
+    cols = np.concatenate([c for c, _ in rows]).astype(np.int64)
+    vals = psi[torch.tensor(cols, device="cuda")].cpu().numpy()
+    got = out[torch.tensor(idx, device="cuda")].cpu().numpy()
+    at = 0
+    for b, (c, coef), g in zip(idx, rows, got):
+        v = vals[at:at + len(c)]
+        at += len(c)
+        want = np.sum(coef * v)
+        scale = max(1.0, float(np.sum(np.abs(coef * v))))
+        assert abs(g - want) <= 1e-12 * scale, (b, g, want)

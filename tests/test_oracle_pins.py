@@ -132,6 +132,21 @@ def test_dense_hamiltonian_matches(oracle_lib, case):
 
 
 @pytest.mark.parametrize("case", DENSE_CASES)
+def test_ham_row_matches_dense(oracle_lib, case):
+    # the row form used for sampled checks at 32 qubits, against the dense
+    # Kronecker-product H (an independent construction of the same operator)
+    m, _ = dense_case(case)
+    _, H = od.generators(m)
+    Hd = H.toarray()
+    for b in range(1 << m.nqubits):
+        row = np.zeros(1 << m.nqubits, dtype=np.complex128)
+        cols, coefs = oc.ham_row(m, b)
+        for c, v in zip(cols, coefs):
+            row[int(c)] += v
+        assert np.max(np.abs(row - Hd[b])) < 1e-13
+
+
+@pytest.mark.parametrize("case", DENSE_CASES)
 def test_dense_circuit_energy_gradient(oracle_lib, case):
     """Amplitudes from eigendecomposed exp(-i th G) products, E from the dense
     H, gradient by forward-mode differentiation -- all independent of the
