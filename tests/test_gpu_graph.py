@@ -38,6 +38,8 @@ CASES = [
     dict(n=8, nb=12, seed=3, U=6.0, general=True, tiles=(8, 7, 3)),
     dict(n=8, nb=9, seed=4, U=3.0, general=False, tiles=(6, 6, 2)),
     dict(n=9, nb=14, seed=5, U=1.5, general=True, tiles=(10, 9, 4)),
+    # a different V on every bond: many V classes per diagonal op
+    dict(n=8, nb=13, seed=6, U=3.5, general=True, tiles=(7, 6, 2), v_each=True),
 ]
 
 
@@ -48,7 +50,8 @@ def test_graph_parity(gpu, case):
     nb = len(bonds)
     kw = dict(t=1 + 0.2 * rng.standard_normal(nb), U=c["U"])
     if c["general"]:
-        kw.update(V=np.full(nb, 0.3), eps=rng.uniform(-0.5, 0.5, c["n"]))
+        V = rng.uniform(-0.6, 0.6, nb) if c.get("v_each") else np.full(nb, 0.3)
+        kw.update(V=V, eps=rng.uniform(-0.5, 0.5, c["n"]))
     spins = [int(x) for x in rng.integers(0, 2, c["n"])]
     om = make_graph_model(c["n"], bonds, site_spin=spins, **kw)
     m = Hubbard.graph(c["n"], bonds, site_spin=spins, **kw)
