@@ -24,7 +24,7 @@ __global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond 
                        const DevModel *, double2 *, double2 *, double *, int, uint32_t);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t, uint32_t);
 __global__ void k_batch_init(const DevInstance *);
-template <int MODE>
+template <int MODE, bool GEN>
 __global__ void k_batch_pass(const DevInstance *, const DevPass *, const DevWork *, double *);
 __global__ void k_reduce_seg(const double *, const int32_t *, const int64_t *, const int32_t *,
                              const double *, const int64_t *, int, double *, double *);
@@ -788,6 +788,7 @@ struct BatchLayout {
     size_t partial_at = 0;      // byte offset of the partial sums
     size_t n_partial = 0;       // doubles
     size_t ws_bytes = 0;
+    bool general = false;       // any instance has eps or V terms: the general path for all
 };
 
 hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
@@ -795,6 +796,9 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
 {
     const int lim = max_smem_per_block();
     size_t at = 0;
+    L.general = false;
+    for (int i = 0; i < n; ++i)
+        L.general = L.general || progs[i]->general;
     L.voff.resize(n);
     for (int i = 0; i < n; ++i) {
         L.voff[i] = at;
@@ -982,8 +986,10 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
         const int lim = max_smem_per_block();
-        const void *fns[] = {(const void *)k_batch_pass<M_FWD>, (const void *)k_batch_pass<M_HAM>,
-                             (const void *)k_batch_pass<M_REV>};
+        const void *fns[] = {
+            (const void *)k_batch_pass<M_FWD, false>, (const void *)k_batch_pass<M_HAM, false>,
+            (const void *)k_batch_pass<M_REV, false>, (const void *)k_batch_pass<M_FWD, true>,
+            (const void *)k_batch_pass<M_HAM, true>,  (const void *)k_batch_pass<M_REV, true>};
         for (const void *f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     });
@@ -1327,15 +1333,25 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
     hipLaunchKernelGGL(k_batch_init, dim3(n, bp->init_y), dim3(256), 0, s, bp->d_inst);
     for (const BatchLaunch &bl : L.launches) {
         const DevWork *w = bp->d_work + bl.item0;
-        if (bl.mode == M_FWD)
-            hipLaunchKernelGGL(k_batch_pass<M_FWD>, dim3(bl.n_items), dim3(bl.threads), bl.smem,
-                               s, bp->d_inst, bp->d_passes, w, partial);
-        else if (bl.mode == M_HAM)
-            hipLaunchKernelGGL(k_batch_pass<M_HAM>, dim3(bl.n_items), dim3(bl.threads), bl.smem,
-                               s, bp->d_inst, bp->d_passes, w, partial);
-        else
-            hipLaunchKernelGGL(k_batch_pass<M_REV>, dim3(bl.n_items), dim3(bl.threads), bl.smem,
-                               s, bp->d_inst, bp->d_passes, w, partial);
+#define HV_BATCH_LAUNCH(MODE, GEN)                                                              \
+    hipLaunchKernelGGL((k_batch_pass<MODE, GEN>), dim3(bl.n_items), dim3(bl.threads), bl.smem, \
+                       s, bp->d_inst, bp->d_passes, w, partial)
+        if (L.general) {
+            if (bl.mode == M_FWD)
+                HV_BATCH_LAUNCH(M_FWD, true);
+            else if (bl.mode == M_HAM)
+                HV_BATCH_LAUNCH(M_HAM, true);
+            else
+                HV_BATCH_LAUNCH(M_REV, true);
+        } else {
+            if (bl.mode == M_FWD)
+                HV_BATCH_LAUNCH(M_FWD, false);
+            else if (bl.mode == M_HAM)
+                HV_BATCH_LAUNCH(M_HAM, false);
+            else
+                HV_BATCH_LAUNCH(M_REV, false);
+        }
+#undef HV_BATCH_LAUNCH
     }
     hipLaunchKernelGGL(k_reduce_seg, dim3((unsigned)L.scale.size()), dim3(256), 0, s, partial,
                        bp->d_seg_ptr, bp->d_seg_off, bp->d_seg_cnt, bp->d_scale, bp->d_out_idx, n,

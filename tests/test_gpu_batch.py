@@ -82,11 +82,14 @@ def test_batch_graph_replay(batch256):
 
 
 def test_small_batches(gpu):
-    # one instance; and a mix of general and U-only models with odd sizes
+    # one instance; a mix of general and U-only models with odd sizes (the
+    # general path for all); U-only models only (the U-only path), 18 qubits
+    # with full tiles among them
     w1 = W.random_instance(2, 3, 3, 5, 71, U=4.0, disorder=0.1, eps_width=0.5, V=0.5)
     w2 = W.random_instance(1, 5, 4, 3, 72, U=2.0)
     w3 = W.random_instance(3, 3, 2, 5, 73, U=6.0, disorder=0.1)
-    for group in ([w1], [w1, w2, w3]):
+    assert w1.general and not w2.general and not w3.general
+    for group in ([w1], [w1, w2, w3], [w2, w3]):
         models = [Hubbard(w.nx, w.ny, **w.kwargs()) for w in group]
         b = Batch(models, [w.layers for w in group])
         th = torch.tensor(np.concatenate([w.theta for w in group]), dtype=torch.float64,
