@@ -24,7 +24,7 @@ __global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond 
                        const DevModel *, double2 *, double2 *, double *, int, uint32_t);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t, uint32_t);
 __global__ void k_batch_init(const DevInstance *);
-template <int MODE, bool GEN>
+template <int MODE, bool GEN, bool FULL>
 __global__ void k_batch_pass(const DevInstance *, const DevPass *, const DevWork *, double *);
 __global__ void k_reduce_seg(const double *, const int32_t *, const int64_t *, const int32_t *,
                              const double *, const int64_t *, int, double *, double *);
@@ -767,6 +767,7 @@ constexpr int kBatchItems = 64;
 
 struct BatchLaunch {
     int mode;               // M_FWD, M_HAM or M_REV
+    bool full;              // every item's tiles fill all registers of exactly `threads`
     int item0, n_items;     // work items [item0, item0 + n_items)
     int threads, smem;
 };
@@ -837,56 +838,73 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
             longest = std::max(longest, pl.pass.size());
         }
         for (size_t j = 0; j < longest; ++j) {
-            BatchLaunch bl;
-            bl.mode = modes[ph];
-            bl.item0 = (int)L.work.size();
-            bl.threads = 64;
-            std::vector<const DevPass *> used;
+            // pass j of every instance that has one; the widest pass sets the
+            // workgroup size, and the passes whose tiles fill all registers of
+            // exactly that many threads get a launch of their own on the
+            // guard-free full-tile path
+            std::vector<int> inst;
+            int widest = 64;
             for (int i = 0; i < n; ++i) {
-                const Program &pr = *progs[i];
-                const PassList &pl = ph == 0 ? pr.fwd : ph == 1 ? pr.ham : pr.rev;
+                const PassList &pl = ph == 0 ? progs[i]->fwd : ph == 1 ? progs[i]->ham : progs[i]->rev;
                 if (j >= pl.pass.size())
                     continue;
-                const DevPass &P = pl.pass[j];
-                const size_t off = (ph == 0 ? 0 : ph == 1 ? pr.fwd.pass.size()
-                                                           : pr.fwd.pass.size() + pr.ham.pass.size());
-                const uint64_t ntiles = (uint64_t)1 << P.nfree;
-                const uint32_t items = (uint32_t)std::min<uint64_t>(ntiles, kBatchItems);
-                const uint32_t per = (uint32_t)(ntiles / items);
-                const int nred = P.n_red;
-                const size_t part0 = L.n_partial;
-                L.n_partial += (size_t)nred * items;
-                for (int r = 0; r < nred; ++r) {
-                    const int prm = pr.row_param[P.red_base + r];
-                    const size_t o = prm < 0 ? (size_t)i : gbase[i] + (size_t)prm;
-                    segs[o].push_back({(int64_t)(part0 + (size_t)r * items), (int32_t)items});
-                }
-                for (uint32_t b = 0; b < items; ++b) {
-                    DevWork w;
-                    std::memset(&w, 0, sizeof(w));
-                    w.inst = i;
-                    w.pass = (int32_t)(pbase[i] + off + j);
-                    w.tile0 = b * per;
-                    w.tile1 = (b + 1) * per;
-                    w.part = (int64_t)(part0 + b);
-                    w.stride = (int32_t)items;
-                    L.work.push_back(w);
-                }
-                bl.threads = std::max(bl.threads, 1 << P.tbits);
-                used.push_back(&P);
+                inst.push_back(i);
+                widest = std::max(widest, 1 << pl.pass[j].tbits);
             }
-            bl.n_items = (int)L.work.size() - bl.item0;
-            bl.smem = 0;
-            for (const DevPass *P : used)
-                bl.smem = std::max(bl.smem, (int)smem_plan(P->k, P->n_ops, P->n_diag, P->n_red,
-                                                           P->n_phases, bl.threads, P->nfree == 0,
-                                                           true)
-                                                .total);
-            if (bl.smem > lim)
-                return fail(HUBBARD_ERR_ARG,
-                            "a batch instance needs more LDS than a workgroup may use");
-            if (bl.n_items > 0)
-                L.launches.push_back(bl);
+            for (int full = 1; full >= 0; --full) {
+                BatchLaunch bl;
+                bl.mode = modes[ph];
+                bl.full = full != 0;
+                bl.item0 = (int)L.work.size();
+                bl.threads = 64;
+                std::vector<const DevPass *> used;
+                for (int i : inst) {
+                    const Program &pr = *progs[i];
+                    const PassList &pl = ph == 0 ? pr.fwd : ph == 1 ? pr.ham : pr.rev;
+                    const DevPass &P = pl.pass[j];
+                    const bool fills = P.k >= kRegBits && (1 << P.tbits) == widest;
+                    if (fills != bl.full)
+                        continue;
+                    const size_t off = (ph == 0 ? 0 : ph == 1 ? pr.fwd.pass.size()
+                                                               : pr.fwd.pass.size() + pr.ham.pass.size());
+                    const uint64_t ntiles = (uint64_t)1 << P.nfree;
+                    const uint32_t items = (uint32_t)std::min<uint64_t>(ntiles, kBatchItems);
+                    const uint32_t per = (uint32_t)(ntiles / items);
+                    const int nred = P.n_red;
+                    const size_t part0 = L.n_partial;
+                    L.n_partial += (size_t)nred * items;
+                    for (int r = 0; r < nred; ++r) {
+                        const int prm = pr.row_param[P.red_base + r];
+                        const size_t o = prm < 0 ? (size_t)i : gbase[i] + (size_t)prm;
+                        segs[o].push_back({(int64_t)(part0 + (size_t)r * items), (int32_t)items});
+                    }
+                    for (uint32_t b = 0; b < items; ++b) {
+                        DevWork w;
+                        std::memset(&w, 0, sizeof(w));
+                        w.inst = i;
+                        w.pass = (int32_t)(pbase[i] + off + j);
+                        w.tile0 = b * per;
+                        w.tile1 = (b + 1) * per;
+                        w.part = (int64_t)(part0 + b);
+                        w.stride = (int32_t)items;
+                        L.work.push_back(w);
+                    }
+                    bl.threads = std::max(bl.threads, 1 << P.tbits);
+                    used.push_back(&P);
+                }
+                bl.n_items = (int)L.work.size() - bl.item0;
+                bl.smem = 0;
+                for (const DevPass *P : used)
+                    bl.smem = std::max(bl.smem, (int)smem_plan(P->k, P->n_ops, P->n_diag, P->n_red,
+                                                               P->n_phases, bl.threads,
+                                                               P->nfree == 0, true)
+                                                    .total);
+                if (bl.smem > lim)
+                    return fail(HUBBARD_ERR_ARG,
+                                "a batch instance needs more LDS than a workgroup may use");
+                if (bl.n_items > 0)
+                    L.launches.push_back(bl);
+            }
         }
     }
     for (size_t o = 0; o < n_out; ++o) {
@@ -987,9 +1005,12 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
     std::call_once(attr_once, [] {
         const int lim = max_smem_per_block();
         const void *fns[] = {
-            (const void *)k_batch_pass<M_FWD, false>, (const void *)k_batch_pass<M_HAM, false>,
-            (const void *)k_batch_pass<M_REV, false>, (const void *)k_batch_pass<M_FWD, true>,
-            (const void *)k_batch_pass<M_HAM, true>,  (const void *)k_batch_pass<M_REV, true>};
+#define HV_BATCH_FNS(GEN, FULL)                                                                 \
+    (const void *)k_batch_pass<M_FWD, GEN, FULL>, (const void *)k_batch_pass<M_HAM, GEN, FULL>, \
+        (const void *)k_batch_pass<M_REV, GEN, FULL>
+            HV_BATCH_FNS(false, false), HV_BATCH_FNS(false, true), HV_BATCH_FNS(true, false),
+            HV_BATCH_FNS(true, true)};
+#undef HV_BATCH_FNS
         for (const void *f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     });
@@ -1333,24 +1354,30 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
     hipLaunchKernelGGL(k_batch_init, dim3(n, bp->init_y), dim3(256), 0, s, bp->d_inst);
     for (const BatchLaunch &bl : L.launches) {
         const DevWork *w = bp->d_work + bl.item0;
-#define HV_BATCH_LAUNCH(MODE, GEN)                                                              \
-    hipLaunchKernelGGL((k_batch_pass<MODE, GEN>), dim3(bl.n_items), dim3(bl.threads), bl.smem, \
-                       s, bp->d_inst, bp->d_passes, w, partial)
+#define HV_BATCH_LAUNCH(MODE, GEN, FULL)                                                        \
+    hipLaunchKernelGGL((k_batch_pass<MODE, GEN, FULL>), dim3(bl.n_items), dim3(bl.threads),    \
+                       bl.smem, s, bp->d_inst, bp->d_passes, w, partial)
+#define HV_BATCH_MODE(GEN, FULL)                                                                \
+    do {                                                                                        \
+        if (bl.mode == M_FWD)                                                                   \
+            HV_BATCH_LAUNCH(M_FWD, GEN, FULL);                                                  \
+        else if (bl.mode == M_HAM)                                                              \
+            HV_BATCH_LAUNCH(M_HAM, GEN, FULL);                                                  \
+        else                                                                                    \
+            HV_BATCH_LAUNCH(M_REV, GEN, FULL);                                                  \
+    } while (0)
         if (L.general) {
-            if (bl.mode == M_FWD)
-                HV_BATCH_LAUNCH(M_FWD, true);
-            else if (bl.mode == M_HAM)
-                HV_BATCH_LAUNCH(M_HAM, true);
+            if (bl.full)
+                HV_BATCH_MODE(true, true);
             else
-                HV_BATCH_LAUNCH(M_REV, true);
+                HV_BATCH_MODE(true, false);
         } else {
-            if (bl.mode == M_FWD)
-                HV_BATCH_LAUNCH(M_FWD, false);
-            else if (bl.mode == M_HAM)
-                HV_BATCH_LAUNCH(M_HAM, false);
+            if (bl.full)
+                HV_BATCH_MODE(false, true);
             else
-                HV_BATCH_LAUNCH(M_REV, false);
+                HV_BATCH_MODE(false, false);
         }
+#undef HV_BATCH_MODE
 #undef HV_BATCH_LAUNCH
     }
     hipLaunchKernelGGL(k_reduce_seg, dim3((unsigned)L.scale.size()), dim3(256), 0, s, partial,

@@ -770,9 +770,10 @@ __global__ void k_batch_init(const DevInstance *__restrict__ inst)
 // GEN: the launch runs the general-diagonal path for every instance (a
 // batch with any eps or V term; the path also holds for U-only instances,
 // whose eps tables are zero and V classes empty), else the U-only path.
-// Instances whose tiles fill all registers of exactly the launch's threads
-// take the guard-free full-tile path.
-template <int MODE, bool GEN>
+// FULL: every item's tiles fill all registers of exactly the launch's
+// threads (the guard-free path; a launch of its own keeps the two paths'
+// registers apart).
+template <int MODE, bool GEN, bool FULL>
 __global__ void __launch_bounds__(512)
 k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ passes,
              const DevWork *__restrict__ work, double *__restrict__ partial)
@@ -782,23 +783,21 @@ k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ p
     const DevInstance I = inst[w.inst];
     const DevPass P = passes[w.pass];
     const Sink sink{partial + w.part, w.stride};
-    double2 *psi = (double2 *)I.psi, *lam = (double2 *)I.lam;
-    if (P.k >= kRegBits && (1u << P.tbits) == blockDim.x)
-        run_pass<MODE, GEN, true, 1>(P, I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                     smem, w.tile0, 1, w.tile1, 32u, sink);
-    else
-        run_pass<MODE, GEN, false, 1>(P, I.phases, I.ops, I.vb, I.theta, I.model, psi, lam,
-                                      smem, w.tile0, 1, w.tile1, 32u, sink);
+    run_pass<MODE, GEN, FULL, 1>(P, I.phases, I.ops, I.vb, I.theta, I.model, (double2 *)I.psi,
+                                 (double2 *)I.lam, smem, w.tile0, 1, w.tile1, 32u, sink);
 }
-#define HV_BATCH(MODE, GEN)                                                                     \
-    template __global__ void k_batch_pass<MODE, GEN>(const DevInstance *, const DevPass *,     \
-                                                     const DevWork *, double *);
-HV_BATCH(M_FWD, false)
-HV_BATCH(M_HAM, false)
-HV_BATCH(M_REV, false)
-HV_BATCH(M_FWD, true)
-HV_BATCH(M_HAM, true)
-HV_BATCH(M_REV, true)
+#define HV_BATCH(MODE, GEN, FULL)                                                               \
+    template __global__ void k_batch_pass<MODE, GEN, FULL>(const DevInstance *, const DevPass *,\
+                                                           const DevWork *, double *);
+#define HV_BATCH_ALL(GEN, FULL)                                                                 \
+    HV_BATCH(M_FWD, GEN, FULL)                                                                  \
+    HV_BATCH(M_HAM, GEN, FULL)                                                                  \
+    HV_BATCH(M_REV, GEN, FULL)
+HV_BATCH_ALL(false, false)
+HV_BATCH_ALL(false, true)
+HV_BATCH_ALL(true, false)
+HV_BATCH_ALL(true, true)
+#undef HV_BATCH_ALL
 #undef HV_BATCH
 
 // out = scale[o] * sum over segments seg_ptr[o] .. seg_ptr[o+1] of the
