@@ -175,7 +175,8 @@ hubbard_status hamiltonian_apply(hubbard_t h, const void *psi_dev, void *out_dev
                                  void *stream);
 
 /* Eq. (4): E_dev[0] <- <psi(theta)|H|psi(theta)> with psi(theta) prepared
- * from the start state in the workspace.  ws_dev must hold
+ * from the start state |b0> in the workspace (the workspace's contents on
+ * entry are not read).  ws_dev must hold
  * hubbard_workspace_size(..., HUBBARD_OP_ENERGY) bytes (HUBBARD_ERR_SIZE). */
 hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers,
                       double *E_dev, void *ws_dev, size_t ws_bytes, void *stream);
@@ -184,7 +185,9 @@ hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers,
  * grad_dev[k] = dE/dtheta_k = 2 Im <lambda_k| G_k |psi_k> for all
  * P = n_layers * params_per_layer parameters, computed in one reverse sweep
  * that un-applies the gates to psi and lambda = H psi in the workspace.
- * ws_dev must hold hubbard_workspace_size(..., HUBBARD_OP_ENERGY_GRAD). */
+ * ws_dev must hold hubbard_workspace_size(..., HUBBARD_OP_ENERGY_GRAD); its
+ * contents on entry are not read, and on return they are scratch (psi and
+ * lambda are kept there in a layout of the library's own). */
 hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,
                            double *E_dev, double *grad_dev, void *ws_dev,
                            size_t ws_bytes, void *stream);
