@@ -196,8 +196,9 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
  * lattices, sizes, U, disorder, V and layer counts; each its own parameters)
  * with no host work per call: a fixed sequence of launches on `stream` -- the
  * start states of all instances, then, for each position j of the forward, H
- * and reverse schedules, one launch that runs pass j of every instance that
- * has one (a large instance's tiles spread over many workgroups), then one
+ * and reverse schedules, launches that run pass j of every instance that has
+ * one (two: passes whose tiles fill the workgroup's registers exactly, and
+ * the others; a large instance's tiles spread over many workgroups), then one
  * reduction of the partial sums into E and the gradients, in a fixed order
  * (results are reproducible run to run).
  *   hs[i]           instance handles (n >= 1)
