@@ -47,9 +47,9 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t x, uint32_t mask)
 // Diagonal sub-term value D_sub(g); GEN: the model has eps or V terms.
 // etab: the op's eight nibble tables of its eps sum (LDS); vb: its V bond
 // classes (see DevVBond).
-template <bool GEN>
-__device__ __forceinline__ double diag_value(const DevOp &op, uint32_t g, const DevModel *M,
-                                             const DevVBond *vb, const double *etab)
+template <bool GEN, typename OpT, typename MT, typename VbT>
+__device__ __forceinline__ double diag_value(const OpT &op, uint32_t g, const MT *M,
+                                             const VbT *vb, const double *etab)
 {
     const uint32_t dn = (uint32_t)((uint64_t)g >> M->ns);
     double d = M->U * (double)__popc(g & dn & op.umask);
@@ -60,12 +60,13 @@ __device__ __forceinline__ double diag_value(const DevOp &op, uint32_t g, const 
         const uint32_t smask = (1u << M->ns) - 1u;
         const uint32_t U = g & smask, D = dn & smask;
         for (int v = op.v_begin; v < op.v_end; ++v) {
-            const DevVBond B = vb[v];
-            const uint32_t Us = B.delta >= 0 ? U >> B.delta : U << -B.delta;
-            const uint32_t Ds = B.delta >= 0 ? D >> B.delta : D << -B.delta;
-            const int cnt = __popc(U & Us & B.src) + __popc(U & Ds & B.src) +
-                            __popc(D & Us & B.src) + __popc(D & Ds & B.src);
-            d += B.V * (double)cnt;
+            const uint32_t src = vb[v].src;
+            const int32_t delta = vb[v].delta;
+            const uint32_t Us = delta >= 0 ? U >> delta : U << -delta;
+            const uint32_t Ds = delta >= 0 ? D >> delta : D << -delta;
+            const int cnt = __popc(U & Us & src) + __popc(U & Ds & src) + __popc(D & Us & src) +
+                            __popc(D & Ds & src);
+            d += vb[v].V * (double)cnt;
         }
     }
     return d;
@@ -76,10 +77,10 @@ __device__ __forceinline__ double diag_value(const DevOp &op, uint32_t g, const 
 // thread's part is looked up once and each register bit's part once; the V
 // classes are the outer loop, so that no loop runs inside the unrolled
 // register loop.
-template <typename Layout>
-__device__ __forceinline__ void diag_values(const DevOp &op, uint32_t gt, const Layout &L,
-                                            const DevModel *M, const DevVBond *vb,
-                                            const double *etab, double (&dv)[kRegs])
+template <typename Layout, typename OpT, typename MT, typename VbT>
+__device__ __forceinline__ void diag_values(const OpT &op, uint32_t gt, const Layout &L,
+                                            const MT *M, const VbT *vb, const double *etab,
+                                            double (&dv)[kRegs])
 {
     const uint32_t ns = M->ns;
     double et = 0.0;
@@ -105,16 +106,18 @@ __device__ __forceinline__ void diag_values(const DevOp &op, uint32_t gt, const 
     }
     const uint32_t smask = (1u << ns) - 1u;
     for (int c = op.v_begin; c < op.v_end; ++c) {
-        const DevVBond B = vb[c];
+        const uint32_t src = vb[c].src;
+        const int32_t delta = vb[c].delta;
+        const double V = vb[c].V;
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) {
             const uint32_t g = gt | L.goff(j);
             const uint32_t U = g & smask, D = (g >> ns) & smask;
-            const uint32_t Us = B.delta >= 0 ? U >> B.delta : U << -B.delta;
-            const uint32_t Ds = B.delta >= 0 ? D >> B.delta : D << -B.delta;
-            const int cnt = __popc(U & Us & B.src) + __popc(U & Ds & B.src) +
-                            __popc(D & Us & B.src) + __popc(D & Ds & B.src);
-            dv[j] += B.V * (double)cnt;
+            const uint32_t Us = delta >= 0 ? U >> delta : U << -delta;
+            const uint32_t Ds = delta >= 0 ? D >> delta : D << -delta;
+            const int cnt = __popc(U & Us & src) + __popc(U & Ds & src) + __popc(D & Us & src) +
+                            __popc(D & Ds & src);
+            dv[j] += V * (double)cnt;
         }
     }
 }
@@ -269,7 +272,8 @@ struct RegLayout {
     }
 };
 
-__device__ __forceinline__ RegLayout reg_layout(const DevPhase &ph)
+template <typename PhT>
+__device__ __forceinline__ RegLayout reg_layout(const PhT &ph)
 {
     RegLayout r;
 #pragma unroll
@@ -398,13 +402,32 @@ __device__ __forceinline__ uint64_t vec_offset(uint64_t g, uint32_t ilv)
 // NT = 2 (forward passes only): every iteration takes the tiles tl and
 // tl + tstep, which needs tile_end - tile0 to be a multiple of 2 tstep; the
 // op stream is then decoded once for two tiles.
-template <int MODE, bool GEN, bool FULL, int NT, bool START = false>
-__device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__restrict__ phases,
-                                         const DevOp *__restrict__ ops,
-                                         const DevVBond *__restrict__ vb,
-                                         const double *__restrict__ theta,
-                                         const DevModel *__restrict__ M, double2 *__restrict__ v0,
-                                         double2 *__restrict__ v1, char *smem, uint64_t tile0,
+// Vector element access through a possibly address-space-qualified type
+// (member by member: the vector type's own copy operations take generic
+// references only).
+template <typename Vec>
+__device__ __forceinline__ double2 vload(const Vec *p)
+{
+    return make_double2(p->x, p->y);
+}
+template <typename Vec>
+__device__ __forceinline__ void vstore(Vec *p, double2 v)
+{
+    p->x = v.x;
+    p->y = v.y;
+}
+
+// Vec and the table types: address-space qualified where the caller knows
+// more than the pointer types say (see k_batch_pass).
+template <int MODE, bool GEN, bool FULL, int NT, bool START = false, typename Vec = double2,
+          typename PhT = DevPhase, typename OpT = DevOp, typename VbT = DevVBond,
+          typename ThT = double, typename MT = DevModel>
+__device__ __forceinline__ void run_pass(const DevPass &P, const PhT *__restrict__ phases,
+                                         const OpT *__restrict__ ops,
+                                         const VbT *__restrict__ vb,
+                                         const ThT *__restrict__ theta,
+                                         const MT *__restrict__ M, Vec *__restrict__ v0,
+                                         Vec *__restrict__ v1, char *smem, uint64_t tile0,
                                          uint64_t tstep, uint64_t tile_end, uint32_t ilv,
                                          const Sink &sink)
 {
@@ -431,7 +454,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
     const int R = (int)sp.rows;            // accumulators per reduction row
     const bool quad = !single && T >= 4;   // rows hold sums over four lanes
 
-    const DevPhase *ph = phases + P.phase_begin;
+    const PhT *ph = phases + P.phase_begin;
     // ---- per-workgroup set-up: lane and wave parts of every phase's
     // tile-local index, as global bits and as LDS slot byte offsets
     const double sign = (MODE == M_REV) ? -1.0 : 1.0;
@@ -446,7 +469,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
         }
         if constexpr (MODE == M_FWD || MODE == M_REV) {
             for (int o = tid; o < P.n_ops; o += T) {
-                const DevOp &op = ops[P.op_begin + o];
+                const OpT &op = ops[P.op_begin + o];
                 if (op.kind == OP_HOP) {
                     double s, c;
                     sincos(theta[op.param] * op.t, &s, &c);
@@ -455,7 +478,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
             }
             if constexpr (!GEN) {
                 for (int o = 0; o < P.n_ops; ++o) {
-                    const DevOp &op = ops[P.op_begin + o];
+                    const OpT &op = ops[P.op_begin + o];
                     if (op.kind != OP_DIAG)
                         continue;
                     for (int m = tid; m < kDiagTab; m += T) {
@@ -475,7 +498,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
         if constexpr (GEN) {
             // eps sum of each diag op over its qubits, per index nibble
             for (int o = 0; o < P.n_ops; ++o) {
-                const DevOp &op = ops[P.op_begin + o];
+                const OpT &op = ops[P.op_begin + o];
                 if (op.kind != OP_DIAG)
                     continue;
                 for (int t = tid; t < 128; t += T) {
@@ -539,10 +562,10 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                 }
                 if (FULL || (act && ((valid >> j) & 1u))) {
                     const uint64_t g = ga | vec_offset(L0.goff(j), ilv);
-                    dst[t * NV][j] = v0[g];
+                    dst[t * NV][j] = vload(v0 + g);
                     if constexpr (NV == 2) {
                         if (!ham_first)
-                            dst[1][j] = v1[g];
+                            dst[1][j] = vload(v1 + g);
                         else if constexpr (FULL)
                             dst[1][j] = make_double2(0.0, 0.0);
                     }
@@ -584,7 +607,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
         for (int t = 0; t < NT; ++t)
             gthr[t] = bases[t] | tp.x;
         for (int q = 0; q < P.n_phases; ++q) {
-            const DevPhase &phq = ph[q];
+            const PhT &phq = ph[q];
             if (q > 0) {
                 const uint2 tn = thread_part(q);
                 const RegLayout Ln = reg_layout(phq);
@@ -597,7 +620,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                     gthr[t] = bases[t] | tp.x;
             }
             for (int o = phq.op_begin; o < phq.op_end; ++o) {
-                const DevOp &op = ops[P.op_begin + o];
+                const OpT &op = ops[P.op_begin + o];
                 double racc = 0.0;   // this op's reduction (thread part)
                 if (op.kind == OP_DIAG) {
                     double th_op = 0.0;
@@ -699,9 +722,9 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const DevPhase *__res
                     if (FULL || (act && ((valid >> j) & 1u))) {
                         const uint64_t g = ga | vec_offset(L.goff(j), ilv);
                         if constexpr (MODE == M_FWD || MODE == M_REV)
-                            v0[g] = v[t * NV][j];
+                            vstore(v0 + g, v[t * NV][j]);
                         if constexpr (NV == 2)
-                            v1[g] = v[1][j];
+                            vstore(v1 + g, v[1][j]);
                         if (MODE == M_HAM && ham_last)
                             eacc += re_conj_mul(v[0][j], v[1][j]);
                     }
@@ -773,6 +796,18 @@ __global__ void k_batch_init(const DevInstance *__restrict__ inst)
 // FULL: every item's tiles fill all registers of exactly the launch's
 // threads (the guard-free path; a launch of its own keeps the two paths'
 // registers apart).
+// An instance's pointers come from memory, so the compiler cannot see where
+// they point: every access would be a flat one (vector loads for the
+// wave-uniform op fields, completion counted together with LDS).  The
+// vectors are global memory, the tables read-only for the launch (scalar
+// loads where uniform).
+typedef __attribute__((address_space(1))) double2 global_double2;
+typedef const __attribute__((address_space(4))) DevPhase const_phase;
+typedef const __attribute__((address_space(4))) DevOp const_op;
+typedef const __attribute__((address_space(4))) DevVBond const_vbond;
+typedef const __attribute__((address_space(4))) double const_double;
+typedef const __attribute__((address_space(4))) DevModel const_model;
+
 template <int MODE, bool GEN, bool FULL>
 __global__ void __launch_bounds__(512)
 k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ passes,
@@ -783,8 +818,10 @@ k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ p
     const DevInstance I = inst[w.inst];
     const DevPass P = passes[w.pass];
     const Sink sink{partial + w.part, w.stride};
-    run_pass<MODE, GEN, FULL, 1>(P, I.phases, I.ops, I.vb, I.theta, I.model, (double2 *)I.psi,
-                                 (double2 *)I.lam, smem, w.tile0, 1, w.tile1, 32u, sink);
+    run_pass<MODE, GEN, FULL, 1, false, global_double2>(
+        P, (const_phase *)I.phases, (const_op *)I.ops, (const_vbond *)I.vb,
+        (const_double *)I.theta, (const_model *)I.model, (global_double2 *)I.psi,
+        (global_double2 *)I.lam, smem, w.tile0, 1, w.tile1, 32u, sink);
 }
 #define HV_BATCH(MODE, GEN, FULL)                                                               \
     template __global__ void k_batch_pass<MODE, GEN, FULL>(const DevInstance *, const DevPass *,\
