@@ -194,13 +194,15 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
 
 /* Batched energy and gradient of many independent instances (different
  * lattices, sizes, U, disorder, V and layer counts; each its own parameters)
- * with no host work per call: a fixed sequence of launches on `stream` -- the
- * start states of all instances, then, for each position j of the forward, H
- * and reverse schedules, launches that run pass j of every instance that has
- * one (two: passes whose tiles fill the workgroup's registers exactly, and
- * the others; a large instance's tiles spread over many workgroups), then one
- * reduction of the partial sums into E and the gradients, in a fixed order
- * (results are reproducible run to run).
+ * with no host work per call: a fixed sequence of launches on `stream` --
+ * for each position j of the forward, H and reverse schedules, launches that
+ * run pass j of every instance that has one (two: passes whose tiles fill the
+ * workgroup's registers exactly, and the others; a large instance's tiles
+ * spread over many workgroups; the first forward passes build the start
+ * states themselves), then one reduction of the partial sums into E and the
+ * gradients, in a fixed order (results are reproducible run to run).  psi
+ * and lambda in the workspace are scratch: an instance's last reverse pass
+ * does not store them.
  *   hs[i]           instance handles (n >= 1)
  *   theta_dev       all parameters, instance i's n_layers[i]*params_per_layer
  *                   values starting at theta_dev + theta_off[i] (device)

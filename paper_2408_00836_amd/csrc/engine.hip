@@ -23,8 +23,7 @@ template <int MODE, bool GEN, bool FULL, int NT, bool START = false>
 __global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,
                        const DevModel *, double2 *, double2 *, double *, int, uint32_t);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t, uint32_t);
-__global__ void k_batch_init(const DevInstance *);
-template <int MODE, bool GEN, bool FULL>
+template <int MODE, bool GEN, bool FULL, bool START>
 __global__ void k_batch_pass(const DevInstance *, const DevPass *, const DevWork *, double *);
 __global__ void k_reduce_seg(const double *, const int32_t *, const int64_t *, const int32_t *,
                              const double *, const int64_t *, int, double *, double *);
@@ -768,6 +767,7 @@ constexpr int kBatchItems = 64;
 struct BatchLaunch {
     int mode;               // M_FWD, M_HAM or M_REV
     bool full;              // every item's tiles fill all registers of exactly `threads`
+    bool start;             // first forward position: the passes build |b0> themselves
     int item0, n_items;     // work items [item0, item0 + n_items)
     int threads, smem;
 };
@@ -829,6 +829,10 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
         pbase[i] = L.passes.size();
         for (const PassList *pl : {&progs[i]->fwd, &progs[i]->ham, &progs[i]->rev})
             L.passes.insert(L.passes.end(), pl->pass.begin(), pl->pass.end());
+        // an instance's last reverse pass is needed for its reductions only;
+        // the next evaluation starts from the start states again
+        if (!progs[i]->rev.pass.empty())
+            L.passes.back().flags |= PF_NO_STORE;
     }
     const int modes[3] = {M_FWD, M_HAM, M_REV};
     for (int ph = 0; ph < 3; ++ph) {
@@ -855,6 +859,7 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
                 BatchLaunch bl;
                 bl.mode = modes[ph];
                 bl.full = full != 0;
+                bl.start = ph == 0 && j == 0;
                 bl.item0 = (int)L.work.size();
                 bl.threads = 64;
                 std::vector<const DevPass *> used;
@@ -946,7 +951,7 @@ struct BatchProgram {
     int32_t *d_seg_ptr = nullptr, *d_seg_cnt = nullptr;
     int64_t *d_seg_off = nullptr, *d_out_idx = nullptr;
     double *d_scale = nullptr;
-    int n = 0, init_y = 1;
+    int n = 0;
     ~BatchProgram()
     {
         (void)hipFree(d_inst);
@@ -973,7 +978,6 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
     // the instances' device programs (cached per handle, device and layer count)
     std::vector<const Program *> progs(n);
     std::vector<DevInstance> insts(n);
-    uint64_t max_dim = 1;
     for (int i = 0; i < n; ++i) {
         Program *pr;
         DeviceState *ds;
@@ -984,14 +988,11 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
         DevInstance &I = insts[i];
         std::memset(&I, 0, sizeof(I));
         I.general = pr->general ? 1 : 0;
-        I.dim = (uint64_t)1 << hs[i]->m.nq;
-        I.neel = hs[i]->m.neel;
         I.phases = pr->d_phases;
         I.ops = pr->d_ops;
         I.vb = pr->d_vb;
         I.model = ds->d_model;
         I.theta = theta + toff[i];
-        max_dim = std::max(max_dim, I.dim);
     }
     hubbard_status st = batch_layout(hs, n, toff, progs, bp.L);
     if (st != HUBBARD_OK)
@@ -1000,14 +1001,15 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
         insts[i].psi = ws + bp.L.voff[i];
         insts[i].lam = ws + bp.L.voff[i] + align256(vec_bytes(hs[i]));
     }
-    bp.init_y = (int)std::min<uint64_t>(64, (max_dim + 255) / 256);
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
         const int lim = max_smem_per_block();
         const void *fns[] = {
 #define HV_BATCH_FNS(GEN, FULL)                                                                 \
-    (const void *)k_batch_pass<M_FWD, GEN, FULL>, (const void *)k_batch_pass<M_HAM, GEN, FULL>, \
-        (const void *)k_batch_pass<M_REV, GEN, FULL>
+    (const void *)k_batch_pass<M_FWD, GEN, FULL, false>,                                        \
+        (const void *)k_batch_pass<M_FWD, GEN, FULL, true>,                                     \
+        (const void *)k_batch_pass<M_HAM, GEN, FULL, false>,                                    \
+        (const void *)k_batch_pass<M_REV, GEN, FULL, false>
             HV_BATCH_FNS(false, false), HV_BATCH_FNS(false, true), HV_BATCH_FNS(true, false),
             HV_BATCH_FNS(true, true)};
 #undef HV_BATCH_FNS
@@ -1351,20 +1353,21 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
     if (ws_bytes < L.ws_bytes)
         return fail(HUBBARD_ERR_SIZE, "workspace too small for energy_grad_batch");
     double *partial = (double *)((char *)ws_dev + L.partial_at);
-    hipLaunchKernelGGL(k_batch_init, dim3(n, bp->init_y), dim3(256), 0, s, bp->d_inst);
     for (const BatchLaunch &bl : L.launches) {
         const DevWork *w = bp->d_work + bl.item0;
-#define HV_BATCH_LAUNCH(MODE, GEN, FULL)                                                        \
-    hipLaunchKernelGGL((k_batch_pass<MODE, GEN, FULL>), dim3(bl.n_items), dim3(bl.threads),    \
-                       bl.smem, s, bp->d_inst, bp->d_passes, w, partial)
+#define HV_BATCH_LAUNCH(MODE, GEN, FULL, START)                                                 \
+    hipLaunchKernelGGL((k_batch_pass<MODE, GEN, FULL, START>), dim3(bl.n_items),               \
+                       dim3(bl.threads), bl.smem, s, bp->d_inst, bp->d_passes, w, partial)
 #define HV_BATCH_MODE(GEN, FULL)                                                                \
     do {                                                                                        \
-        if (bl.mode == M_FWD)                                                                   \
-            HV_BATCH_LAUNCH(M_FWD, GEN, FULL);                                                  \
+        if (bl.mode == M_FWD && bl.start)                                                       \
+            HV_BATCH_LAUNCH(M_FWD, GEN, FULL, true);                                            \
+        else if (bl.mode == M_FWD)                                                              \
+            HV_BATCH_LAUNCH(M_FWD, GEN, FULL, false);                                           \
         else if (bl.mode == M_HAM)                                                              \
-            HV_BATCH_LAUNCH(M_HAM, GEN, FULL);                                                  \
+            HV_BATCH_LAUNCH(M_HAM, GEN, FULL, false);                                           \
         else                                                                                    \
-            HV_BATCH_LAUNCH(M_REV, GEN, FULL);                                                  \
+            HV_BATCH_LAUNCH(M_REV, GEN, FULL, false);                                           \
     } while (0)
         if (L.general) {
             if (bl.full)

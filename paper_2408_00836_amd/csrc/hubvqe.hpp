@@ -32,7 +32,8 @@ enum OpKind : int32_t {
 enum PassFlags : int32_t {
     PF_HAM_FIRST = 1,   // H pass: phi <- D psi + terms (else phi += terms)
     PF_HAM_LAST = 2,    // H pass: also reduce Re <psi|phi> into row 0
-    // set per launch, not planned:
+    // never planned; set on a launch's copy of a pass (single state) or in a
+    // batch's own pass array:
     PF_FROM_START = 4,  // forward pass: the input is the start state |b0>, not read
     PF_NO_STORE = 8,    // reverse pass: the vectors are not needed afterwards
 };
@@ -123,7 +124,6 @@ struct DevPass {
 struct DevInstance {
     int32_t general;        // diagonal has eps or V terms
     int32_t pad;
-    uint64_t dim, neel;
     const struct DevPhase *phases;
     const struct DevOp *ops;
     const struct DevVBond *vb;

@@ -781,15 +781,6 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
 // each instance's tiles split into work items over many workgroups, and a
 // final reduction of the partial rows.  No workgroup waits for another.
 
-__global__ void k_batch_init(const DevInstance *__restrict__ inst)
-{
-    const DevInstance I = inst[blockIdx.x];
-    double2 *psi = (double2 *)I.psi;
-    const uint64_t stride = (uint64_t)gridDim.y * blockDim.x;
-    for (uint64_t b = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; b < I.dim; b += stride)
-        psi[b] = make_double2(b == I.neel ? 1.0 : 0.0, 0.0);
-}
-
 // GEN: the launch runs the general-diagonal path for every instance (a
 // batch with any eps or V term; the path also holds for U-only instances,
 // whose eps tables are zero and V classes empty), else the U-only path.
@@ -808,7 +799,9 @@ typedef const __attribute__((address_space(4))) DevVBond const_vbond;
 typedef const __attribute__((address_space(4))) double const_double;
 typedef const __attribute__((address_space(4))) DevModel const_model;
 
-template <int MODE, bool GEN, bool FULL>
+// START (forward, first schedule position): every instance's first pass
+// builds its start state |b0> in registers; nothing is read.
+template <int MODE, bool GEN, bool FULL, bool START>
 __global__ void __launch_bounds__(512)
 k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ passes,
              const DevWork *__restrict__ work, double *__restrict__ partial)
@@ -818,18 +811,19 @@ k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ p
     const DevInstance I = inst[w.inst];
     const DevPass P = passes[w.pass];
     const Sink sink{partial + w.part, w.stride};
-    run_pass<MODE, GEN, FULL, 1, false, global_double2>(
+    run_pass<MODE, GEN, FULL, 1, START, global_double2>(
         P, (const_phase *)I.phases, (const_op *)I.ops, (const_vbond *)I.vb,
         (const_double *)I.theta, (const_model *)I.model, (global_double2 *)I.psi,
         (global_double2 *)I.lam, smem, w.tile0, 1, w.tile1, 32u, sink);
 }
-#define HV_BATCH(MODE, GEN, FULL)                                                               \
-    template __global__ void k_batch_pass<MODE, GEN, FULL>(const DevInstance *, const DevPass *,\
-                                                           const DevWork *, double *);
+#define HV_BATCH(MODE, GEN, FULL, START)                                                        \
+    template __global__ void k_batch_pass<MODE, GEN, FULL, START>(                              \
+        const DevInstance *, const DevPass *, const DevWork *, double *);
 #define HV_BATCH_ALL(GEN, FULL)                                                                 \
-    HV_BATCH(M_FWD, GEN, FULL)                                                                  \
-    HV_BATCH(M_HAM, GEN, FULL)                                                                  \
-    HV_BATCH(M_REV, GEN, FULL)
+    HV_BATCH(M_FWD, GEN, FULL, false)                                                           \
+    HV_BATCH(M_FWD, GEN, FULL, true)                                                            \
+    HV_BATCH(M_HAM, GEN, FULL, false)                                                           \
+    HV_BATCH(M_REV, GEN, FULL, false)
 HV_BATCH_ALL(false, false)
 HV_BATCH_ALL(false, true)
 HV_BATCH_ALL(true, false)
