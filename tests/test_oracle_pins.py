@@ -345,6 +345,48 @@ def test_variational_bound_config1(oracle_lib):
         assert oc.energy(m, rng.uniform(-np.pi, np.pi, 6), 2) >= E0 - 1e-12
 
 
+def _sector_csr(m, nu, nd):
+    """(nu, nd) block of H assembled from the C oracle's rows (scipy CSR)."""
+    import scipy.sparse as sp
+    idx = [b for b in range(1 << m.nqubits) if sector_of(m, b) == (nu, nd)]
+    pos = {b: i for i, b in enumerate(idx)}
+    r, c, v = [], [], []
+    for i, b in enumerate(idx):
+        cols, coefs = oc.ham_row(m, b)
+        for col, x in zip(cols, coefs):
+            r.append(i)
+            c.append(pos[int(col)])   # H conserves (N_up, N_dn): no column leaves the sector
+            v.append(x)
+    return sp.csr_matrix((v, (r, c)), shape=(len(idx), len(idx)))
+
+
+@pytest.mark.parametrize("U", [1.0, 4.0, 8.0])
+def test_chain8_sector_energy_two_mechanisms(oracle_lib, U):
+    """Stored 8-site chain ground energies (Kronecker-product H, Lanczos)
+    against H rebuilt from the C oracle's Jordan-Wigner rows."""
+    import scipy.sparse.linalg as sla
+    with open(os.path.join(GOLDEN, "sector_ground_energies.json")) as f:
+        E0 = json.load(f)[f"config2_chain8_U{U:g}"]["E0"]
+    m = make_model(1, 8, U=U)
+    H = _sector_csr(m, 4, 4)
+    assert abs(H - H.T).max() < 1e-14
+    w = sla.eigsh(H, k=1, which="SA", tol=1e-13)[0]
+    assert abs(float(w[0]) - E0) < 1e-9
+
+
+@pytest.mark.parametrize("U", [1.0, 4.0, 8.0])
+def test_variational_bound_config2(oracle_lib, U):
+    """8 layers of [U, even, odd] on the 8-site chain never go below the
+    (4, 4) sector ground energy, at random and at small angles."""
+    with open(os.path.join(GOLDEN, "sector_ground_energies.json")) as f:
+        E0 = json.load(f)[f"config2_chain8_U{U:g}"]["E0"]
+    m = make_model(1, 8, U=U)
+    rng = np.random.default_rng(int(U) + 40)
+    for width in (np.pi, 0.3):
+        for _ in range(3):
+            assert oc.energy(m, rng.uniform(-width, width, 24), 8) >= E0 - 1e-12
+
+
 def test_golden_values(oracle_lib):
     """Stored values: closed forms (cited) and sector ground energies written by
     tests/golden/make_golden.py from the oracle's H (sparse Lanczos)."""
