@@ -47,6 +47,11 @@
  *     thread).  No C++ exception crosses this boundary.
  *   - A handle may be used from one host thread at a time; calls that share
  *     a workspace on different streams race.
+ *   - Once a call of energy (or of energy_grad) with a given handle, device
+ *     and layer count has uploaded its plan, later such calls only launch
+ *     kernels (no allocation, memset or synchronisation) and may be captured
+ *     into a HIP graph and replayed with new theta values in place; the
+ *     batch call states its own rule.
  */
 #ifndef HUBBARD_H
 #define HUBBARD_H
