@@ -898,6 +898,19 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
                     used.push_back(&P);
                 }
                 bl.n_items = (int)L.work.size() - bl.item0;
+                // longest items first: an instance that fits one tile runs its
+                // whole circuit in one workgroup, which must not start last
+                // (the order only maps workgroups to items; every item writes
+                // its own partial slots)
+                std::stable_sort(L.work.begin() + bl.item0, L.work.end(),
+                                 [&](const DevWork &a, const DevWork &b) {
+                                     auto cost = [&](const DevWork &w) {
+                                         const DevPass &P = L.passes[w.pass];
+                                         return (double)(P.n_ops + 1) * (w.tile1 - w.tile0) *
+                                                (double)(1u << P.k);
+                                     };
+                                     return cost(a) > cost(b);
+                                 });
                 bl.smem = 0;
                 for (const DevPass *P : used)
                     bl.smem = std::max(bl.smem, (int)smem_plan(P->k, P->n_ops, P->n_diag, P->n_red,
