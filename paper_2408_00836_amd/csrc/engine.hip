@@ -768,6 +768,7 @@ struct BatchLaunch {
     int mode;               // M_FWD, M_HAM or M_REV
     bool full;              // every item's tiles fill all registers of exactly `threads`
     bool start;             // first forward position: the passes build |b0> themselves
+    bool side;              // instances with one pass per schedule, on the side stream
     int item0, n_items;     // work items [item0, item0 + n_items)
     int threads, smem;
 };
@@ -855,11 +856,16 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
                 inst.push_back(i);
                 widest = std::max(widest, 1 << pl.pass[j].tbits);
             }
+            // an instance with one pass per schedule (its whole state in one
+            // tile) runs its circuit in one workgroup per launch: its three
+            // launches go to a side stream, alongside the others' sequence
+            for (int lane = 0; lane < 2; ++lane)
             for (int full = 1; full >= 0; --full) {
                 BatchLaunch bl;
                 bl.mode = modes[ph];
                 bl.full = full != 0;
                 bl.start = ph == 0 && j == 0;
+                bl.side = lane == 1;
                 bl.item0 = (int)L.work.size();
                 bl.threads = 64;
                 std::vector<const DevPass *> used;
@@ -868,7 +874,9 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
                     const PassList &pl = ph == 0 ? pr.fwd : ph == 1 ? pr.ham : pr.rev;
                     const DevPass &P = pl.pass[j];
                     const bool fills = P.k >= kRegBits && (1 << P.tbits) == widest;
-                    if (fills != bl.full)
+                    const bool single = pr.fwd.pass.size() == 1 && pr.ham.pass.size() == 1 &&
+                                        pr.rev.pass.size() == 1;
+                    if (fills != bl.full || single != bl.side)
                         continue;
                     const size_t off = (ph == 0 ? 0 : ph == 1 ? pr.fwd.pass.size()
                                                                : pr.fwd.pass.size() + pr.ham.pass.size());
@@ -965,8 +973,18 @@ struct BatchProgram {
     int64_t *d_seg_off = nullptr, *d_out_idx = nullptr;
     double *d_scale = nullptr;
     int n = 0;
+    // side stream of the single-pass instances (default priority), forked
+    // from and joined to the caller's stream by two events each call
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     ~BatchProgram()
     {
+        if (fork)
+            (void)hipEventDestroy(fork);
+        if (join)
+            (void)hipEventDestroy(join);
+        if (side)
+            (void)hipStreamDestroy(side);
         (void)hipFree(d_inst);
         (void)hipFree(d_passes);
         (void)hipFree(d_work);
@@ -1010,6 +1028,15 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
     hubbard_status st = batch_layout(hs, n, toff, progs, bp.L);
     if (st != HUBBARD_OK)
         return st;
+    bool any_side = false;
+    for (const BatchLaunch &bl : bp.L.launches)
+        any_side = any_side || bl.side;
+    if (any_side) {
+        if (hipStreamCreateWithFlags(&bp.side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&bp.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&bp.join, hipEventDisableTiming) != hipSuccess)
+            return fail(HUBBARD_ERR_DEVICE, "creating the batch side stream");
+    }
     for (int i = 0; i < n; ++i) {
         insts[i].psi = ws + bp.L.voff[i];
         insts[i].lam = ws + bp.L.voff[i] + align256(vec_bytes(hs[i]));
@@ -1366,11 +1393,17 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
     if (ws_bytes < L.ws_bytes)
         return fail(HUBBARD_ERR_SIZE, "workspace too small for energy_grad_batch");
     double *partial = (double *)((char *)ws_dev + L.partial_at);
+    if (bp->side) {
+        if (hipEventRecord(bp->fork, s) != hipSuccess ||
+            hipStreamWaitEvent(bp->side, bp->fork, 0) != hipSuccess)
+            return fail(HUBBARD_ERR_DEVICE, "forking the batch side stream");
+    }
     for (const BatchLaunch &bl : L.launches) {
         const DevWork *w = bp->d_work + bl.item0;
+        hipStream_t ls = bl.side ? bp->side : s;
 #define HV_BATCH_LAUNCH(MODE, GEN, FULL, START)                                                 \
     hipLaunchKernelGGL((k_batch_pass<MODE, GEN, FULL, START>), dim3(bl.n_items),               \
-                       dim3(bl.threads), bl.smem, s, bp->d_inst, bp->d_passes, w, partial)
+                       dim3(bl.threads), bl.smem, ls, bp->d_inst, bp->d_passes, w, partial)
 #define HV_BATCH_MODE(GEN, FULL)                                                                \
     do {                                                                                        \
         if (bl.mode == M_FWD && bl.start)                                                       \
@@ -1395,6 +1428,11 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
         }
 #undef HV_BATCH_MODE
 #undef HV_BATCH_LAUNCH
+    }
+    if (bp->side) {
+        if (hipEventRecord(bp->join, bp->side) != hipSuccess ||
+            hipStreamWaitEvent(s, bp->join, 0) != hipSuccess)
+            return fail(HUBBARD_ERR_DEVICE, "joining the batch side stream");
     }
     hipLaunchKernelGGL(k_reduce_seg, dim3((unsigned)L.scale.size()), dim3(256), 0, s, partial,
                        bp->d_seg_ptr, bp->d_seg_off, bp->d_seg_cnt, bp->d_scale, bp->d_out_idx, n,
