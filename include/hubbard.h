@@ -206,11 +206,14 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
  * spread over many workgroups; the first forward passes build the start
  * states themselves), then one reduction of the partial sums into E and the
  * gradients, in a fixed order (results are reproducible run to run).  The
- * passes of instances that fit one tile (one pass per schedule) run on a
- * side stream of the library's own, forked from `stream` by an event and
- * joined back before the reduction; under graph capture both branches are
- * recorded.  psi and lambda in the workspace are scratch: an instance's
- * last reverse pass does not store them.
+ * instances are split into lanes by schedule length (those that fit one
+ * tile, and groups of shorter forward schedules); each lane's launches run
+ * on a stream of the library's own, forked from `stream` by an event and
+ * joined back before the reduction, so that a lane that has finished its
+ * forward runs its H and reverse passes while longer ones still run
+ * theirs; under graph capture every branch is recorded.  psi and lambda in
+ * the workspace are scratch: an instance's last reverse pass does not
+ * store them.
  *   hs[i]           instance handles (n >= 1)
  *   theta_dev       all parameters, instance i's n_layers[i]*params_per_layer
  *                   values starting at theta_dev + theta_off[i] (device)

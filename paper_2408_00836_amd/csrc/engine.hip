@@ -763,12 +763,17 @@ void mark(hubbard_model *h, int i, hipStream_t s)
 // Work items per instance pass: enough to spread a large instance over many
 // workgroups, few enough that each item streams several tiles.
 constexpr int kBatchItems = 64;
+// Streams of a batched evaluation: the caller's (lane 0, the longest
+// forward schedules) and the batch program's own: lane 1 for the instances
+// with one pass per schedule, lanes 2.. for shorter forward schedules.
+constexpr int kMultiLanes = 3;   // 256 uneven instances: 2, 3, 4 lanes took 13.5, 13.1, 13.2 ms
+constexpr int kBatchLanes = kMultiLanes + 1;
 
 struct BatchLaunch {
     int mode;               // M_FWD, M_HAM or M_REV
     bool full;              // every item's tiles fill all registers of exactly `threads`
     bool start;             // first forward position: the passes build |b0> themselves
-    bool side;              // instances with one pass per schedule, on the side stream
+    int lane;               // stream of the launch (kBatchLanes, below)
     int item0, n_items;     // work items [item0, item0 + n_items)
     int threads, smem;
 };
@@ -835,6 +840,25 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
         if (!progs[i]->rev.pass.empty())
             L.passes.back().flags |= PF_NO_STORE;
     }
+    // lanes: instances grouped by forward length, each group's launch
+    // sequence on its own stream, so that a group that has finished its
+    // forward runs its H and reverse while longer ones still run theirs;
+    // lane 1 holds the instances with one pass per schedule (whole state in
+    // one tile: one workgroup runs the circuit)
+    size_t fmax = 1;
+    for (int i = 0; i < n; ++i)
+        fmax = std::max(fmax, progs[i]->fwd.pass.size());
+    std::vector<int> lane_of(n);
+    for (int i = 0; i < n; ++i) {
+        const Program &pr = *progs[i];
+        const bool single = pr.fwd.pass.size() == 1 && pr.ham.pass.size() == 1 &&
+                            pr.rev.pass.size() == 1;
+        // multi-pass instances: group q = 0 (longest) .. kMultiLanes-1 by the
+        // share of the longest forward schedule still ahead of them
+        const int q = std::min<int>(kMultiLanes - 1,
+                                    (int)(kMultiLanes * (fmax - pr.fwd.pass.size()) / fmax));
+        lane_of[i] = single ? 1 : (q == 0 ? 0 : q + 1);
+    }
     const int modes[3] = {M_FWD, M_HAM, M_REV};
     for (int ph = 0; ph < 3; ++ph) {
         size_t longest = 0;
@@ -856,16 +880,13 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
                 inst.push_back(i);
                 widest = std::max(widest, 1 << pl.pass[j].tbits);
             }
-            // an instance with one pass per schedule (its whole state in one
-            // tile) runs its circuit in one workgroup per launch: its three
-            // launches go to a side stream, alongside the others' sequence
-            for (int lane = 0; lane < 2; ++lane)
+            for (int lane = 0; lane < kBatchLanes; ++lane)
             for (int full = 1; full >= 0; --full) {
                 BatchLaunch bl;
                 bl.mode = modes[ph];
                 bl.full = full != 0;
                 bl.start = ph == 0 && j == 0;
-                bl.side = lane == 1;
+                bl.lane = lane;
                 bl.item0 = (int)L.work.size();
                 bl.threads = 64;
                 std::vector<const DevPass *> used;
@@ -874,9 +895,7 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
                     const PassList &pl = ph == 0 ? pr.fwd : ph == 1 ? pr.ham : pr.rev;
                     const DevPass &P = pl.pass[j];
                     const bool fills = P.k >= kRegBits && (1 << P.tbits) == widest;
-                    const bool single = pr.fwd.pass.size() == 1 && pr.ham.pass.size() == 1 &&
-                                        pr.rev.pass.size() == 1;
-                    if (fills != bl.full || single != bl.side)
+                    if (fills != bl.full || lane_of[i] != bl.lane)
                         continue;
                     const size_t off = (ph == 0 ? 0 : ph == 1 ? pr.fwd.pass.size()
                                                                : pr.fwd.pass.size() + pr.ham.pass.size());
@@ -973,18 +992,20 @@ struct BatchProgram {
     int64_t *d_seg_off = nullptr, *d_out_idx = nullptr;
     double *d_scale = nullptr;
     int n = 0;
-    // side stream of the single-pass instances (default priority), forked
-    // from and joined to the caller's stream by two events each call
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    // streams of lanes 1.. (default priority), forked from the caller's
+    // stream by one event and joined back by one event each per call
+    hipStream_t lane_s[kBatchLanes] = {};
+    hipEvent_t fork = nullptr, join[kBatchLanes] = {};
     ~BatchProgram()
     {
         if (fork)
             (void)hipEventDestroy(fork);
-        if (join)
-            (void)hipEventDestroy(join);
-        if (side)
-            (void)hipStreamDestroy(side);
+        for (int l = 1; l < kBatchLanes; ++l) {
+            if (join[l])
+                (void)hipEventDestroy(join[l]);
+            if (lane_s[l])
+                (void)hipStreamDestroy(lane_s[l]);
+        }
         (void)hipFree(d_inst);
         (void)hipFree(d_passes);
         (void)hipFree(d_work);
@@ -1028,14 +1049,16 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
     hubbard_status st = batch_layout(hs, n, toff, progs, bp.L);
     if (st != HUBBARD_OK)
         return st;
-    bool any_side = false;
+    bool used[kBatchLanes] = {};
     for (const BatchLaunch &bl : bp.L.launches)
-        any_side = any_side || bl.side;
-    if (any_side) {
-        if (hipStreamCreateWithFlags(&bp.side, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&bp.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&bp.join, hipEventDisableTiming) != hipSuccess)
-            return fail(HUBBARD_ERR_DEVICE, "creating the batch side stream");
+        used[bl.lane] = true;
+    for (int l = 1; l < kBatchLanes; ++l) {
+        if (!used[l])
+            continue;
+        if ((!bp.fork && hipEventCreateWithFlags(&bp.fork, hipEventDisableTiming) != hipSuccess) ||
+            hipStreamCreateWithFlags(&bp.lane_s[l], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&bp.join[l], hipEventDisableTiming) != hipSuccess)
+            return fail(HUBBARD_ERR_DEVICE, "creating the batch lane streams");
     }
     for (int i = 0; i < n; ++i) {
         insts[i].psi = ws + bp.L.voff[i];
@@ -1393,14 +1416,14 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
     if (ws_bytes < L.ws_bytes)
         return fail(HUBBARD_ERR_SIZE, "workspace too small for energy_grad_batch");
     double *partial = (double *)((char *)ws_dev + L.partial_at);
-    if (bp->side) {
-        if (hipEventRecord(bp->fork, s) != hipSuccess ||
-            hipStreamWaitEvent(bp->side, bp->fork, 0) != hipSuccess)
-            return fail(HUBBARD_ERR_DEVICE, "forking the batch side stream");
-    }
+    if (bp->fork && hipEventRecord(bp->fork, s) != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, "forking the batch lane streams");
+    for (int l = 1; l < kBatchLanes; ++l)
+        if (bp->lane_s[l] && hipStreamWaitEvent(bp->lane_s[l], bp->fork, 0) != hipSuccess)
+            return fail(HUBBARD_ERR_DEVICE, "forking the batch lane streams");
     for (const BatchLaunch &bl : L.launches) {
         const DevWork *w = bp->d_work + bl.item0;
-        hipStream_t ls = bl.side ? bp->side : s;
+        hipStream_t ls = bl.lane == 0 ? s : bp->lane_s[bl.lane];
 #define HV_BATCH_LAUNCH(MODE, GEN, FULL, START)                                                 \
     hipLaunchKernelGGL((k_batch_pass<MODE, GEN, FULL, START>), dim3(bl.n_items),               \
                        dim3(bl.threads), bl.smem, ls, bp->d_inst, bp->d_passes, w, partial)
@@ -1429,11 +1452,10 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
 #undef HV_BATCH_MODE
 #undef HV_BATCH_LAUNCH
     }
-    if (bp->side) {
-        if (hipEventRecord(bp->join, bp->side) != hipSuccess ||
-            hipStreamWaitEvent(s, bp->join, 0) != hipSuccess)
-            return fail(HUBBARD_ERR_DEVICE, "joining the batch side stream");
-    }
+    for (int l = 1; l < kBatchLanes; ++l)
+        if (bp->lane_s[l] && (hipEventRecord(bp->join[l], bp->lane_s[l]) != hipSuccess ||
+                              hipStreamWaitEvent(s, bp->join[l], 0) != hipSuccess))
+            return fail(HUBBARD_ERR_DEVICE, "joining the batch lane streams");
     hipLaunchKernelGGL(k_reduce_seg, dim3((unsigned)L.scale.size()), dim3(256), 0, s, partial,
                        bp->d_seg_ptr, bp->d_seg_off, bp->d_seg_cnt, bp->d_scale, bp->d_out_idx, n,
                        E_dev, grad_dev);
