@@ -174,8 +174,10 @@ class EnergyGrad(torch.autograd.Function):
 
 class Batch:
     """Many independent instances evaluated (energy + adjoint gradient) by one
-    fixed launch sequence (one launch per schedule position for all instances
-    together, then one reduction).  Parameters of instance i live at
+    fixed launch sequence: the instances in lanes by schedule length, each
+    lane one launch per schedule position on a stream of its own (forked
+    from and joined to the current stream), then one reduction.  Parameters
+    of instance i live at
     theta[offsets[i] : offsets[i] + n_params[i]] of one device vector; the
     gradient uses the same layout.
 
