@@ -1,5 +1,5 @@
-"""Batched persistent launch (256 uneven instances, 8-20 qubits) against the
-oracle and against the single-instance path; graph capture and replay."""
+"""Batched evaluation (256 uneven instances, 8-20 qubits) against the oracle
+and against the single-instance path; graph capture and replay; error paths."""
 import sys
 
 import numpy as np
@@ -8,7 +8,7 @@ import torch
 
 from oracle import core as oc
 from oracle.model import make_model
-from paper_2408_00836_amd import workloads as W
+from paper_2408_00836_amd import abi, workloads as W
 from paper_2408_00836_amd.model import Batch, Hubbard
 
 pytestmark = pytest.mark.gpu
@@ -32,7 +32,7 @@ def batch256(gpu):
 
 def test_batch_matches_oracle(batch256):
     ws, models, b, theta = batch256
-    say("[batch] 256 instances, one persistent launch")
+    say("[batch] 256 instances, one launch sequence")
     E, g = b.energy_grad(theta)
     torch.cuda.synchronize()
     E, g = E.cpu().numpy(), g.cpu().numpy()
@@ -105,3 +105,37 @@ def test_small_batches(gpu):
             o = b.offsets[i]
             assert abs(E[i] - E_ref) <= 1e-12 * max(1, abs(E_ref))
             assert np.max(np.abs(g[o:o + w.n_params] - g_ref)) <= 1e-8
+
+
+def test_batch_error_paths(gpu):
+    """A short workspace is HUBBARD_ERR_SIZE; a first call (which plans the
+    batch and uploads its tables) under graph capture is HUBBARD_ERR_STATE.
+    Neither launches anything."""
+    group = [W.random_instance(2, 3, 2, 5, 91, U=4.0, V=0.5),
+             W.random_instance(2, 4, 3, 5, 92, U=2.0)]
+    models = [Hubbard(w.nx, w.ny, **w.kwargs()) for w in group]
+    b = Batch(models, [w.layers for w in group])
+    hs = [m.handle for m in models]
+    th = torch.tensor(np.concatenate([w.theta for w in group]), dtype=torch.float64,
+                      device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    with pytest.raises(abi.HubbardError) as e:
+        abi.energy_grad_batch(hs, th.data_ptr(), b.offsets, b.layers, b.E.data_ptr(),
+                              b.grad.data_ptr(), b.ws.data_ptr(), b.ws.numel() - 1, s)
+    assert e.value.status == abi.HUBBARD_ERR_SIZE
+    th2 = th.clone()   # other theta pointer: a batch not planned yet
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with pytest.raises(abi.HubbardError) as e:
+        with torch.cuda.graph(graph):
+            abi.energy_grad_batch(hs, th2.data_ptr(), b.offsets, b.layers, b.E.data_ptr(),
+                                  b.grad.data_ptr(), b.ws.data_ptr(), b.ws.numel(),
+                                  torch.cuda.current_stream().cuda_stream)
+    assert e.value.status == abi.HUBBARD_ERR_STATE
+    torch.cuda.synchronize()
+    # the batch still evaluates normally afterwards
+    E, g = b.energy_grad(th)
+    torch.cuda.synchronize()
+    for i, w in enumerate(group):
+        E_ref, _ = oc.energy_grad(make_model(w.nx, w.ny, **w.kwargs()), w.theta, w.layers)
+        assert abs(E[i].item() - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
