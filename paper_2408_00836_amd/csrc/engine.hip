@@ -769,7 +769,10 @@ static_assert((kBatchItems & (kBatchItems - 1)) == 0, "kBatchItems must be a pow
 // Streams of a batched evaluation: the caller's (lane 0, the longest
 // forward schedules) and the batch program's own: lane 1 for the instances
 // with one pass per schedule, lanes 2.. for shorter forward schedules.
-constexpr int kMultiLanes = 3;   // 256 uneven instances: 2, 3, 4 lanes took 13.5, 13.1, 13.2 ms
+// Four streams in all, the hardware queues a process gets by default; with
+// 32 work items, 2, 3, 4, 5 length groups took 13.0, 12.5, 12.8, 13.3 ms
+// (eager; more streams than queues share queues) for 256 uneven instances.
+constexpr int kMultiLanes = 3;
 constexpr int kBatchLanes = kMultiLanes + 1;
 
 struct BatchLaunch {
