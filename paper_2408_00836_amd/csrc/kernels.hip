@@ -775,11 +775,13 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
 }
 
 // ------------------------------------------------------------------ batch --
-// A batched evaluation is a sequence of launches: the start states of all
-// instances, then one launch per pass index of the forward, H and reverse
-// schedules, each running that pass of every instance that has one, with
-// each instance's tiles split into work items over many workgroups, and a
-// final reduction of the partial rows.  No workgroup waits for another.
+// A batched evaluation is a sequence of launches per lane (a group of
+// instances with its own stream): one launch per pass index of the forward,
+// H and reverse schedules, each running that pass of every instance of the
+// lane that has one (the first forward launch builds the start states in
+// registers), with each instance's tiles split into work items over many
+// workgroups; then one reduction of the partial rows.  No workgroup waits
+// for another.
 
 // GEN: the launch runs the general-diagonal path for every instance (a
 // batch with any eps or V term; the path also holds for U-only instances,
