@@ -379,3 +379,331 @@ void orc_set_threads(int t) { omp_set_num_threads(t); }
 int orc_threads(void) { return 1; }
 void orc_set_threads(int t) { (void)t; }
 #endif
+
+/* ------------------------------------ fixed-(N_up, N_dn) sector form ----- */
+
+/* Every hopping term moves one electron between two qubits of the same spin
+ * and D is diagonal, so every gate of Eq. (7) and H itself conserve the
+ * number of spin-up and of spin-down electrons.  A circuit started from the
+ * basis state |b0> therefore stays in the sector of basis states with the
+ * same counts, and every amplitude outside it stays exactly zero.  The
+ * functions below keep only the sector's amplitudes (spin-blocked qubit order
+ * only): at 4x4 half filling C(16,8)^2 = 1.66e8 of the 2^32 amplitudes.
+ *
+ * Sector position i = rd * n_up_patterns + ru, where ru (rd) is the rank of
+ * the spin-up (spin-down) occupation pattern among all patterns with that
+ * many electrons, in increasing numerical order; the full amplitude index is
+ * up[ru] | (dn[rd] << nsites).  The gate and H arithmetic per amplitude pair
+ * is the one of the full-space functions above, term for term. */
+
+typedef struct {
+    int ns;
+    int64_t cu, cd;     /* number of spin-up / spin-down patterns */
+    uint32_t *up, *dn;  /* patterns, increasing */
+    int64_t *rank_up;   /* pattern -> rank, -1 if its popcount differs (2^ns) */
+    int64_t *rank_dn;
+} orc_sector;
+
+static int popcount32(uint32_t x)
+{
+    int c = 0;
+    for (; x; x &= x - 1u)
+        c++;
+    return c;
+}
+
+static void sector_free(orc_sector *S)
+{
+    free(S->up);
+    free(S->dn);
+    free(S->rank_up);
+    free(S->rank_dn);
+    memset(S, 0, sizeof(*S));
+}
+
+/* Patterns of nsites bits with exactly k set, and the inverse map. */
+static int sector_patterns(int ns, int k, uint32_t **list, int64_t **rank, int64_t *count)
+{
+    const uint64_t np = (uint64_t)1 << ns;
+    *rank = malloc(np * sizeof(int64_t));
+    int64_t c = 0;
+    if (!*rank)
+        return -1;
+    for (uint64_t u = 0; u < np; u++)
+        (*rank)[u] = popcount32((uint32_t)u) == k ? c++ : -1;
+    *list = malloc((size_t)(c ? c : 1) * sizeof(uint32_t));
+    if (!*list)
+        return -1;
+    for (uint64_t u = 0; u < np; u++)
+        if ((*rank)[u] >= 0)
+            (*list)[(*rank)[u]] = (uint32_t)u;
+    *count = c;
+    return 0;
+}
+
+/* The sector of basis state b0 (its up and down electron counts). */
+static int sector_make(const orc_model *m, uint64_t b0, orc_sector *S)
+{
+    memset(S, 0, sizeof(*S));
+    if (m->interleaved)
+        return -1;
+    const int ns = m->nsites;
+    const uint32_t smask = (uint32_t)(((uint64_t)1 << ns) - 1u);
+    S->ns = ns;
+    if (sector_patterns(ns, popcount32((uint32_t)b0 & smask), &S->up, &S->rank_up, &S->cu) ||
+        sector_patterns(ns, popcount32((uint32_t)(b0 >> ns) & smask), &S->dn, &S->rank_dn,
+                        &S->cd)) {
+        sector_free(S);
+        return -1;
+    }
+    return 0;
+}
+
+static uint64_t sector_full(const orc_sector *S, int64_t i)
+{
+    return (uint64_t)S->up[i % S->cu] | ((uint64_t)S->dn[i / S->cu] << S->ns);
+}
+
+static int64_t sector_pos(const orc_sector *S, uint64_t b)
+{
+    const uint64_t smask = ((uint64_t)1 << S->ns) - 1u;
+    const int64_t ru = S->rank_up[b & smask], rd = S->rank_dn[(b >> S->ns) & smask];
+    if (ru < 0 || rd < 0 || (b >> (2 * S->ns)) != 0)
+        return -1;
+    return rd * S->cu + ru;
+}
+
+static int64_t sector_dim(const orc_sector *S) { return S->cu * S->cd; }
+
+/* psi <- exp(-i theta coef (a+_p a_q + a+_q a_p)) psi on the sector, p and q
+ * of one spin: the pairs (x, y = x with the electron moved from p to q). */
+static void sec_apply_hop(const orc_sector *S, int spin, int p, int q, double coef, double theta,
+                          cplx *psi)
+{
+    const double c = cos(theta * coef), s = sin(theta * coef);
+    const int ns = S->ns;
+    const uint32_t pm = 1u << (p - ns * spin), qm = 1u << (q - ns * spin);
+    if (spin == 0) {
+        /* pairs inside one row of fixed down pattern */
+#pragma omp parallel for schedule(static)
+        for (int64_t rd = 0; rd < S->cd; rd++) {
+            for (int64_t ru = 0; ru < S->cu; ru++) {
+                const uint32_t u = S->up[ru];
+                if (!(u & pm) || (u & qm))
+                    continue;
+                const int64_t x = rd * S->cu + ru, y = rd * S->cu + S->rank_up[u ^ pm ^ qm];
+                const double sg = jw_sign(sector_full(S, x), p, q);
+                cplx px = psi[x], py = psi[y];
+                psi[x] = c * px - I * (sg * s) * py;
+                psi[y] = -I * (sg * s) * px + c * py;
+            }
+        }
+    } else {
+#pragma omp parallel for schedule(static)
+        for (int64_t rd = 0; rd < S->cd; rd++) {
+            const uint32_t d = S->dn[rd];
+            if (!(d & pm) || (d & qm))
+                continue;
+            const int64_t rd2 = S->rank_dn[d ^ pm ^ qm];
+            for (int64_t ru = 0; ru < S->cu; ru++) {
+                const int64_t x = rd * S->cu + ru, y = rd2 * S->cu + ru;
+                const double sg = jw_sign(sector_full(S, x), p, q);
+                cplx px = psi[x], py = psi[y];
+                psi[x] = c * px - I * (sg * s) * py;
+                psi[y] = -I * (sg * s) * px + c * py;
+            }
+        }
+    }
+}
+
+/* out += coef * (a+_p a_q + a+_q a_p) psi on the sector. */
+static void sec_add_hop(const orc_sector *S, int p, int q, double coef, const cplx *psi,
+                        cplx *out)
+{
+    const uint64_t mask = ((uint64_t)1 << p) | ((uint64_t)1 << q);
+    const int64_t dim = sector_dim(S);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < dim; i++) {
+        const uint64_t b = sector_full(S, i);
+        if (bit(b, p) != bit(b, q))
+            out[i] += coef * jw_sign(b, p, q) * psi[sector_pos(S, b ^ mask)];
+    }
+}
+
+static void sec_apply_slot(const orc_model *m, const orc_sector *S, int slot, double theta,
+                           cplx *psi)
+{
+    if (slot == 0) {
+        const int64_t dim = sector_dim(S);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < dim; i++) {
+            double ang = theta * diag_value(m, sector_full(S, i));
+            psi[i] *= cos(ang) - I * sin(ang);
+        }
+        return;
+    }
+    for (int k = 0; k < m->nbonds; k++) {
+        if (m->bond_slot[k] != slot)
+            continue;
+        for (int spin = 0; spin < 2; spin++)
+            sec_apply_hop(S, spin, qubit_of(m, m->bond_i[k], spin),
+                          qubit_of(m, m->bond_j[k], spin), -m->t[k], theta, psi);
+    }
+}
+
+static void sec_generator_apply(const orc_model *m, const orc_sector *S, int slot,
+                                const cplx *psi, cplx *out)
+{
+    const int64_t dim = sector_dim(S);
+    if (slot == 0) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < dim; i++)
+            out[i] = diag_value(m, sector_full(S, i)) * psi[i];
+        return;
+    }
+    memset(out, 0, (size_t)dim * sizeof(cplx));
+    for (int k = 0; k < m->nbonds; k++) {
+        if (m->bond_slot[k] != slot)
+            continue;
+        for (int spin = 0; spin < 2; spin++)
+            sec_add_hop(S, qubit_of(m, m->bond_i[k], spin), qubit_of(m, m->bond_j[k], spin),
+                        -m->t[k], psi, out);
+    }
+}
+
+static void sec_ham_apply(const orc_model *m, const orc_sector *S, const cplx *psi, cplx *out)
+{
+    const int64_t dim = sector_dim(S);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < dim; i++)
+        out[i] = diag_value(m, sector_full(S, i)) * psi[i];
+    for (int k = 0; k < m->nbonds; k++)
+        for (int spin = 0; spin < 2; spin++)
+            sec_add_hop(S, qubit_of(m, m->bond_i[k], spin), qubit_of(m, m->bond_j[k], spin),
+                        -m->t[k], psi, out);
+}
+
+/* <a|b> over n entries, compensated, chunk-deterministic. */
+static void sec_inner(int64_t n, const cplx *a, const cplx *b, double *re, double *im)
+{
+    const int64_t chunk = (int64_t)1 << CHUNK_BITS;
+    const int64_t nchunks = (n + chunk - 1) / chunk;
+    double *pr = malloc((size_t)(nchunks ? nchunks : 1) * sizeof(double));
+    double *pi = malloc((size_t)(nchunks ? nchunks : 1) * sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nchunks; c++) {
+        nsum sr = {0, 0}, si = {0, 0};
+        const int64_t end = (c + 1) * chunk < n ? (c + 1) * chunk : n;
+        for (int64_t k = c * chunk; k < end; k++) {
+            cplx z = conj(a[k]) * b[k];
+            nsum_add(&sr, creal(z));
+            nsum_add(&si, cimag(z));
+        }
+        pr[c] = nsum_value(&sr);
+        pi[c] = nsum_value(&si);
+    }
+    nsum tr = {0, 0}, ti = {0, 0};
+    for (int64_t c = 0; c < nchunks; c++) {
+        nsum_add(&tr, pr[c]);
+        nsum_add(&ti, pi[c]);
+    }
+    *re = nsum_value(&tr);
+    *im = nsum_value(&ti);
+    free(pr);
+    free(pi);
+}
+
+/* Number of amplitudes in the sector of b0 (0 for the interleaved order). */
+int64_t orc_sector_dim(const orc_model *m, uint64_t b0)
+{
+    orc_sector S;
+    if (sector_make(m, b0, &S))
+        return 0;
+    int64_t d = sector_dim(&S);
+    sector_free(&S);
+    return d;
+}
+
+/* Full amplitude index of every sector position (out holds dim entries). */
+int orc_sector_indices(const orc_model *m, uint64_t b0, uint64_t *out)
+{
+    orc_sector S;
+    if (sector_make(m, b0, &S))
+        return -1;
+    for (int64_t i = 0; i < sector_dim(&S); i++)
+        out[i] = sector_full(&S, i);
+    sector_free(&S);
+    return 0;
+}
+
+/* Eq. (3) on the sector: psi (dim entries) = U_P ... U_1 |b0>. */
+int orc_sector_ansatz(const orc_model *m, const double *theta, int layers, uint64_t b0, cplx *psi)
+{
+    orc_sector S;
+    if (sector_make(m, b0, &S))
+        return -1;
+    const int per = 1 + m->ngroups;
+    memset(psi, 0, (size_t)sector_dim(&S) * sizeof(cplx));
+    psi[sector_pos(&S, b0)] = 1.0;
+    for (int l = 0; l < layers; l++)
+        for (int s = 0; s < per; s++)
+            sec_apply_slot(m, &S, s, theta[l * per + s], psi);
+    sector_free(&S);
+    return 0;
+}
+
+/* out = H psi on the sector of b0 (H maps the sector into itself). */
+int orc_sector_ham_apply(const orc_model *m, uint64_t b0, const cplx *psi, cplx *out)
+{
+    orc_sector S;
+    if (sector_make(m, b0, &S))
+        return -1;
+    sec_ham_apply(m, &S, psi, out);
+    sector_free(&S);
+    return 0;
+}
+
+/* Energy and adjoint gradient on the sector: the recursion of
+ * orc_energy_grad with every vector restricted to the sector.  Returns 0, or
+ * -1 (allocation failure or interleaved order). */
+int orc_sector_energy_grad(const orc_model *m, const double *theta, int layers, uint64_t b0,
+                           double *E, double *grad)
+{
+    orc_sector S;
+    if (sector_make(m, b0, &S))
+        return -1;
+    const int64_t dim = sector_dim(&S);
+    const int per = 1 + m->ngroups;
+    cplx *psi = malloc((size_t)dim * sizeof(cplx));
+    cplx *lam = malloc((size_t)dim * sizeof(cplx));
+    cplx *tmp = grad ? malloc((size_t)dim * sizeof(cplx)) : NULL;
+    if (!psi || !lam || (grad && !tmp)) {
+        free(psi);
+        free(lam);
+        free(tmp);
+        sector_free(&S);
+        return -1;
+    }
+    memset(psi, 0, (size_t)dim * sizeof(cplx));
+    psi[sector_pos(&S, b0)] = 1.0;
+    for (int l = 0; l < layers; l++)
+        for (int s = 0; s < per; s++)
+            sec_apply_slot(m, &S, s, theta[l * per + s], psi);
+    sec_ham_apply(m, &S, psi, lam);
+    double re, im;
+    sec_inner(dim, psi, lam, &re, &im);
+    *E = re;
+    for (int k = grad ? layers * per - 1 : -1; k >= 0; k--) {
+        int slot = k % per;
+        sec_generator_apply(m, &S, slot, psi, tmp);
+        sec_inner(dim, lam, tmp, &re, &im);
+        grad[k] = 2.0 * im;
+        sec_apply_slot(m, &S, slot, -theta[k], psi);
+        sec_apply_slot(m, &S, slot, -theta[k], lam);
+    }
+    free(psi);
+    free(lam);
+    free(tmp);
+    sector_free(&S);
+    return 0;
+}
