@@ -227,6 +227,16 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
  * be under graph capture); later calls only launch kernels, allocate
  * nothing, and may be captured into a graph and replayed with new theta
  * values in place.
+ * Lifetime of a planned batch: it is keyed by each handle's identity (a
+ * number never given to another handle, not its address) and tile
+ * configuration, so a batch of new handles never reuses an old plan.  It
+ * points into its members' device tables, so hubbard_destroy,
+ * hubbard_set_tiles or hubbard_tune of any member discards it (after
+ * waiting for the device to go idle), and at most 16 planned batches are
+ * kept: planning a 17th discards the least recently called one.  A graph
+ * captured from a discarded batch -- or an energy/energy_grad graph
+ * captured before hubbard_set_tiles or hubbard_tune of its handle -- must
+ * not be replayed; the next eager call plans again.
  * Errors: HUBBARD_ERR_ARG, HUBBARD_ERR_SIZE (workspace), HUBBARD_ERR_STATE
  * (first call under capture), HUBBARD_ERR_DEVICE. */
 hubbard_status hubbard_batch_workspace_size(const hubbard_t *hs, int32_t n,

@@ -29,8 +29,10 @@ hubbard_status hubbard_plan_dump(hubbard_t h, int32_t n_layers, int32_t which, i
                                  int64_t cap, int64_t *len);
 
 /* Tile bits of forward and reverse passes (2..13) and the minimum contiguous
- * low bits c of every tile.  Drops cached device programs of the handle;
- * call it before queueing work, not while work is in flight. */
+ * low bits c of every tile.  Drops cached device programs of the handle and
+ * every planned batch that includes it (graphs captured from them must not
+ * be replayed afterwards); call it before queueing work, not while work is
+ * in flight. */
 hubbard_status hubbard_set_tiles(hubbard_t h, int32_t fwd_k, int32_t rev_k, int32_t c);
 
 /* Current tile configuration: cfg[0] forward k, cfg[1] reverse k, cfg[2] c. */
@@ -48,6 +50,10 @@ hubbard_status hubbard_get_tiles(hubbard_t h, int32_t *cfg);
 hubbard_status hubbard_tune(hubbard_t h, int32_t n_layers, const double *theta_dev, void *ws_dev,
                             size_t ws_bytes, void *stream, int32_t reps, int32_t *table,
                             int32_t table_cap, int32_t *n_tried, float *table_ms);
+
+/* Number of planned batches (energy_grad_batch) the library currently
+ * keeps (at most 16). */
+hubbard_status hubbard_batch_cached(int32_t *count);
 
 /* Phase timing.  When enabled, every later call records HIP events on its own
  * stream around its phases: the forward passes, the H (or expectation)

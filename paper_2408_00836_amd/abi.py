@@ -32,6 +32,7 @@ EXPORTED = [
     "hubbard_plan_dump", "hubbard_set_tiles", "hubbard_set_timing", "hubbard_phase_ms",
     "hubbard_kernel_ms",
     "hubbard_batch_workspace_size", "energy_grad_batch", "hubbard_get_tiles", "hubbard_tune",
+    "hubbard_batch_cached",
 ]
 
 
@@ -105,6 +106,7 @@ def lib() -> ctypes.CDLL:
             "hubbard_phase_ms": ([vp, P(ctypes.c_float), P(ctypes.c_float),
                                   P(ctypes.c_float)], st),
             "hubbard_kernel_ms": ([vp, i32, P(ctypes.c_float), P(i32)], st),
+            "hubbard_batch_cached": ([P(i32)], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -317,3 +319,10 @@ def hubbard_tune(h: int, n_layers: int, theta_dev: int, ws_dev: int, ws_bytes: i
     _check(lib().hubbard_tune(h, int(n_layers), theta_dev, ws_dev, int(ws_bytes), stream,
                               int(reps), table, cap, ctypes.byref(n), ms))
     return [(table[3 * i], table[3 * i + 1], table[3 * i + 2], ms[i]) for i in range(n.value)]
+
+
+def hubbard_batch_cached() -> int:
+    n = ctypes.c_int32()
+    _check(lib().hubbard_batch_cached(ctypes.byref(n)))
+    return n.value
+

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -112,6 +113,11 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct hubbard_model {
     Model m;
+    // identity of the handle for caches that outlive a call: never reused by
+    // a later handle (unlike its address); gen counts the changes of the
+    // tile configuration, which replace the device programs
+    uint64_t uid = 0;
+    uint64_t gen = 0;
     TileConfig fwd_tc{12, 4};
     TileConfig rev_tc{12, 4};
     std::map<int, DeviceState> dev;
@@ -991,6 +997,8 @@ hubbard_status batch_host_programs(const hubbard_t *hs, int n, const int32_t *la
 
 struct BatchProgram {
     BatchLayout L;
+    std::vector<uint64_t> uids;   // handles whose device tables the instances point into
+    uint64_t last_use = 0;        // cache clock of the last call
     DevInstance *d_inst = nullptr;
     DevPass *d_passes = nullptr;
     DevWork *d_work = nullptr;
@@ -1023,8 +1031,45 @@ struct BatchProgram {
     }
 };
 
+// Batch programs by their signature: the device, theta and workspace
+// pointers (the program's work items point into them) and each instance's
+// handle uid, tile generation, layer count and parameter offset.  A program
+// points into its instances' device programs, so a change of any member's
+// tiles (hubbard_set_tiles, hubbard_tune) or its destruction evicts every
+// program that uses it; at most kMaxBatches programs are kept, the least
+// recently called one is evicted first.  Eviction waits for the device to go
+// idle before freeing (work queued with those tables may still run).
+constexpr size_t kMaxBatches = 16;
 std::mutex g_batch_mu;
 std::map<std::string, std::unique_ptr<BatchProgram>> g_batches;
+uint64_t g_batch_clock = 0;
+std::atomic<uint64_t> g_next_uid{1};
+
+// g_batch_mu held.  Frees the programs for which pred() holds.
+template <typename Pred>
+void evict_batches_locked(Pred pred)
+{
+    bool synced = false;
+    for (auto it = g_batches.begin(); it != g_batches.end();) {
+        if (!pred(*it->second)) {
+            ++it;
+            continue;
+        }
+        if (!synced) {
+            (void)hipDeviceSynchronize();
+            synced = true;
+        }
+        it = g_batches.erase(it);
+    }
+}
+
+void evict_batches_of(uint64_t uid)
+{
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    evict_batches_locked([uid](const BatchProgram &bp) {
+        return std::find(bp.uids.begin(), bp.uids.end(), uid) != bp.uids.end();
+    });
+}
 
 hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, const int64_t *toff,
                            const int32_t *layers, char *ws, BatchProgram &bp)
@@ -1033,6 +1078,9 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
     if (hipGetDevice(&dev) != hipSuccess)
         return fail(HUBBARD_ERR_DEVICE, "no current device");
     bp.n = n;
+    for (int i = 0; i < n; ++i)
+        if (std::find(bp.uids.begin(), bp.uids.end(), hs[i]->uid) == bp.uids.end())
+            bp.uids.push_back(hs[i]->uid);
     // the instances' device programs (cached per handle, device and layer count)
     std::vector<const Program *> progs(n);
     std::vector<DevInstance> insts(n);
@@ -1135,6 +1183,7 @@ hubbard_status hubbard_create(const hubbard_desc *d, hubbard_t *out)
         delete h;
         return fail(HUBBARD_ERR_ARG, err);
     }
+    h->uid = g_next_uid.fetch_add(1);
     *out = h;
     return HUBBARD_OK;
 }
@@ -1157,6 +1206,7 @@ hubbard_status hubbard_create_graph(const hubbard_graph_desc *d, hubbard_t *out)
         delete h;
         return fail(HUBBARD_ERR_ARG, err);
     }
+    h->uid = g_next_uid.fetch_add(1);
     *out = h;
     return HUBBARD_OK;
 }
@@ -1165,6 +1215,7 @@ void hubbard_destroy(hubbard_t h)
 {
     if (!h)
         return;
+    evict_batches_of(h->uid);
     if (h->ev_ready)
         for (int j = 0; j < 4; ++j)
             (void)hipEventDestroy(h->ev[j]);
@@ -1317,6 +1368,49 @@ hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers, do
     return run_reduce(*pr, partial, E_dev, nullptr, s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The launch sequence of energy_grad on given psi, lambda and partial-sum
+// buffers.  th: the handle whose timing events are recorded, or NULL (no
+// event is created or recorded).
+hubbard_status grad_sequence(hubbard_model *h, hubbard_model *th, const Program &pr,
+                             const DeviceState &ds, const double *theta_dev, double *E_dev,
+                             double *grad_dev, double2 *psi, double2 *lam, double *partial,
+                             VecLayout vl, hipStream_t s)
+{
+    hubbard_status st;
+    // the first forward pass starts from |b0> itself (no init pass), and the
+    // last reverse pass stores nothing: only its reductions are needed
+    const bool from_start = !pr.fwd.pass.empty();
+    if (!from_start && (st = run_init(h, psi, s, vl)) != HUBBARD_OK)
+        return st;
+    if (th) {
+        th->ev_used = 0;
+        th->kmode.clear();
+        mark(th, 0, s);
+    }
+    if ((st = run_forward(pr, ds, theta_dev, psi, s, th, vl, from_start)) != HUBBARD_OK)
+        return st;
+    if (th)
+        mark(th, 1, s);
+    if ((st = run_ham(pr, ds, psi, lam, partial, s, th, vl)) != HUBBARD_OK)
+        return st;
+    if (th)
+        mark(th, 2, s);
+    launch_list<M_REV>(pr, ds, pr.rev, theta_dev, psi, lam, partial, s, th, vl, 0, PF_NO_STORE);
+    if ((st = check_launch("reverse pass")) != HUBBARD_OK)
+        return st;
+    if (th)
+        mark(th, 3, s);
+    return run_reduce(pr, partial, E_dev, grad_dev, s);
+}
+
+}  // namespace
+
+extern "C" {
+
 hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers, double *E_dev,
                            double *grad_dev, void *ws_dev, size_t ws_bytes, void *stream)
 {
@@ -1337,26 +1431,7 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
     double2 *lam = vl.ilv == kPlainVec ? (double2 *)((char *)ws_dev + vb)
                                        : psi + ((size_t)1 << vl.ilv);
     double *partial = (double *)((char *)ws_dev + 2 * vb);
-    // the first forward pass starts from |b0> itself (no init pass), and the
-    // last reverse pass stores nothing: only its reductions are needed
-    const bool from_start = !pr->fwd.pass.empty();
-    if (!from_start && (st = run_init(h, psi, s, vl)) != HUBBARD_OK)
-        return st;
-    h->ev_used = 0;
-    h->kmode.clear();
-    mark(h, 0, s);
-    if ((st = run_forward(*pr, *ds, theta_dev, psi, s, h, vl, from_start)) != HUBBARD_OK)
-        return st;
-    mark(h, 1, s);
-    if ((st = run_ham(*pr, *ds, psi, lam, partial, s, h, vl)) != HUBBARD_OK)
-        return st;
-    mark(h, 2, s);
-    launch_list<M_REV>(*pr, *ds, pr->rev, theta_dev, psi, lam, partial, s, h, vl, 0,
-                       PF_NO_STORE);
-    if ((st = check_launch("reverse pass")) != HUBBARD_OK)
-        return st;
-    mark(h, 3, s);
-    return run_reduce(*pr, partial, E_dev, grad_dev, s);
+    return grad_sequence(h, h, *pr, *ds, theta_dev, E_dev, grad_dev, psi, lam, partial, vl, s);
 }
 
 hubbard_status hubbard_batch_workspace_size(const hubbard_t *hs, int32_t n,
@@ -1397,8 +1472,8 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
     std::string key = std::to_string(dev) + ":" + std::to_string((uintptr_t)theta_dev) + ":" +
                       std::to_string((uintptr_t)ws_dev);
     for (int i = 0; i < n; ++i)
-        key += ":" + std::to_string((uintptr_t)hs[i]) + "/" + std::to_string(n_layers[i]) + "/" +
-               std::to_string(theta_off[i]);
+        key += ":" + std::to_string(hs[i]->uid) + "." + std::to_string(hs[i]->gen) + "/" +
+               std::to_string(n_layers[i]) + "/" + std::to_string(theta_off[i]);
     hipStream_t s = (hipStream_t)stream;
     BatchProgram *bp = nullptr;
     {
@@ -1409,6 +1484,13 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
             if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
                 return fail(HUBBARD_ERR_STATE, "first call of a batch must happen outside graph "
                                                "capture (it uploads the batch tables)");
+            if (g_batches.size() >= kMaxBatches) {
+                const BatchProgram *lru = nullptr;
+                for (const auto &kv : g_batches)
+                    if (!lru || kv.second->last_use < lru->last_use)
+                        lru = kv.second.get();
+                evict_batches_locked([lru](const BatchProgram &bp) { return &bp == lru; });
+            }
             std::unique_ptr<BatchProgram> nb(new BatchProgram());
             hubbard_status st = build_batch(hs, n, theta_dev, theta_off, n_layers,
                                             (char *)ws_dev, *nb);
@@ -1417,6 +1499,7 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
             it = g_batches.emplace(key, std::move(nb)).first;
         }
         bp = it->second.get();
+        bp->last_use = ++g_batch_clock;
     }
     const BatchLayout &L = bp->L;
     if (ws_bytes < L.ws_bytes)
@@ -1514,9 +1597,13 @@ hubbard_status hubbard_set_tiles(hubbard_t h, int32_t fwd_k, int32_t rev_k, int3
     if (!h || fwd_k < 2 || fwd_k > kMaxTileBits || rev_k < 2 || rev_k > kMaxTileBits || c < 0 ||
         c > fwd_k || c > rev_k)
         return fail(HUBBARD_ERR_ARG, "tile bits must be in [2, 13] and c <= k");
+    // batches point into the device programs dropped below; evict them first
+    // (lock order: the batch cache before a handle)
+    evict_batches_of(h->uid);
     std::lock_guard<std::mutex> lk(h->mu);
     h->fwd_tc = TileConfig{fwd_k, c};
     h->rev_tc = TileConfig{rev_k, c};
+    ++h->gen;
     for (auto &kv : h->dev)
         kv.second.progs.clear();
     return HUBBARD_OK;
@@ -1609,11 +1696,22 @@ hubbard_status hubbard_tune(hubbard_t h, int32_t n_layers, const double *theta_d
     (void)hipEventDestroy(e1);
     *n_tried = tried;
     if (st != HUBBARD_OK) {
-        h->fwd_tc = keep_f;
-        h->rev_tc = keep_r;
+        // back to the configuration on entry (drops the candidate's programs)
+        const std::string err = g_err;
+        hubbard_set_tiles(h, keep_f.k, keep_r.k, keep_f.c);
+        g_err = err;
         return st;
     }
     hubbard_set_tiles(h, bestc[0], bestc[1], bestc[2]);
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_batch_cached(int32_t *count)
+{
+    if (!count)
+        return fail(HUBBARD_ERR_ARG, "NULL count");
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    *count = (int32_t)g_batches.size();
     return HUBBARD_OK;
 }
 
