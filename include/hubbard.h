@@ -197,6 +197,24 @@ hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layer
                            double *E_dev, double *grad_dev, void *ws_dev,
                            size_t ws_bytes, void *stream);
 
+/* energy_grad for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and results as energy_grad, with
+ * psi, lambda and the reduction partials in a 48 MiB array that the library
+ * holds in every device's memory from its load until the process ends.
+ * It allocates nothing, creates no events and synchronises nothing.
+ *   - At most 20 qubits and 128 reduction rows (the circuits of up to 20
+ *     qubits used here have fewer than 70); larger: HUBBARD_ERR_SIZE.
+ *   - The handle's plan for this device and layer count must already be
+ *     uploaded by one earlier energy_grad call (HUBBARD_ERR_STATE
+ *     otherwise).
+ *   - Every call on a device shares that device's array and keeps the last
+ *     call's contents; each call writes the parts it reads before reading
+ *     them.  Calls that overlap on one device (other streams, other host
+ *     threads) race. */
+hubbard_status energy_grad_noalloc(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                                   double *E_dev, double *grad_dev, void *stream);
+
 /* Batched energy and gradient of many independent instances (different
  * lattices, sizes, U, disorder, V and layer counts; each its own parameters)
  * with no host work per call: a fixed sequence of launches on `stream` --

@@ -32,7 +32,7 @@ EXPORTED = [
     "hubbard_plan_dump", "hubbard_set_tiles", "hubbard_set_timing", "hubbard_phase_ms",
     "hubbard_kernel_ms",
     "hubbard_batch_workspace_size", "energy_grad_batch", "hubbard_get_tiles", "hubbard_tune",
-    "hubbard_batch_cached",
+    "hubbard_batch_cached", "energy_grad_noalloc",
 ]
 
 
@@ -107,6 +107,7 @@ def lib() -> ctypes.CDLL:
                                   P(ctypes.c_float)], st),
             "hubbard_kernel_ms": ([vp, i32, P(ctypes.c_float), P(i32)], st),
             "hubbard_batch_cached": ([P(i32)], st),
+            "energy_grad_noalloc": ([vp, vp, i32, vp, vp, vp], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -326,3 +327,8 @@ def hubbard_batch_cached() -> int:
     _check(lib().hubbard_batch_cached(ctypes.byref(n)))
     return n.value
 
+
+
+def energy_grad_noalloc(h: int, theta_dev: int, n_layers: int, E_dev: int, grad_dev: int,
+                        stream: int = 0) -> None:
+    _check(lib().energy_grad_noalloc(h, theta_dev, int(n_layers), E_dev, grad_dev, stream))

@@ -1407,9 +1407,92 @@ hubbard_status grad_sequence(hubbard_model *h, hubbard_model *th, const Program 
     return run_reduce(pr, partial, E_dev, grad_dev, s);
 }
 
+// ------------------------------------------------- library-owned scratch --
+// energy_grad_noalloc keeps psi, lambda and the partial sums in this array
+// instead of a caller workspace: psi at offset 0 and lambda at
+// kScratchVecBytes (2^20 amplitudes each, plain layout), the partial rows
+// (kGridMax doubles each, up to kScratchRows) after them.  Each device that
+// runs the library holds its own copy until the process ends.  In host code
+// the name is only a stand-in for the symbol: kernels get the device
+// address from hipGetSymbolAddress (per device, on that device's first
+// call), never the name.
+constexpr int kScratchQubits = 20;
+constexpr size_t kScratchVecBytes = ((size_t)16) << kScratchQubits;
+constexpr int kScratchRows = 128;
+constexpr size_t kScratchBytes =
+    2 * kScratchVecBytes + (size_t)kScratchRows * kGridMax * sizeof(double);   // 48 MiB
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr;   // device -> address of its copy of `scratch`
+
+hubbard_status scratch_address(int dev, char **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        char *p = nullptr;
+        hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HUBBARD_ERR_DEVICE,
+                        std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return HUBBARD_OK;
+}
+
+// The handle's uploaded program of (kind, layers) on the current device, or
+// NULL: looks only, never plans or uploads (no allocation).
+Program *find_program(hubbard_model *h, int dev, int kind, int layers, DeviceState **dsout)
+{
+    std::lock_guard<std::mutex> lk(h->mu);
+    auto d = h->dev.find(dev);
+    if (d == h->dev.end() || !d->second.d_model)
+        return nullptr;
+    auto it = d->second.progs.find(std::make_pair(kind, layers));
+    if (it == d->second.progs.end())
+        return nullptr;
+    *dsout = &d->second;
+    return it->second.get();
+}
+
 }  // namespace
 
 extern "C" {
+
+hubbard_status energy_grad_noalloc(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                                   double *E_dev, double *grad_dev, void *stream)
+{
+    if (!h || !E_dev || n_layers < 0 || (n_layers > 0 && (!theta_dev || !grad_dev)))
+        return fail(HUBBARD_ERR_ARG, "bad arguments to energy_grad_noalloc");
+    if (h->m.nq > kScratchQubits)
+        return fail(HUBBARD_ERR_SIZE, "energy_grad_noalloc: " + std::to_string(h->m.nq) +
+                                          " qubits exceed the library scratch (at most " +
+                                          std::to_string(kScratchQubits) + ")");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    DeviceState *ds = nullptr;
+    Program *pr = find_program(h, dev, PROG_GRAD, n_layers, &ds);
+    if (!pr)
+        return fail(HUBBARD_ERR_STATE, "energy_grad_noalloc: no uploaded plan for this handle, "
+                                       "device and layer count (call energy_grad once first)");
+    if (pr->n_rows > kScratchRows)
+        return fail(HUBBARD_ERR_SIZE, "energy_grad_noalloc: " + std::to_string(pr->n_rows) +
+                                          " reduction rows exceed the library scratch (at most " +
+                                          std::to_string(kScratchRows) + ")");
+    char *base = nullptr;
+    hubbard_status st = scratch_address(dev, &base);
+    if (st != HUBBARD_OK)
+        return st;
+    double2 *psi = (double2 *)base;
+    double2 *lam = (double2 *)(base + kScratchVecBytes);
+    double *partial = (double *)(base + 2 * kScratchVecBytes);
+    return grad_sequence(h, nullptr, *pr, *ds, theta_dev, E_dev, grad_dev, psi, lam, partial,
+                         VecLayout(), (hipStream_t)stream);
+}
 
 hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers, double *E_dev,
                            double *grad_dev, void *ws_dev, size_t ws_bytes, void *stream)
