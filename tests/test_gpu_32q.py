@@ -1,10 +1,13 @@
 """Parity at the full 32-qubit size (4x4 periodic, U=8, 16 layers, 80 params),
 in the launch configuration bench.py times.
 
-A dense oracle run at 32 qubits needs three 64 GiB vectors and hours of CPU,
-so the full-size checks use exact special cases that the oracle side computes
-independently of any 32-qubit state vector, plus properties that hold at any
-size:
+At the benchmark's own seeded angles the energy, all 80 gradient entries and
+301 sampled amplitudes are compared with the oracle's values, stored in
+tests/golden/c5_4x4_periodic_U8.json by tests/golden/make_c5_golden.py (the
+oracle's particle-number sector form, which holds the 1.66e8 nonzero
+amplitudes instead of 2^32).  Besides that, exact special cases that the
+oracle side computes independently of any 32-qubit state vector, and
+properties that hold at any size:
   * free-fermion case (diagonal angles zero after layer 0): sampled amplitudes
     from Slater determinants, E from Wick's theorem, every hopping gradient
     exactly (oracle.freefermion, 16 x 16 matrices);
@@ -16,6 +19,8 @@ size:
   * H|psi> of a seeded random vector (torch's generator, not the library):
     sampled outputs against single rows of H from the oracle.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -32,6 +37,8 @@ pytestmark = pytest.mark.gpu
 
 AMP_TOL = 1e-10
 GRAD_TOL = 1e-8
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "c5_4x4_periodic_U8.json")
 
 
 def say(*a):
@@ -67,6 +74,29 @@ def sector_samples(rng, n):
         dn = rng.choice(16, 8, replace=False)
         out.append(int(sum(1 << int(s) for s in up) + sum(1 << (16 + int(s)) for s in dn)))
     return out
+
+
+def test_bench_theta_vs_oracle_32q(c5):
+    """E to 1e-12 relative, every gradient entry to 1e-8 and sampled
+    amplitudes to 1e-10 against the oracle at the benchmark's angles."""
+    w, m, om = c5
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    assert np.array_equal(np.array(gold["theta"]), w.theta)   # same seeded input
+    tdev = torch.tensor(w.theta, dtype=torch.float64, device="cuda")
+    say("[32q] bench theta: energy_grad vs the oracle's golden values")
+    E, g = m.energy_grad(tdev)
+    E, g = E.item(), g.cpu().numpy()
+    assert abs(E - gold["E"]) <= 1e-12 * max(1.0, abs(gold["E"])), (E, gold["E"])
+    err = np.abs(g - np.array(gold["grad"]))
+    assert err.max() <= GRAD_TOL, (int(err.argmax()), float(err.max()))
+    say("[32q] bench theta: sampled amplitudes")
+    psi = state_in_workspace(m, tdev)
+    idx = torch.tensor(gold["amp_index"], device="cuda")
+    got = psi[idx].cpu().numpy()
+    want = np.array(gold["amp_re"]) + 1j * np.array(gold["amp_im"])
+    assert np.max(np.abs(got - want)) <= AMP_TOL
+    assert np.max(np.abs(want)) > 1e-5   # the samples are not all trivial
 
 
 def test_free_fermion_32q(c5):
@@ -174,9 +204,9 @@ def test_symmetry_norm_and_fd_32q(c5):
     psi = state_in_workspace(m, tdev)
     nrm = sum(torch.vdot(c, c).real.item() for c in psi.split(1 << 28))
     assert abs(nrm - 1.0) < 1e-12
-    say("[32q] central finite differences for two parameters")
+    say("[32q] central finite differences: every slot class of layer 7, layers 0 and 15")
     h = 1e-5
-    for k in (1, 77):
+    for k in (1, 35, 36, 37, 38, 39, 77):
         tp, tm = tdev.clone(), tdev.clone()
         tp[k] += h
         tm[k] -= h

@@ -87,29 +87,29 @@ def test_sector_free_fermion_24q(oracle_lib):
     assert abs(np.vdot(psi, psi).real - 1.0) <= 1e-12
 
 
-def test_sector_periodic_4x4_one_layer_invariants(oracle_lib):
-    """The benchmark lattice itself at one layer: E(theta) = E(-theta), the
-    gradient is odd, the first diagonal angle has zero gradient, and H maps
-    the sector state to one of the same norm as H applied column by column
-    through single rows (a pin of H on the 4x4 torus with wrap strings)."""
+def test_sector_periodic_4x4_low_filling(oracle_lib):
+    """The benchmark's 4x4 torus (wrap bonds with Jordan-Wigner strings
+    across whole rows) in the 2-up, 2-down sector of a chosen basis state
+    (14400 amplitudes): H against single rows of the full-space H, the
+    symmetry E(theta) = E(-theta) with an odd gradient, the first diagonal
+    angle's zero gradient, and the norm."""
     om = make_model(4, 4, periodic_x=True, periodic_y=True, U=8.0)
-    th = rng_theta(9, om.params_per_layer)
-    E1, g1 = sector.energy_grad(om, th, 1)
-    E2, g2 = sector.energy_grad(om, -th, 1)
-    assert abs(E1 - E2) <= 1e-12 * abs(E1)
+    b0 = (1 << 0) | (1 << 5) | (1 << (16 + 10)) | (1 << (16 + 15))
+    L = 2
+    th = rng_theta(9, L * om.params_per_layer)
+    E1, g1 = sector.energy_grad(om, th, L, b0)
+    E2, g2 = sector.energy_grad(om, -th, L, b0)
+    assert abs(E1 - E2) <= 1e-12 * max(1.0, abs(E1))
     assert np.max(np.abs(g1 + g2)) <= 1e-12
     assert abs(g1[0]) <= 1e-13
-    psi = sector.ansatz(om, th, 1)
-    phi = sector.ham_apply(om, psi)
-    idx = sector.indices(om)
-    pos = {}
-    pick = np.random.default_rng(10).choice(idx.size, 40, replace=False)
+    psi = sector.ansatz(om, th, L, b0)
+    assert abs(np.vdot(psi, psi).real - 1.0) <= 1e-12
+    phi = sector.ham_apply(om, psi, b0)
+    idx = sector.indices(om, b0)
+    assert idx.size == 120 ** 2
+    pick = np.random.default_rng(10).choice(idx.size, 500, replace=False)
     for i in pick:
         cols, coefs = core.ham_row(om, int(idx[i]))
-        vals = []
-        for c in cols:
-            p = pos.get(int(c))
-            if p is None:
-                p = pos[int(c)] = int(np.searchsorted(idx, np.uint64(c)))
-            vals.append(psi[p] if idx[p] == c else 0.0)
-        assert abs(phi[i] - np.sum(coefs * np.array(vals))) <= 1e-13
+        pos = np.searchsorted(idx, cols)
+        assert np.array_equal(idx[pos], cols)   # H keeps the sector
+        assert abs(phi[i] - np.sum(coefs * psi[pos])) <= 1e-13
