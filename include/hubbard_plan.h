@@ -29,7 +29,8 @@ hubbard_status hubbard_plan_dump(hubbard_t h, int32_t n_layers, int32_t which, i
                                  int64_t cap, int64_t *len);
 
 /* Tile bits of forward and reverse passes (2..13) and the minimum contiguous
- * low bits c of every tile.  Drops cached device programs of the handle and
+ * low bits c of every tile; k - c >= 2 unless k covers every qubit
+ * (HUBBARD_ERR_ARG otherwise).  Drops cached device programs of the handle and
  * every planned batch that includes it (graphs captured from them must not
  * be replayed afterwards); call it before queueing work, not while work is
  * in flight. */
@@ -50,6 +51,17 @@ hubbard_status hubbard_get_tiles(hubbard_t h, int32_t *cfg);
 hubbard_status hubbard_tune(hubbard_t h, int32_t n_layers, const double *theta_dev, void *ws_dev,
                             size_t ws_bytes, void *stream, int32_t reps, int32_t *table,
                             int32_t table_cap, int32_t *n_tried, float *table_ms);
+
+/* Planning parameters of later batches (energy_grad_batch): work items per
+ * instance pass (a power of two in [1, 4096]; an instance's tiles are split
+ * over up to that many workgroups) and stream lanes in [1, 4] (1: every
+ * launch on the caller's stream; else the single-tile instances on one lane
+ * of their own and the others split over lanes-1 groups by forward length).
+ * A batch is planned with the values current at its first call and keyed
+ * by them, so batches planned under different values coexist.  Default
+ * (32, 4).  Host only; process-wide. */
+hubbard_status hubbard_batch_set_config(int32_t items, int32_t lanes);
+hubbard_status hubbard_batch_get_config(int32_t *items, int32_t *lanes);
 
 /* Number of planned batches (energy_grad_batch) the library currently
  * keeps (at most 16). */

@@ -766,26 +766,39 @@ void mark(hubbard_model *h, int i, hipStream_t s)
 
 // ================================================================ batch
 
-// Work items per instance pass: enough to spread a large instance over many
-// workgroups, few enough that each item streams several tiles (256 uneven
-// instances with lanes: 16, 32, 64, 128 items took 14.1, 12.6, 13.0, 13.5 ms).
-// A power of two, as the tile counts are: every item gets the same share.
-constexpr int kBatchItems = 32;
-static_assert((kBatchItems & (kBatchItems - 1)) == 0, "kBatchItems must be a power of two");
-// Streams of a batched evaluation: the caller's (lane 0, the longest
-// forward schedules) and the batch program's own: lane 1 for the instances
-// with one pass per schedule, lanes 2.. for shorter forward schedules.
-// Four streams in all, the hardware queues a process gets by default; with
-// 32 work items, 2, 3, 4, 5 length groups took 13.0, 12.5, 12.8, 13.3 ms
-// (eager; more streams than queues share queues) for 256 uneven instances.
-constexpr int kMultiLanes = 3;
-constexpr int kBatchLanes = kMultiLanes + 1;
+// Planning parameters of a batch (hubbard_batch_set_config; tuned and cached
+// by the Python front end, which sets them before a batch is first planned):
+//  - work items per instance pass: enough to spread a large instance over
+//    many workgroups, few enough that each item streams several tiles; a
+//    power of two, as the tile counts are, so every item gets the same
+//    share (256 uneven instances with four lanes: 16, 32, 64, 128 items
+//    took 14.1, 12.6, 13.0, 13.5 ms);
+//  - lanes (streams): the caller's (lane 0, the longest forward schedules)
+//    and the batch program's own: lane 1 for the instances with one pass
+//    per schedule, lanes 2.. for shorter forward schedules.  At most four,
+//    the hardware queues a process gets by default (with 32 work items, 2,
+//    3, 4, 5 length groups took 13.0, 12.5, 12.8, 13.3 ms eager for 256
+//    uneven instances; more streams than queues share queues).  One lane
+//    puts every launch on the caller's stream.
+constexpr int kBatchLanes = 4;
+struct BatchConfig {
+    int items = 32;
+    int lanes = kBatchLanes;
+};
+std::mutex g_batch_cfg_mu;
+BatchConfig g_batch_cfg;
+
+BatchConfig batch_config()
+{
+    std::lock_guard<std::mutex> lk(g_batch_cfg_mu);
+    return g_batch_cfg;
+}
 
 struct BatchLaunch {
     int mode;               // M_FWD, M_HAM or M_REV
     bool full;              // every item's tiles fill all registers of exactly `threads`
     bool start;             // first forward position: the passes build |b0> themselves
-    int lane;               // stream of the launch (kBatchLanes, below)
+    int lane;               // stream of the launch (0 .. lanes-1)
     int item0, n_items;     // work items [item0, item0 + n_items)
     int threads, smem;
 };
@@ -811,7 +824,8 @@ struct BatchLayout {
 };
 
 hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
-                            const std::vector<const Program *> &progs, BatchLayout &L)
+                            const std::vector<const Program *> &progs, const BatchConfig &cfg,
+                            BatchLayout &L)
 {
     const int lim = max_smem_per_block();
     size_t at = 0;
@@ -860,15 +874,15 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
     size_t fmax = 1;
     for (int i = 0; i < n; ++i)
         fmax = std::max(fmax, progs[i]->fwd.pass.size());
-    std::vector<int> lane_of(n);
-    for (int i = 0; i < n; ++i) {
+    std::vector<int> lane_of(n, 0);
+    const int groups = cfg.lanes - 1;   // length groups of multi-pass instances
+    for (int i = 0; i < n && cfg.lanes > 1; ++i) {
         const Program &pr = *progs[i];
         const bool single = pr.fwd.pass.size() == 1 && pr.ham.pass.size() == 1 &&
                             pr.rev.pass.size() == 1;
-        // multi-pass instances: group q = 0 (longest) .. kMultiLanes-1 by the
+        // multi-pass instances: group q = 0 (longest) .. groups-1 by the
         // share of the longest forward schedule still ahead of them
-        const int q = std::min<int>(kMultiLanes - 1,
-                                    (int)(kMultiLanes * (fmax - pr.fwd.pass.size()) / fmax));
+        const int q = std::min<int>(groups - 1, (int)(groups * (fmax - pr.fwd.pass.size()) / fmax));
         lane_of[i] = single ? 1 : (q == 0 ? 0 : q + 1);
     }
     const int modes[3] = {M_FWD, M_HAM, M_REV};
@@ -892,7 +906,7 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
                 inst.push_back(i);
                 widest = std::max(widest, 1 << pl.pass[j].tbits);
             }
-            for (int lane = 0; lane < kBatchLanes; ++lane)
+            for (int lane = 0; lane < cfg.lanes; ++lane)
             for (int full = 1; full >= 0; --full) {
                 BatchLaunch bl;
                 bl.mode = modes[ph];
@@ -912,7 +926,7 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
                     const size_t off = (ph == 0 ? 0 : ph == 1 ? pr.fwd.pass.size()
                                                                : pr.fwd.pass.size() + pr.ham.pass.size());
                     const uint64_t ntiles = (uint64_t)1 << P.nfree;
-                    const uint32_t items = (uint32_t)std::min<uint64_t>(ntiles, kBatchItems);
+                    const uint32_t items = (uint32_t)std::min<uint64_t>(ntiles, (uint64_t)cfg.items);
                     const uint32_t per = (uint32_t)(ntiles / items);
                     const int nred = P.n_red;
                     const size_t part0 = L.n_partial;
@@ -1072,7 +1086,8 @@ void evict_batches_of(uint64_t uid)
 }
 
 hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, const int64_t *toff,
-                           const int32_t *layers, char *ws, BatchProgram &bp)
+                           const int32_t *layers, char *ws, const BatchConfig &cfg,
+                           BatchProgram &bp)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
@@ -1100,7 +1115,7 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
         I.model = ds->d_model;
         I.theta = theta + toff[i];
     }
-    hubbard_status st = batch_layout(hs, n, toff, progs, bp.L);
+    hubbard_status st = batch_layout(hs, n, toff, progs, cfg, bp.L);
     if (st != HUBBARD_OK)
         return st;
     bool used[kBatchLanes] = {};
@@ -1532,7 +1547,7 @@ hubbard_status hubbard_batch_workspace_size(const hubbard_t *hs, int32_t n,
         return st;
     std::vector<int64_t> toff(n, 0);
     BatchLayout L;
-    st = batch_layout(hs, n, toff.data(), progs, L);
+    st = batch_layout(hs, n, toff.data(), progs, batch_config(), L);
     if (st != HUBBARD_OK)
         return st;
     *bytes = L.ws_bytes;
@@ -1552,8 +1567,10 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
     }
     int dev = 0;
     (void)hipGetDevice(&dev);
+    const BatchConfig cfg = batch_config();
     std::string key = std::to_string(dev) + ":" + std::to_string((uintptr_t)theta_dev) + ":" +
-                      std::to_string((uintptr_t)ws_dev);
+                      std::to_string((uintptr_t)ws_dev) + ":" + std::to_string(cfg.items) + "." +
+                      std::to_string(cfg.lanes);
     for (int i = 0; i < n; ++i)
         key += ":" + std::to_string(hs[i]->uid) + "." + std::to_string(hs[i]->gen) + "/" +
                std::to_string(n_layers[i]) + "/" + std::to_string(theta_off[i]);
@@ -1576,7 +1593,7 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
             }
             std::unique_ptr<BatchProgram> nb(new BatchProgram());
             hubbard_status st = build_batch(hs, n, theta_dev, theta_off, n_layers,
-                                            (char *)ws_dev, *nb);
+                                            (char *)ws_dev, cfg, *nb);
             if (st != HUBBARD_OK)
                 return st;
             it = g_batches.emplace(key, std::move(nb)).first;
@@ -1680,6 +1697,12 @@ hubbard_status hubbard_set_tiles(hubbard_t h, int32_t fwd_k, int32_t rev_k, int3
     if (!h || fwd_k < 2 || fwd_k > kMaxTileBits || rev_k < 2 || rev_k > kMaxTileBits || c < 0 ||
         c > fwd_k || c > rev_k)
         return fail(HUBBARD_ERR_ARG, "tile bits must be in [2, 13] and c <= k");
+    // a hopping term on two qubits above the contiguous low bits needs two
+    // more tile bits (unless a tile holds the whole state)
+    for (int k : {fwd_k, rev_k})
+        if (k - c < 2 && k < h->m.nq)
+            return fail(HUBBARD_ERR_ARG, "a tile needs at least two bits beyond its c contiguous "
+                                         "low bits (or all qubits)");
     // batches point into the device programs dropped below; evict them first
     // (lock order: the batch cache before a handle)
     evict_batches_of(h->uid);
@@ -1786,6 +1809,28 @@ hubbard_status hubbard_tune(hubbard_t h, int32_t n_layers, const double *theta_d
         return st;
     }
     hubbard_set_tiles(h, bestc[0], bestc[1], bestc[2]);
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_batch_set_config(int32_t items, int32_t lanes)
+{
+    if (items < 1 || items > 4096 || (items & (items - 1)) != 0 || lanes < 1 ||
+        lanes > kBatchLanes)
+        return fail(HUBBARD_ERR_ARG, "batch items must be a power of two in [1, 4096] and "
+                                     "lanes in [1, 4]");
+    std::lock_guard<std::mutex> lk(g_batch_cfg_mu);
+    g_batch_cfg.items = items;
+    g_batch_cfg.lanes = lanes;
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_batch_get_config(int32_t *items, int32_t *lanes)
+{
+    if (!items || !lanes)
+        return fail(HUBBARD_ERR_ARG, "NULL argument to hubbard_batch_get_config");
+    const BatchConfig c = batch_config();
+    *items = c.items;
+    *lanes = c.lanes;
     return HUBBARD_OK;
 }
 

@@ -13,6 +13,7 @@
 // commute with each other.  The diagonal of a layer is split into one
 // sub-term per site (U n_up n_dn + eps n) and one per V bond, so a spin-up
 // gate only waits for the sub-terms on its own sites.
+#include <stdexcept>
 #include <algorithm>
 #include <cstdint>
 #include <functional>
@@ -279,6 +280,9 @@ std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig 
             }
             return bestv;
         };
+        if (cands.empty())
+            throw std::runtime_error("no hopping term fits a tile of " + std::to_string(k) +
+                                     " bits with " + std::to_string(c) + " fixed low bits");
         Closure best = cands.front();
         if (tc.lookahead > 0 && cands.size() > 1) {
             int best_score = -1;
@@ -395,6 +399,9 @@ std::vector<HostPass> plan_hamiltonian(const Model &m, const TileConfig &tc)
                 --left;
                 p.ops.push_back(terms[i]);
             }
+        if (!first && p.ops.empty())
+            throw std::runtime_error("no Hamiltonian term fits a tile of " + std::to_string(k) +
+                                     " bits with " + std::to_string(c) + " fixed low bits");
         p.flags = first ? PF_HAM_FIRST : 0;
         first = false;
         plan_phases(p);

@@ -306,3 +306,21 @@ def test_create_graph_defaults_agree_with_oracle():
 def test_create_graph_rejects_invalid(n, bonds, kw, msg):
     with pytest.raises(abi.HubbardError, match=msg):
         abi.hubbard_create_graph(n, bonds, **kw)
+
+
+def test_tiles_too_small_for_a_hop_are_rejected():
+    """A tile with fewer than two bits beyond its contiguous low bits cannot
+    hold a hopping term on two higher qubits: rejected up front instead of
+    planned."""
+    h = abi.hubbard_create(2, 3, False, False, None, 4.0, None, None, None)
+    try:
+        with pytest.raises(abi.HubbardError) as e:
+            abi.hubbard_set_tiles(h, 3, 3, 2)
+        assert e.value.status == abi.HUBBARD_ERR_ARG
+        abi.hubbard_set_tiles(h, 4, 4, 2)              # two free bits: fine
+        assert len(abi.hubbard_plan_dump(h, 2, 0)) > 1
+        h1 = abi.hubbard_create(1, 1, False, False, None, 4.0, None, None, None)
+        abi.hubbard_set_tiles(h1, 2, 2, 2)             # the tile holds every qubit
+        abi.hubbard_destroy(h1)
+    finally:
+        abi.hubbard_destroy(h)
