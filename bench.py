@@ -73,6 +73,7 @@ def batch_bench(torch, dev, reps=3):
     ws = W.batch(256)
     models = [Hubbard(w.nx, w.ny, **w.kwargs()) for w in ws]
     b = Batch(models, [w.layers for w in ws])
+    tiles_src = sorted({m.tiles_source for m in models})
     theta = torch.tensor(np.concatenate([w.theta for w in ws]), dtype=torch.float64, device=dev)
     ths = [theta[o:o + w.n_params].contiguous() for o, w in zip(b.offsets, ws)]
 
@@ -102,7 +103,9 @@ def batch_bench(torch, dev, reps=3):
             "evals_per_s": n / t_graph, "ms_per_batch_graph": t_graph * 1e3,
             "ms_per_batch_eager": t_eager * 1e3, "ms_per_instance_calls": t_calls * 1e3,
             "evals_per_s_instance_calls": n / t_calls, "speedup_vs_instance_calls": t_calls / t_graph,
-            "qubits": sorted({w.n_qubits for w in ws})}
+            "qubits": sorted({w.n_qubits for w in ws}),
+            "config": {"work_items": b.config[0], "lanes": b.config[1],
+                       "source": b.config_source, "instance_tiles": tiles_src}}
 
 
 def copy_reference(torch, dev, gib=8, reps=3):
@@ -205,7 +208,9 @@ def main():
     n_ham = len(abi.hubbard_plan_dump(m.handle, L, 1))
     n_rev = len(abi.hubbard_plan_dump(m.handle, L, 2))
     n_exp = len(abi.hubbard_plan_dump(m.handle, L, 3))
-    log(f"[bench] {w.name}: passes fwd={n_fwd} ham={n_ham} rev={n_rev} exp={n_exp}")
+    tiles = m.tiles()
+    log(f"[bench] {w.name}: tiles {tiles} ({m.tiles_source}); passes fwd={n_fwd} "
+        f"ham={n_ham} rev={n_rev} exp={n_exp}")
 
     abi.hubbard_set_timing(m.handle, True)
     E = torch.empty(1, dtype=torch.float64, device=dev)
@@ -324,7 +329,9 @@ def main():
         "config": {"workload": w.name, "lattice": f"{w.nx}x{w.ny}",
                    "periodic": [w.periodic_x, w.periodic_y], "U": w.U, "qubits": n,
                    "layers": L, "params": P, "passes": {"fwd": n_fwd, "ham": n_ham,
-                                                        "rev": n_rev, "exp": n_exp}},
+                                                        "rev": n_rev, "exp": n_exp},
+                   "tiles": {"fwd_k": tiles[0], "rev_k": tiles[1], "c": tiles[2],
+                             "source": m.tiles_source}},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["GBs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GBs"] / HBM_PEAK_GBS,
                      "traffic": traffic_bytes(dom["kernel"], w.name),

@@ -32,7 +32,8 @@ EXPORTED = [
     "hubbard_plan_dump", "hubbard_set_tiles", "hubbard_set_timing", "hubbard_phase_ms",
     "hubbard_kernel_ms",
     "hubbard_batch_workspace_size", "energy_grad_batch", "hubbard_get_tiles", "hubbard_tune",
-    "hubbard_batch_cached", "energy_grad_noalloc",
+    "hubbard_batch_cached", "hubbard_batch_set_config", "hubbard_batch_get_config",
+    "energy_grad_noalloc",
 ]
 
 
@@ -107,6 +108,8 @@ def lib() -> ctypes.CDLL:
                                   P(ctypes.c_float)], st),
             "hubbard_kernel_ms": ([vp, i32, P(ctypes.c_float), P(i32)], st),
             "hubbard_batch_cached": ([P(i32)], st),
+            "hubbard_batch_set_config": ([i32, i32], st),
+            "hubbard_batch_get_config": ([P(i32), P(i32)], st),
             "energy_grad_noalloc": ([vp, vp, i32, vp, vp, vp], st),
         }
         for name, (args, res) in sig.items():
@@ -322,11 +325,21 @@ def hubbard_tune(h: int, n_layers: int, theta_dev: int, ws_dev: int, ws_bytes: i
     return [(table[3 * i], table[3 * i + 1], table[3 * i + 2], ms[i]) for i in range(n.value)]
 
 
+def hubbard_batch_set_config(items: int, lanes: int) -> None:
+    _check(lib().hubbard_batch_set_config(int(items), int(lanes)))
+
+
+def hubbard_batch_get_config():
+    """(work items per instance pass, stream lanes) used for newly planned batches."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().hubbard_batch_get_config(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
 def hubbard_batch_cached() -> int:
     n = ctypes.c_int32()
     _check(lib().hubbard_batch_cached(ctypes.byref(n)))
     return n.value
-
 
 
 def energy_grad_noalloc(h: int, theta_dev: int, n_layers: int, E_dev: int, grad_dev: int,

@@ -33,11 +33,17 @@ class Hubbard:
     """One Hubbard model instance (Eq. (1)/(2)/(15)/(16)) and its HVA circuit."""
 
     def __init__(self, nx: int, ny: int, *, periodic_x: bool = False, periodic_y: bool = False,
-                 t=None, U: float = 0.0, V=None, eps=None, groups=None, _handle=None):
+                 t=None, U: float = 0.0, V=None, eps=None, groups=None, tuned: bool = True,
+                 _handle=None):
+        """tuned: apply the autotuner's cached tile configuration for this
+        lattice and GPU when the cache has one (else the library defaults)."""
         self.handle = (_handle if _handle is not None else
                        abi.hubbard_create(nx, ny, periodic_x, periodic_y, t, U, V, eps, groups))
         self.nx, self.ny = nx, ny
         self.periodic_x, self.periodic_y = bool(periodic_x), bool(periodic_y)
+        # the diagonal has eps or V terms besides U (selects the general kernels)
+        self.general = any(a is not None and bool(np.any(np.asarray(a, dtype=np.float64) != 0))
+                           for a in (V, eps))
         q = abi.hubbard_query(self.handle)
         self.n_qubits = q["n_qubits"]
         self.n_bonds = q["n_bonds"]
@@ -46,13 +52,19 @@ class Hubbard:
         self.neel_index = q["neel_index"]
         self._ws = {}
         self._ws_bytes = {}   # (layers, op) -> bytes, per tile configuration
+        self.tiles_gen = 0    # counts tile changes (workspace sizes depend on tiles)
+        self.tiles_source = "library default"
+        if tuned:
+            from . import tune
+            if tune.apply_cached(self) is not None:
+                self.tiles_source = "tune cache"
 
     @classmethod
     def graph(cls, n_sites: int, bonds, *, t=None, U: float = 0.0, V=None, eps=None,
               groups=None, site_spin=None) -> "Hubbard":
         """The model on an arbitrary graph of sites (see hubbard_create_graph)."""
         h = abi.hubbard_create_graph(n_sites, bonds, t, U, V, eps, groups, site_spin)
-        return cls(1, n_sites, _handle=h)
+        return cls(1, n_sites, V=V, eps=eps, tuned=False, _handle=h)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -80,6 +92,12 @@ class Hubbard:
         abi.hubbard_set_tiles(self.handle, fwd_k, rev_k, c)
         self._ws.clear()
         self._ws_bytes.clear()
+        self.tiles_gen += 1
+        self.tiles_source = "set by caller"
+
+    def tiles(self):
+        """(forward k, reverse k, c) currently configured."""
+        return abi.hubbard_get_tiles(self.handle)
 
     def workspace(self, layers: int, op: int, device=None) -> torch.Tensor:
         """Device workspace of at least hubbard_workspace_size bytes; an existing
@@ -187,7 +205,11 @@ class Batch:
         E, g = b.replay()                  # reads theta in place
     """
 
-    def __init__(self, models, layers, device="cuda"):
+    def __init__(self, models, layers, device="cuda", tuned: bool = True):
+        """tuned: plan with the autotuner's cached (work items, lanes,
+        member tiles) for this batch composition and GPU when the cache has
+        them -- the members' tiles are then set as the entry says -- else
+        with the library's defaults and the members as they are."""
         self.models = list(models)
         self.layers = [int(L) for L in layers]
         self.n_params = [m.n_params(L) for m, L in zip(self.models, self.layers)]
@@ -198,14 +220,51 @@ class Batch:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         hs = [m.handle for m in self.models]
-        self.ws = torch.empty(abi.hubbard_batch_workspace_size(hs, self.layers), dtype=torch.uint8,
-                              device=dev)
+        self.ws = None          # sized for the configuration on the first launch
+        self._ws_need = {}      # (config, member tile generations) -> workspace bytes
         self.E = torch.empty(len(self.models), dtype=torch.float64, device=dev)
         self.grad = torch.empty(max(self.total, 1), dtype=torch.float64, device=dev)
         self.theta = torch.zeros(max(self.total, 1), dtype=torch.float64, device=dev)
         self.graph = None
+        self.config = abi.hubbard_batch_get_config()
+        self.member_tiles = "as built"
+        self.config_source = "library default"
+        if tuned:
+            from . import tune
+            ent = tune.lookup_batch(self.models, self.layers)
+            if ent is not None:
+                items, lanes, tiles = ent["best"]
+                tune.apply_member_tiles(self.models, tiles)
+                self.config = (int(items), int(lanes))
+                self.member_tiles = tiles
+                self.config_source = "tune cache"
+
+    def set_config(self, items: int, lanes: int, member_tiles: str | None = None) -> None:
+        """Work items per instance pass and stream lanes for this batch's plan
+        (a new plan on the next call; a captured graph must be re-captured)."""
+        self.config = (int(items), int(lanes))
+        if member_tiles is not None:
+            self.member_tiles = member_tiles
+        self.config_source = "set by caller"
+        self.graph = None
+
+    def workspace(self) -> torch.Tensor:
+        """Device workspace sized for the current configuration (the partial
+        sums grow with the work items); sets that configuration in the
+        library, which plans and keys a batch with the values current at its
+        first call."""
+        abi.hubbard_batch_set_config(*self.config)
+        key = (self.config, tuple(m.tiles_gen for m in self.models))
+        need = self._ws_need.get(key)
+        if need is None:
+            need = self._ws_need[key] = abi.hubbard_batch_workspace_size(
+                [m.handle for m in self.models], self.layers)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self.ws
 
     def _launch(self):
+        self.workspace()
         abi.energy_grad_batch([m.handle for m in self.models], self.theta.data_ptr(),
                               self.offsets, self.layers, self.E.data_ptr(),
                               self.grad.data_ptr(), self.ws.data_ptr(), self.ws.numel(),

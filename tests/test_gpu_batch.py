@@ -120,6 +120,7 @@ def test_batch_error_paths(gpu):
     th = torch.tensor(np.concatenate([w.theta for w in group]), dtype=torch.float64,
                       device="cuda")
     s = torch.cuda.current_stream().cuda_stream
+    b.workspace()
     with pytest.raises(abi.HubbardError) as e:
         abi.energy_grad_batch(hs, th.data_ptr(), b.offsets, b.layers, b.E.data_ptr(),
                               b.grad.data_ptr(), b.ws.data_ptr(), b.ws.numel() - 1, s)

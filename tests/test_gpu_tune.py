@@ -1,5 +1,7 @@
 """Autotuner: every candidate schedule computes the same energy and gradient
-(schedule invariance), and the configuration it leaves is oracle-correct."""
+(schedule invariance), the product path applies the cached winner (models:
+tile sizes; batches: work items and lanes), and the applied configuration
+stays oracle-correct."""
 import numpy as np
 import pytest
 import torch
@@ -7,29 +9,79 @@ import torch
 from oracle import core as oc
 from oracle.model import make_model
 from paper_2408_00836_amd import abi, tune, workloads as W
-from paper_2408_00836_amd.model import Hubbard
+from paper_2408_00836_amd.model import Batch, Hubbard
 
 pytestmark = pytest.mark.gpu
 
 
 def test_tuner_schedules_agree(gpu, tmp_path):
     w = W.random_instance(2, 6, 3, 5, 81, U=4.0, disorder=0.1, eps_width=0.5, V=0.5)
-    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    m = Hubbard(w.nx, w.ny, tuned=False, **w.kwargs())
+    assert m.general
     th = torch.tensor(w.theta, dtype=torch.float64, device="cuda")
-    ent = tune.autotune(m, th, general=True, reps=1, path=str(tmp_path / "t.json"))
+    path = str(tmp_path / "t.json")
+    ent = tune.autotune(m, th, reps=1, path=path)
     assert len(ent["table"]) >= 6
     best = abi.hubbard_get_tiles(m.handle)
     assert list(best) == ent["best"]
     om = make_model(w.nx, w.ny, **w.kwargs())
     E_ref, g_ref = oc.energy_grad(om, w.theta, w.layers)
-    Es, gs = [], []
+    Es = []
     for row in ent["table"]:
         m.set_tiles(row["fwd_k"], row["rev_k"], row["c"])
         E, g = m.energy_grad(th)
         Es.append(E.item())
-        gs.append(g.cpu().numpy())
         assert abs(Es[-1] - E_ref) <= 1e-12 * max(1, abs(E_ref)), row
-        assert np.max(np.abs(gs[-1] - g_ref)) <= 1e-8, row
+        assert np.max(np.abs(g.cpu().numpy() - g_ref)) <= 1e-8, row
     # different schedules sum in different orders: agree to rounding
     assert max(Es) - min(Es) <= 1e-12 * max(1, abs(E_ref))
-    assert tune.lookup(m, w.layers, True, str(tmp_path / "t.json"))["best"] == list(best)
+    assert tune.lookup(m, path)["best"] == list(best)
+
+
+def test_product_path_applies_cached_tiles(gpu, tmp_path, monkeypatch):
+    """A model built after tuning runs the cached best configuration (not the
+    library default) and matches the oracle with it."""
+    w = W.config2(4.0)
+    path = str(tmp_path / "t.json")
+    m0 = Hubbard(w.nx, w.ny, tuned=False, **w.kwargs())
+    th = torch.tensor(w.theta, dtype=torch.float64, device="cuda")
+    ent = tune.autotune(m0, th, reps=1, path=path)
+    # make the cached winner differ from the library default so that the
+    # check below can tell them apart
+    ent["best"] = [11, 10, 4] if ent["best"] == [12, 12, 4] else ent["best"]
+    tune._store(path, tune.model_key(m0), ent)
+    monkeypatch.setenv("HUBVQE_TUNE_CACHE", path)
+    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    assert m.tiles_source == "tune cache"
+    assert list(m.tiles()) == ent["best"]
+    E, g = m.energy_grad(th)
+    E_ref, g_ref = oc.energy_grad(make_model(w.nx, w.ny, **w.kwargs()), w.theta, w.layers)
+    assert abs(E.item() - E_ref) <= 1e-12 * max(1, abs(E_ref))
+    assert np.max(np.abs(g.cpu().numpy() - g_ref)) <= 1e-8
+
+
+def test_batch_tuner_and_cached_config(gpu, tmp_path, monkeypatch):
+    wl = W.batch(24)
+    path = str(tmp_path / "t.json")
+    monkeypatch.setenv("HUBVQE_TUNE_CACHE", path)
+    models = [Hubbard(w.nx, w.ny, **w.kwargs()) for w in wl]
+    layers = [w.layers for w in wl]
+    theta = torch.tensor(np.concatenate([w.theta for w in wl]), dtype=torch.float64,
+                         device="cuda")
+    b = Batch(models, layers)
+    assert b.config_source == "library default"
+    ent = tune.autotune_batch(b, theta, reps=1)
+    assert len(ent["table"]) == (len(tune.BATCH_TILES) * len(tune.BATCH_ITEMS) *
+                                 len(tune.BATCH_LANES))
+    b2 = Batch(models, layers)
+    assert b2.config_source == "tune cache"
+    assert [*b2.config, b2.member_tiles] == ent["best"]
+    E, g = b2.energy_grad(theta)
+    assert abi.hubbard_batch_get_config() == tuple(ent["best"][:2])
+    E, g = E.cpu().numpy(), g.cpu().numpy()
+    for i, w in enumerate(wl):
+        E_ref, g_ref = oc.energy_grad(make_model(w.nx, w.ny, **w.kwargs()), w.theta, w.layers)
+        o = b2.offsets[i]
+        assert abs(E[i] - E_ref) <= 1e-12 * max(1, abs(E_ref)), i
+        assert np.max(np.abs(g[o:o + w.n_params] - g_ref)) <= 1e-8, i
+    abi.hubbard_batch_set_config(32, 4)
