@@ -86,10 +86,16 @@ def test_config2_chain8(gpu, U):
     assert m.energy(th).item() >= E0 - 1e-12   # variational bound
 
 
-def test_config2_adjoint_vs_gpu_fd(gpu):
-    """Adjoint gradient against central finite differences of the GPU energy
-    (h = 1e-5), both against the oracle gradient."""
-    w = W.config2(4.0)
+FD_CONFIGS = {"c1": W.config1, "c2": lambda: W.config2(4.0), "c3": W.config3}
+
+
+@pytest.mark.parametrize("cfg", sorted(FD_CONFIGS))
+def test_adjoint_vs_gpu_fd(gpu, cfg):
+    """The plain form's accuracy: central finite differences of the GPU energy
+    (h = 1e-5, one energy() call per evaluation) against the oracle's adjoint
+    gradient, and the GPU adjoint against both (configs 1, 2 and 3)."""
+    w = FD_CONFIGS[cfg]()
+    say(f"[fd] {w.name}: {2 * w.n_params} energy evaluations")
     m, om = build(w)
     th = th_dev(w, gpu)
     _, g = m.energy_grad(th)
