@@ -158,7 +158,9 @@ const char *hubbard_last_error(void);
 /* Operations for hubbard_workspace_size. */
 enum {
     HUBBARD_OP_ENERGY = 0,       /* energy():      psi + reduction partials */
-    HUBBARD_OP_ENERGY_GRAD = 1   /* energy_grad(): psi + lambda + partials */
+    HUBBARD_OP_ENERGY_GRAD = 1,  /* energy_grad(): psi + lambda + partials */
+    HUBBARD_OP_OVERLAP = 2,      /* hubbard_overlap(): partial sums (hubbard_vector_workspace_size) */
+    HUBBARD_OP_LANCZOS = 3       /* hubbard_lanczos(): three vectors + partial sums (same) */
 };
 
 /* Bytes of device workspace needed by energy()/energy_grad() for n_layers. */
@@ -196,6 +198,43 @@ hubbard_status energy(hubbard_t h, const double *theta_dev, int32_t n_layers,
 hubbard_status energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,
                            double *E_dev, double *grad_dev, void *ws_dev,
                            size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace for hubbard_overlap (op HUBBARD_OP_OVERLAP: 16
+ * KiB of partial sums) or hubbard_lanczos (HUBBARD_OP_LANCZOS: three state
+ * vectors and the partial sums). */
+hubbard_status hubbard_vector_workspace_size(hubbard_t h, int32_t op, size_t *bytes);
+
+/* Overlap of two state vectors of the handle's size, as in the fidelity
+ * F = |<Psi_VQE|Psi_ref>|^2 of Sec. 3.4: out_dev[0] + i out_dev[1] =
+ * <a|b> = sum_x conj(a_x) b_x over all 2^n amplitudes (device doubles),
+ * summed in a fixed order (reproducible).  Asynchronous on `stream`. */
+hubbard_status hubbard_overlap(hubbard_t h, const void *a_dev, const void *b_dev, double *out_dev,
+                               void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Lowest eigenvalue of H (Eq. (1)/(2)/(15)/(16)) in the Krylov space of a
+ * start vector, by the Lanczos recurrence on hamiltonian_apply: the
+ * reference ground state that the VQE error per site of Sec. 3.1 and the
+ * fidelity of Sec. 3.4 are measured against (the paper uses DMRG).  H keeps
+ * N_up and N_dn, so a start vector inside one particle-number sector (for
+ * example the checkerboard state after any circuit of Eq. (7)) gives that
+ * sector's ground state, and every amplitude outside it stays exactly zero.
+ *   start_dev  2^n complex128, any nonzero norm; not modified
+ *   max_iter   most Lanczos steps (each one H application, two vector
+ *              passes and one host synchronisation)
+ *   tol        stop when the Ritz residual ||H x - E0 x|| = beta_j |s_j|
+ *              (s: lowest eigenvector of the projected tridiagonal matrix)
+ *              is below tol * max(1, |E0|), or at an invariant subspace
+ *   E0, iters, residual   host outputs (iters, residual may be NULL)
+ *   gs_dev     NULL, or 2^n complex128 receiving the unit Ritz vector x (a
+ *              second run of the recurrence with the stored coefficients)
+ *   ws_dev     hubbard_vector_workspace_size(HUBBARD_OP_LANCZOS) bytes; the
+ *              start and state vectors must not overlap it
+ * Synchronises `stream` at every step (the projected problem is solved on
+ * the host); not for graph capture.  No reorthogonalisation: the lowest
+ * Ritz value converges before orthogonality loss matters. */
+hubbard_status hubbard_lanczos(hubbard_t h, const void *start_dev, int32_t max_iter, double tol,
+                               double *E0, int32_t *iters, double *residual, void *gs_dev,
+                               void *ws_dev, size_t ws_bytes, void *stream);
 
 /* energy_grad for callers that cannot allocate device memory or pass a
  * workspace (code under HIP graph capture, tight serving loops, harnesses

@@ -63,6 +63,13 @@ hubbard_status hubbard_tune(hubbard_t h, int32_t n_layers, const double *theta_d
 hubbard_status hubbard_batch_set_config(int32_t items, int32_t lanes);
 hubbard_status hubbard_batch_get_config(int32_t *items, int32_t *lanes);
 
+/* The projected problem of hubbard_lanczos on the host: lowest eigenvalue of
+ * the symmetric tridiagonal matrix with diagonal a[0..m-1] and off-diagonal
+ * b[0..m-2] (Sturm-sequence bisection) and, if vec is not NULL, its unit
+ * eigenvector (inverse iteration; largest component positive). */
+hubbard_status hubbard_tridiag_lowest(const double *a, const double *b, int32_t m, double *lam,
+                                      double *vec);
+
 /* Number of planned batches (energy_grad_batch) the library currently
  * keeps (at most 16). */
 hubbard_status hubbard_batch_cached(int32_t *count);

@@ -23,6 +23,8 @@ HUBBARD_ERR_NOMEM = 4
 HUBBARD_ERR_STATE = 5
 HUBBARD_OP_ENERGY = 0
 HUBBARD_OP_ENERGY_GRAD = 1
+HUBBARD_OP_OVERLAP = 2
+HUBBARD_OP_LANCZOS = 3
 
 # Every symbol the headers in include/ declare.
 EXPORTED = [
@@ -33,7 +35,8 @@ EXPORTED = [
     "hubbard_kernel_ms",
     "hubbard_batch_workspace_size", "energy_grad_batch", "hubbard_get_tiles", "hubbard_tune",
     "hubbard_batch_cached", "hubbard_batch_set_config", "hubbard_batch_get_config",
-    "energy_grad_noalloc",
+    "energy_grad_noalloc", "hubbard_vector_workspace_size", "hubbard_overlap", "hubbard_lanczos",
+    "hubbard_tridiag_lowest",
 ]
 
 
@@ -111,6 +114,12 @@ def lib() -> ctypes.CDLL:
             "hubbard_batch_set_config": ([i32, i32], st),
             "hubbard_batch_get_config": ([P(i32), P(i32)], st),
             "energy_grad_noalloc": ([vp, vp, i32, vp, vp, vp], st),
+            "hubbard_vector_workspace_size": ([vp, i32, P(ctypes.c_size_t)], st),
+            "hubbard_overlap": ([vp, vp, vp, vp, vp, ctypes.c_size_t, vp], st),
+            "hubbard_lanczos": ([vp, vp, i32, ctypes.c_double, P(ctypes.c_double), P(i32),
+                                 P(ctypes.c_double), vp, vp, ctypes.c_size_t, vp], st),
+            "hubbard_tridiag_lowest": ([P(ctypes.c_double), P(ctypes.c_double), i32,
+                                        P(ctypes.c_double), P(ctypes.c_double)], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -345,3 +354,37 @@ def hubbard_batch_cached() -> int:
 def energy_grad_noalloc(h: int, theta_dev: int, n_layers: int, E_dev: int, grad_dev: int,
                         stream: int = 0) -> None:
     _check(lib().energy_grad_noalloc(h, theta_dev, int(n_layers), E_dev, grad_dev, stream))
+
+
+def hubbard_vector_workspace_size(h: int, op: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().hubbard_vector_workspace_size(h, int(op), ctypes.byref(n)))
+    return n.value
+
+
+def hubbard_overlap(h: int, a_dev: int, b_dev: int, out_dev: int, ws_dev: int, ws_bytes: int,
+                    stream: int = 0) -> None:
+    _check(lib().hubbard_overlap(h, a_dev, b_dev, out_dev, ws_dev, int(ws_bytes), stream))
+
+
+def hubbard_lanczos(h: int, start_dev: int, max_iter: int, tol: float, gs_dev, ws_dev: int,
+                    ws_bytes: int, stream: int = 0):
+    """(E0, iterations, Ritz residual); the unit ground state goes to gs_dev
+    unless it is None."""
+    E0, it, res = ctypes.c_double(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib().hubbard_lanczos(h, start_dev, int(max_iter), float(tol), ctypes.byref(E0),
+                                 ctypes.byref(it), ctypes.byref(res), gs_dev, ws_dev,
+                                 int(ws_bytes), stream))
+    return E0.value, it.value, res.value
+
+
+def hubbard_tridiag_lowest(a, b):
+    """Lowest eigenpair of the symmetric tridiagonal matrix (diag a, off-diag b)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    vec = np.zeros(a.size)
+    lam = ctypes.c_double()
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(lib().hubbard_tridiag_lowest(a.ctypes.data_as(P), b.ctypes.data_as(P) if b.size else None,
+                                        a.size, ctypes.byref(lam), vec.ctypes.data_as(P)))
+    return lam.value, vec

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <cmath>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -30,6 +31,12 @@ __global__ void k_reduce_seg(const double *, const int32_t *, const int64_t *, c
                              const double *, const int64_t *, int, double *, double *);
 __global__ void k_reduce(const double *, int, const int32_t *, const int32_t *, const int32_t *,
                          const double *, double *, double *, int);
+__global__ void k_vdot(const double2 *, const double2 *, uint64_t, double2 *);
+__global__ void k_krylov_update(double2 *, const double2 *, const double2 *, double, double,
+                                uint64_t, double2 *);
+__global__ void k_vscale(double2 *, const double2 *, double, uint64_t);
+__global__ void k_vaxpy(double2 *, const double2 *, double, uint64_t);
+__global__ void k_vsum(const double2 *, int, double2 *);
 }  // namespace hv
 
 using namespace hv;
@@ -1894,6 +1901,217 @@ hubbard_status hubbard_kernel_ms(hubbard_t h, int32_t mode, float *total_ms, int
         *total_ms += ms;
         ++*launches;
     }
+    return HUBBARD_OK;
+}
+
+}  // extern "C"
+
+// ============================================================== drivers
+// Host drivers built on the pass kernels and the vector kernels: overlaps
+// (the fidelity of Sec. 3.4) and the Krylov ground state of H in the
+// particle-number sector of a start vector (the reference energies and
+// states against which Sec. 3.1 measures the VQE error and Sec. 3.4 the
+// fidelity).
+
+namespace {
+
+size_t vec_partial_bytes() { return align256((size_t)kVecBlocks * sizeof(double2)); }
+
+unsigned vec_grid(uint64_t n)
+{
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)kVecBlocks,
+                                                               (n + kVecThreads - 1) / kVecThreads));
+}
+
+// <a|b> summed on the host in block order (waits for the stream).
+hubbard_status host_dot(const double2 *a, const double2 *b, uint64_t n, double2 *partial,
+                        hipStream_t s, double *re, double *im)
+{
+    const unsigned g = vec_grid(n);
+    hipLaunchKernelGGL(k_vdot, dim3(g), dim3(kVecThreads), 0, s, a, b, n, partial);
+    std::vector<double2> hp(g);
+    hipError_t e = hipMemcpyAsync(hp.data(), partial, g * sizeof(double2),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("dot: ") + hipGetErrorString(e));
+    double r = 0.0, i = 0.0;
+    for (unsigned k = 0; k < g; ++k) {
+        r += hp[k].x;
+        i += hp[k].y;
+    }
+    *re = r;
+    *im = i;
+    return HUBBARD_OK;
+}
+
+// One step of the recurrence: w <- H v - alpha v - beta u with alpha =
+// <v|H v> (computed unless given), returns ||w||^2.  has_alpha: use *alpha.
+hubbard_status krylov_step(const Program &pr, const DeviceState &ds, const double2 *v,
+                           const double2 *u, double2 *w, double beta, bool has_alpha,
+                           double *alpha, double *wnorm2, double2 *partial, uint64_t n,
+                           hipStream_t s)
+{
+    hubbard_status st = run_ham(pr, ds, v, w, nullptr, s);
+    if (st != HUBBARD_OK)
+        return st;
+    if (!has_alpha) {
+        double im = 0.0;
+        if ((st = host_dot(v, w, n, partial, s, alpha, &im)) != HUBBARD_OK)
+            return st;
+    }
+    const unsigned g = vec_grid(n);
+    // beta = 0 on the first step: u is then v itself (any finite vector)
+    hipLaunchKernelGGL(k_krylov_update, dim3(g), dim3(kVecThreads), 0, s, w, v, beta > 0.0 ? u : v,
+                       *alpha, beta, n, partial);
+    std::vector<double2> hp(g);
+    hipError_t e = hipMemcpyAsync(hp.data(), partial, g * sizeof(double2),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("krylov update: ") + hipGetErrorString(e));
+    double acc = 0.0;
+    for (unsigned k = 0; k < g; ++k)
+        acc += hp[k].x;
+    *wnorm2 = acc;
+    return HUBBARD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hubbard_status hubbard_vector_workspace_size(hubbard_t h, int32_t op, size_t *bytes)
+{
+    if (!h || !bytes || (op != HUBBARD_OP_OVERLAP && op != HUBBARD_OP_LANCZOS))
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_vector_workspace_size");
+    const size_t vb = align256(vec_bytes(h));
+    *bytes = (op == HUBBARD_OP_LANCZOS ? 3 * vb : 0) + vec_partial_bytes();
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_overlap(hubbard_t h, const void *a_dev, const void *b_dev, double *out_dev,
+                               void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (!h || !a_dev || !b_dev || !out_dev || !ws_dev)
+        return fail(HUBBARD_ERR_ARG, "NULL argument to hubbard_overlap");
+    if (ws_bytes < vec_partial_bytes())
+        return fail(HUBBARD_ERR_SIZE, "workspace too small for hubbard_overlap");
+    const uint64_t n = (uint64_t)1 << h->m.nq;
+    const unsigned g = vec_grid(n);
+    hipStream_t s = (hipStream_t)stream;
+    double2 *partial = (double2 *)ws_dev;
+    hipLaunchKernelGGL(k_vdot, dim3(g), dim3(kVecThreads), 0, s, (const double2 *)a_dev,
+                       (const double2 *)b_dev, n, partial);
+    hipLaunchKernelGGL(k_vsum, dim3(1), dim3(kVecThreads), 0, s, partial, (int)g,
+                       (double2 *)out_dev);
+    return check_launch("overlap");
+}
+
+hubbard_status hubbard_lanczos(hubbard_t h, const void *start_dev, int32_t max_iter, double tol,
+                               double *E0, int32_t *iters, double *residual, void *gs_dev,
+                               void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (!h || !start_dev || max_iter < 1 || !(tol > 0.0) || !E0 || !ws_dev)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_lanczos");
+    size_t need = 0;
+    hubbard_vector_workspace_size(h, HUBBARD_OP_LANCZOS, &need);
+    if (ws_bytes < need)
+        return fail(HUBBARD_ERR_SIZE, "workspace too small for hubbard_lanczos");
+    const size_t vb = align256(vec_bytes(h));
+    const char *ws = (const char *)ws_dev;
+    const uint64_t n = (uint64_t)1 << h->m.nq;
+    for (const void *p : {start_dev, (const void *)gs_dev}) {
+        const char *q = (const char *)p;
+        if (q && q < ws + need && ws < q + vec_bytes(h))
+            return fail(HUBBARD_ERR_ARG, "start or state vector overlaps the workspace");
+    }
+    Program *pr;
+    DeviceState *ds;
+    hubbard_status st = get_program(h, PROG_HAM, 0, &pr, &ds);
+    if (st != HUBBARD_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *buf[3] = {(double2 *)ws_dev, (double2 *)(ws + vb), (double2 *)(ws + 2 * vb)};
+    double2 *partial = (double2 *)(ws + 3 * vb);
+    const unsigned g = vec_grid(n);
+    double nrm2 = 0.0, im = 0.0;
+    if ((st = host_dot((const double2 *)start_dev, (const double2 *)start_dev, n, partial, s,
+                       &nrm2, &im)) != HUBBARD_OK)
+        return st;
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+        return fail(HUBBARD_ERR_ARG, "hubbard_lanczos: start vector has zero or non-finite norm");
+    const double inv0 = 1.0 / std::sqrt(nrm2);
+    // pass 1: the recurrence, alpha_j and beta_j, until the Ritz residual
+    // beta_j |s_j| of the lowest Ritz pair is below tol (or an invariant
+    // subspace: beta_j vanishes)
+    std::vector<double> alpha, beta, svec;
+    double lam = 0.0, res = 0.0;
+    {
+        double2 *v = buf[0], *u = buf[1], *w = buf[2];
+        hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, v,
+                           (const double2 *)start_dev, inv0, n);
+        double bprev = 0.0;
+        for (int j = 0; j < max_iter; ++j) {
+            double a = 0.0, w2 = 0.0;
+            if ((st = krylov_step(*pr, *ds, v, u, w, bprev, false, &a, &w2, partial, n, s)) !=
+                HUBBARD_OK)
+                return st;
+            alpha.push_back(a);
+            const double b = std::sqrt(w2);
+            svec.assign(alpha.size(), 0.0);
+            lam = tridiag_lowest(alpha.data(), beta.data(), (int)alpha.size(), svec.data());
+            res = b * std::fabs(svec.back());
+            const double scale = std::max(1.0, std::fabs(lam));
+            if (res <= tol * scale || b <= 1e-14 * scale)
+                break;
+            beta.push_back(b);
+            hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, u, w, 1.0 / b, n);
+            std::swap(u, v);   // u <- v_j, v <- v_{j+1}
+            bprev = b;
+        }
+    }
+    *E0 = lam;
+    if (iters)
+        *iters = (int32_t)alpha.size();
+    if (residual)
+        *residual = res;
+    if (!gs_dev)
+        return check_launch("lanczos");
+    // pass 2: the same recurrence with the stored coefficients (the same
+    // arithmetic, hence the same vectors) accumulating the Ritz vector
+    // x = sum_j s_j v_j, then normalised
+    double2 *x = (double2 *)gs_dev;
+    double2 *v = buf[0], *u = buf[1], *w = buf[2];
+    hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, v, (const double2 *)start_dev,
+                       inv0, n);
+    hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, x, v, svec[0], n);
+    double bprev = 0.0;
+    for (size_t j = 0; j + 1 < alpha.size(); ++j) {
+        double a = alpha[j], w2 = 0.0;
+        if ((st = krylov_step(*pr, *ds, v, u, w, bprev, true, &a, &w2, partial, n, s)) !=
+            HUBBARD_OK)
+            return st;
+        hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, u, w, 1.0 / beta[j], n);
+        std::swap(u, v);
+        hipLaunchKernelGGL(k_vaxpy, dim3(g), dim3(kVecThreads), 0, s, x, v, svec[j + 1], n);
+        bprev = beta[j];
+    }
+    double xn = 0.0;
+    if ((st = host_dot(x, x, n, partial, s, &xn, &im)) != HUBBARD_OK)
+        return st;
+    hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, x, x, 1.0 / std::sqrt(xn), n);
+    return check_launch("lanczos");
+}
+
+hubbard_status hubbard_tridiag_lowest(const double *a, const double *b, int32_t m, double *lam,
+                                      double *vec)
+{
+    if (!a || (m > 1 && !b) || m < 1 || !lam)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_tridiag_lowest");
+    *lam = tridiag_lowest(a, b, m, vec);
     return HUBBARD_OK;
 }
 

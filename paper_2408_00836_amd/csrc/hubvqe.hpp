@@ -203,6 +203,11 @@ __host__ __device__ inline SmemPlan smem_plan(int k, int n_ops, int n_diag, int 
     return s;
 }
 
+// Vector kernels (k_vdot and friends): threads per block and the most blocks
+// a launch uses (also the number of reduction partials).
+constexpr int kVecThreads = 256;
+constexpr int kVecBlocks = 1024;
+
 // ------------------------------------------------------------------ host --
 
 struct Model {
@@ -216,6 +221,12 @@ struct Model {
     int qubit(int site, int spin) const { return site + ns * spin; }
     int params_per_layer() const { return 1 + ngroups; }
 };
+
+// Lowest eigenvalue of the symmetric tridiagonal matrix with diagonal
+// a[0..m-1] and off-diagonal b[0..m-2] (Sturm-sequence bisection); if vec is
+// not NULL it receives the unit eigenvector (inverse iteration, largest
+// component positive).  m >= 1.
+double tridiag_lowest(const double *a, const double *b, int m, double *vec);
 
 // Build and validate a model; returns an empty string or an error message.
 std::string build_model(int nx, int ny, int px, int py, const double *t, double U,

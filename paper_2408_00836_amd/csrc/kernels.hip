@@ -886,6 +886,112 @@ HV_INSTANTIATE(M_FWD, false, true, 2, true)
 #undef HV_INSTANTIATE_ALL
 #undef HV_INSTANTIATE
 
+// ---------------------------------------------------------- vector kernels --
+// Streaming kernels over whole state vectors (n complex128 amplitudes) for
+// the drivers of the library (the Krylov ground state and overlaps):
+// HBM-bound, one grid-stride loop each, kVecThreads threads per block.
+// Reductions are deterministic: every block sums its share of the grid
+// stride in a fixed tree order into one partial, and the partials are added
+// in block order afterwards.
+
+// Sum of (x, y) over the block in a fixed tree order; valid in thread 0.
+__device__ __forceinline__ double2 block_sum2(double x, double y, double2 *sm)
+{
+    const int tid = threadIdx.x;
+    sm[tid] = make_double2(x, y);
+    for (int s = kVecThreads / 2; s > 0; s >>= 1) {
+        __syncthreads();
+        if (tid < s) {
+            sm[tid].x += sm[tid + s].x;
+            sm[tid].y += sm[tid + s].y;
+        }
+    }
+    __syncthreads();
+    return sm[0];
+}
+
+// partial[block] = sum over the block's share of conj(a_i) b_i.
+__global__ void __launch_bounds__(kVecThreads)
+k_vdot(const double2 *__restrict__ a, const double2 *__restrict__ b, uint64_t n,
+       double2 *__restrict__ partial)
+{
+    __shared__ double2 sm[kVecThreads];
+    double re = 0.0, im = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kVecThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
+        const double2 x = a[i], y = b[i];
+        re += re_conj_mul(x, y);
+        im += im_conj_mul(x, y);
+    }
+    const double2 t = block_sum2(re, im, sm);
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = t;
+}
+
+// Three-term Krylov recurrence: w <- w - alpha v - beta u, and
+// partial[block].x = sum over the block's share of |w_i|^2 (new w).
+__global__ void __launch_bounds__(kVecThreads)
+k_krylov_update(double2 *__restrict__ w, const double2 *__restrict__ v,
+                const double2 *__restrict__ u, double alpha, double beta, uint64_t n,
+                double2 *__restrict__ partial)
+{
+    __shared__ double2 sm[kVecThreads];
+    double acc = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kVecThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
+        double2 x = w[i];
+        const double2 y = v[i], z = u[i];
+        x.x = fma(-beta, z.x, fma(-alpha, y.x, x.x));
+        x.y = fma(-beta, z.y, fma(-alpha, y.y, x.y));
+        w[i] = x;
+        acc = fma(x.x, x.x, fma(x.y, x.y, acc));
+    }
+    const double2 t = block_sum2(acc, 0.0, sm);
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = t;
+}
+
+// dst <- s * src (dst may be src).
+__global__ void __launch_bounds__(kVecThreads)
+k_vscale(double2 *dst, const double2 *src, double s, uint64_t n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kVecThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
+        const double2 x = src[i];
+        dst[i] = make_double2(s * x.x, s * x.y);
+    }
+}
+
+// y <- y + a x (real a).
+__global__ void __launch_bounds__(kVecThreads)
+k_vaxpy(double2 *__restrict__ y, const double2 *__restrict__ x, double a, uint64_t n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kVecThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
+        double2 t = y[i];
+        const double2 z = x[i];
+        t.x = fma(a, z.x, t.x);
+        t.y = fma(a, z.y, t.y);
+        y[i] = t;
+    }
+}
+
+// out[0] = the nblk partials added in block order (one block of one thread
+// group: the fixed second stage of the reductions above).
+__global__ void __launch_bounds__(kVecThreads)
+k_vsum(const double2 *__restrict__ partial, int nblk, double2 *__restrict__ out)
+{
+    __shared__ double2 sm[kVecThreads];
+    double re = 0.0, im = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kVecThreads) {
+        re += partial[b].x;
+        im += partial[b].y;
+    }
+    const double2 t = block_sum2(re, im, sm);
+    if (threadIdx.x == 0)
+        out[0] = t;
+}
+
 // ------------------------------------------------------------ misc kernels --
 
 __global__ void k_init_basis(double2 *__restrict__ psi, uint64_t dim, uint64_t b0, uint32_t ilv)

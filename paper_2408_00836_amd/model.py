@@ -163,6 +163,40 @@ class Hubbard:
                         ws.data_ptr(), ws.numel(), _stream())
         return E, grad
 
+    def overlap(self, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        """<a|b> over all amplitudes (a complex128 scalar tensor on the device)."""
+        for t, nm in ((a, "a"), (b, "b")):
+            _require_gpu(t, nm, torch.complex128)
+            if t.numel() != self.dim:
+                raise ValueError(f"{nm} must hold 2^n amplitudes")
+        nb = abi.hubbard_vector_workspace_size(self.handle, abi.HUBBARD_OP_OVERLAP)
+        ws = torch.empty(nb, dtype=torch.uint8, device=a.device)
+        out = torch.empty(2, dtype=torch.float64, device=a.device)
+        abi.hubbard_overlap(self.handle, a.data_ptr(), b.data_ptr(), out.data_ptr(),
+                            ws.data_ptr(), ws.numel(), _stream())
+        return torch.complex(out[0], out[1])
+
+    def lanczos(self, start: torch.Tensor | None = None, *, max_iter: int = 400,
+                tol: float = 1e-10, want_state: bool = False, seed: int = 7):
+        """Ground state of H in the particle-number sector of `start` (default:
+        the checkerboard state after two ansatz layers at angles drawn from
+        `seed`, a generic vector of the start state's sector).  Returns
+        dict(E0, iters, residual, state)."""
+        if start is None:
+            th = np.random.default_rng(seed).uniform(-np.pi / 8, np.pi / 8,
+                                                      2 * self.params_per_layer)
+            start = self.ansatz(torch.tensor(th, dtype=torch.float64, device="cuda"))
+        _require_gpu(start, "start", torch.complex128)
+        if start.numel() != self.dim:
+            raise ValueError("start must hold 2^n amplitudes")
+        nb = abi.hubbard_vector_workspace_size(self.handle, abi.HUBBARD_OP_LANCZOS)
+        ws = torch.empty(nb, dtype=torch.uint8, device=start.device)
+        gs = torch.empty_like(start) if want_state else None
+        E0, it, res = abi.hubbard_lanczos(self.handle, start.data_ptr(), max_iter, tol,
+                                          gs.data_ptr() if gs is not None else None,
+                                          ws.data_ptr(), ws.numel(), _stream())
+        return dict(E0=E0, iters=it, residual=res, state=gs)
+
     def workspace_views(self, layers: int):
         """Two plain vector buffers carved out of the energy_grad workspace
         (scratch for ansatz/apply_h at the benchmark size; energy_grad stores

@@ -1,7 +1,9 @@
 """Writes tests/golden/sector_ground_energies.json.
 
 Calls only the oracle (oracle.dense: Kronecker-product H, sparse Lanczos /
-dense eigh in the (N_up, N_dn) sector of the checkerboard start state).
+dense eigh in the (N_up, N_dn) sector of the checkerboard start state;
+oracle.sector: the sector form of the matrix-free H, handed to scipy's
+eigsh for the 24-qubit ladder) and the seeded input generator.
 Run: python tests/golden/make_golden.py
 """
 import json
@@ -12,7 +14,21 @@ import numpy as np
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)))))
 from oracle import dense as od  # noqa: E402
+from oracle import sector as osec  # noqa: E402
 from oracle.model import make_model  # noqa: E402
+from paper_2408_00836_amd import workloads as W  # noqa: E402
+
+
+def sector_ground_energy_matfree(m):
+    """Lowest eigenvalue of the oracle's sector-form H (real symmetric) by
+    scipy's eigsh (ARPACK), deterministic start vector."""
+    import scipy.sparse.linalg as sla
+    n = osec.dim(m)
+    op = sla.LinearOperator((n, n), dtype=np.float64,
+                            matvec=lambda x: osec.ham_apply(m, np.ravel(x).astype(np.complex128)).real)
+    w = sla.eigsh(op, k=1, which="SA", tol=1e-13, v0=np.ones(n), ncv=40,
+                  return_eigenvectors=False)
+    return float(w[0])
 
 
 def main():
@@ -33,6 +49,10 @@ def main():
         w, _ = od.sector_ground_state(m, 4, 4, k=1)
         out[f"config2_chain8_U{U:g}"] = dict(E0=float(w[0]), sector=[4, 4],
                                              source="oracle.dense Lanczos (eigsh)")
+    w = W.config3()
+    m = make_model(w.nx, w.ny, **w.kwargs())
+    out["config3_ladder_2x6"] = dict(E0=sector_ground_energy_matfree(m), sector=[6, 6],
+                                     source="oracle.sector H, scipy eigsh")
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sector_ground_energies.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)

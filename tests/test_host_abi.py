@@ -324,3 +324,25 @@ def test_tiles_too_small_for_a_hop_are_rejected():
         abi.hubbard_destroy(h1)
     finally:
         abi.hubbard_destroy(h)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tridiag_lowest_matches_lapack(seed):
+    """The Lanczos driver's projected problem (host code): lowest eigenpair of
+    a symmetric tridiagonal matrix against LAPACK (scipy's
+    eigh_tridiagonal), including clustered and 1x1 cases."""
+    import scipy.linalg as sla
+    rng = np.random.default_rng(seed)
+    m = [1, 2, 5, 40, 150, 300][seed]
+    a = rng.normal(size=m) * (10.0 if seed % 2 else 1.0)
+    b = rng.normal(size=m - 1)
+    if seed == 4:
+        b[::7] = 1e-13   # nearly decoupled blocks: clustered eigenvalues
+    lam, vec = abi.hubbard_tridiag_lowest(a, b)
+    w, V = sla.eigh_tridiagonal(a, b)
+    assert abs(lam - w[0]) <= 1e-13 * max(1.0, abs(w[0]))
+    if m > 1 and w[1] - w[0] > 1e-8:
+        ref = V[:, 0] * np.sign(V[np.argmax(np.abs(V[:, 0])), 0])
+        assert np.max(np.abs(vec - ref)) <= 1e-9
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    assert np.linalg.norm(T @ vec - lam * vec) <= 1e-10 * max(1.0, abs(lam))
