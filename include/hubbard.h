@@ -236,6 +236,53 @@ hubbard_status hubbard_lanczos(hubbard_t h, const void *start_dev, int32_t max_i
                                double *E0, int32_t *iters, double *residual, void *gs_dev,
                                void *ws_dev, size_t ws_bytes, void *stream);
 
+/* The VQE optimisation of Sec. 2.1: minimise E(theta) = <psi(theta)|H|psi(theta)>
+ * by L-BFGS (limited-memory BFGS, strong-Wolfe line search) on energy_grad
+ * evaluations, stopping when the energy changes by less than e_tol between
+ * consecutive iterates, the gradient's Euclidean norm is below g_tol, or
+ * after max_steps iterations (the paper: 1e-7, 1e-6, 1000).  The paper runs
+ * ten optimisations from random starts and keeps the lowest energy; here
+ * n_starts > 1 advances that many independent optimisations of the same
+ * model in lockstep, every round one energy_grad_batch launch for all of
+ * them (finished ones are evaluated at their final point).
+ *   theta_dev   n_starts * n_layers * params_per_layer doubles (device):
+ *               in: the start points, out: each optimisation's final iterate
+ *   opts        NULL: the paper's settings (history 10)
+ *   results     n_starts entries (host): final energy, gradient norm,
+ *               iterations, evaluations, stopping reason
+ *   ws_dev      hubbard_vqe_workspace_size bytes
+ * Synchronises `stream` at every round (the optimiser runs on the host). */
+typedef struct {
+    int32_t max_steps;   /* iterations (1000) */
+    int32_t history;     /* (s, y) pairs kept (10) */
+    double e_tol;        /* |E_k - E_{k-1}| (1e-7) */
+    double g_tol;        /* ||grad||_2 (1e-6) */
+} hubbard_vqe_opts;
+
+enum {
+    HUBBARD_VQE_RUNNING = 0,
+    HUBBARD_VQE_ENERGY_TOL = 1,
+    HUBBARD_VQE_GRAD_TOL = 2,
+    HUBBARD_VQE_MAX_STEPS = 3,
+    HUBBARD_VQE_LINE_SEARCH = 4,   /* no acceptable step: a local minimum to rounding */
+    HUBBARD_VQE_NOT_FINITE = 5
+};
+
+typedef struct {
+    double E;            /* energy at the final iterate */
+    double grad_norm;    /* its gradient's Euclidean norm */
+    int32_t steps;       /* L-BFGS iterations */
+    int32_t evals;       /* energy+gradient evaluations */
+    int32_t reason;      /* HUBBARD_VQE_* */
+    int32_t pad;
+} hubbard_vqe_result;
+
+hubbard_status hubbard_vqe_workspace_size(hubbard_t h, int32_t n_layers, int32_t n_starts,
+                                          size_t *bytes);
+hubbard_status hubbard_vqe(hubbard_t h, int32_t n_layers, int32_t n_starts, double *theta_dev,
+                           const hubbard_vqe_opts *opts, hubbard_vqe_result *results,
+                           void *ws_dev, size_t ws_bytes, void *stream);
+
 /* energy_grad for callers that cannot allocate device memory or pass a
  * workspace (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc): the same kernels and results as energy_grad, with

@@ -70,6 +70,18 @@ hubbard_status hubbard_batch_get_config(int32_t *items, int32_t *lanes);
 hubbard_status hubbard_tridiag_lowest(const double *a, const double *b, int32_t m, double *lam,
                                       double *vec);
 
+/* hubbard_vqe's optimiser on the host, driven by the caller's evaluations
+ * (reverse communication): create it at x0, evaluate f and its gradient at
+ * the point it returns, tell it, and repeat while *state is 0; the final
+ * iterate is returned once *state is a HUBBARD_VQE_* reason. */
+typedef struct hubbard_lbfgs *hubbard_lbfgs_t;
+hubbard_status hubbard_lbfgs_create(const double *x0, int32_t n, const hubbard_vqe_opts *opts,
+                                    hubbard_lbfgs_t *out);
+hubbard_status hubbard_lbfgs_tell(hubbard_lbfgs_t L, double f, const double *g, int32_t *state,
+                                  double *x_next);
+hubbard_status hubbard_lbfgs_result(hubbard_lbfgs_t L, hubbard_vqe_result *res);
+void hubbard_lbfgs_destroy(hubbard_lbfgs_t L);
+
 /* Number of planned batches (energy_grad_batch) the library currently
  * keeps (at most 16). */
 hubbard_status hubbard_batch_cached(int32_t *count);

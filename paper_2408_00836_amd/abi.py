@@ -36,8 +36,24 @@ EXPORTED = [
     "hubbard_batch_workspace_size", "energy_grad_batch", "hubbard_get_tiles", "hubbard_tune",
     "hubbard_batch_cached", "hubbard_batch_set_config", "hubbard_batch_get_config",
     "energy_grad_noalloc", "hubbard_vector_workspace_size", "hubbard_overlap", "hubbard_lanczos",
-    "hubbard_tridiag_lowest",
+    "hubbard_tridiag_lowest", "hubbard_vqe_workspace_size", "hubbard_vqe", "hubbard_lbfgs_create",
+    "hubbard_lbfgs_tell", "hubbard_lbfgs_result", "hubbard_lbfgs_destroy",
 ]
+
+
+class hubbard_vqe_opts(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_int32), ("history", ctypes.c_int32),
+                ("e_tol", ctypes.c_double), ("g_tol", ctypes.c_double)]
+
+
+class hubbard_vqe_result(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("grad_norm", ctypes.c_double),
+                ("steps", ctypes.c_int32), ("evals", ctypes.c_int32),
+                ("reason", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+VQE_REASONS = {0: "running", 1: "energy tolerance", 2: "gradient tolerance", 3: "max steps",
+               4: "line search", 5: "not finite"}
 
 
 class HubbardError(RuntimeError):
@@ -120,6 +136,14 @@ def lib() -> ctypes.CDLL:
                                  P(ctypes.c_double), vp, vp, ctypes.c_size_t, vp], st),
             "hubbard_tridiag_lowest": ([P(ctypes.c_double), P(ctypes.c_double), i32,
                                         P(ctypes.c_double), P(ctypes.c_double)], st),
+            "hubbard_vqe_workspace_size": ([vp, i32, i32, P(ctypes.c_size_t)], st),
+            "hubbard_vqe": ([vp, i32, i32, vp, P(hubbard_vqe_opts), P(hubbard_vqe_result), vp,
+                             ctypes.c_size_t, vp], st),
+            "hubbard_lbfgs_create": ([P(ctypes.c_double), i32, P(hubbard_vqe_opts), P(vp)], st),
+            "hubbard_lbfgs_tell": ([vp, ctypes.c_double, P(ctypes.c_double), P(i32),
+                                    P(ctypes.c_double)], st),
+            "hubbard_lbfgs_result": ([vp, P(hubbard_vqe_result)], st),
+            "hubbard_lbfgs_destroy": ([vp], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -388,3 +412,70 @@ def hubbard_tridiag_lowest(a, b):
     _check(lib().hubbard_tridiag_lowest(a.ctypes.data_as(P), b.ctypes.data_as(P) if b.size else None,
                                         a.size, ctypes.byref(lam), vec.ctypes.data_as(P)))
     return lam.value, vec
+
+
+def _opts(opts):
+    if opts is None:
+        return None
+    o = hubbard_vqe_opts()
+    o.max_steps = int(opts.get("max_steps", 1000))
+    o.history = int(opts.get("history", 10))
+    o.e_tol = float(opts.get("e_tol", 1e-7))
+    o.g_tol = float(opts.get("g_tol", 1e-6))
+    return o
+
+
+def _result(r):
+    return dict(E=r.E, grad_norm=r.grad_norm, steps=r.steps, evals=r.evals, reason=r.reason,
+                why=VQE_REASONS.get(r.reason, "?"))
+
+
+def hubbard_vqe_workspace_size(h: int, n_layers: int, n_starts: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().hubbard_vqe_workspace_size(h, int(n_layers), int(n_starts), ctypes.byref(n)))
+    return n.value
+
+
+def hubbard_vqe(h: int, n_layers: int, n_starts: int, theta_dev: int, ws_dev: int, ws_bytes: int,
+                stream: int = 0, opts: dict | None = None):
+    """Runs the optimisations in place on theta_dev; returns one result dict per start."""
+    res = (hubbard_vqe_result * int(n_starts))()
+    o = _opts(opts)
+    _check(lib().hubbard_vqe(h, int(n_layers), int(n_starts), theta_dev,
+                             ctypes.byref(o) if o is not None else None, res, ws_dev,
+                             int(ws_bytes), stream))
+    return [_result(r) for r in res]
+
+
+class Lbfgs:
+    """The library's optimiser driven from Python (reverse communication):
+    x = opt.start; loop: f, g = F(x); state, x = opt.tell(f, g)."""
+
+    def __init__(self, x0, opts: dict | None = None):
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        self.n = x0.size
+        self.start = x0.copy()
+        self._h = ctypes.c_void_p()
+        o = _opts(opts)
+        _check(lib().hubbard_lbfgs_create(x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          self.n, ctypes.byref(o) if o is not None else None,
+                                          ctypes.byref(self._h)))
+
+    def tell(self, f: float, g):
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        x = np.zeros(self.n)
+        st = ctypes.c_int32()
+        P = ctypes.POINTER(ctypes.c_double)
+        _check(lib().hubbard_lbfgs_tell(self._h, float(f), g.ctypes.data_as(P), ctypes.byref(st),
+                                        x.ctypes.data_as(P)))
+        return st.value, x
+
+    def result(self):
+        r = hubbard_vqe_result()
+        _check(lib().hubbard_lbfgs_result(self._h, ctypes.byref(r)))
+        return _result(r)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().hubbard_lbfgs_destroy(self._h)
+            self._h = ctypes.c_void_p()

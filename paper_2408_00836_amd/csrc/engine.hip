@@ -2116,3 +2116,192 @@ hubbard_status hubbard_tridiag_lowest(const double *a, const double *b, int32_t 
 }
 
 }  // extern "C"
+
+// ================================================================== VQE
+// The optimisation loop of Sec. 2.1 on the host: L-BFGS (lbfgs.cpp) over
+// energy_grad evaluations, one start per call or many starts advanced in
+// lockstep with one energy_grad_batch launch per round.
+
+namespace {
+
+LbfgsOptions vqe_options(const hubbard_vqe_opts *o)
+{
+    LbfgsOptions r;
+    if (o) {
+        r.max_steps = o->max_steps;
+        r.history = o->history;
+        r.e_tol = o->e_tol;
+        r.g_tol = o->g_tol;
+    }
+    return r;
+}
+
+size_t vqe_eval_bytes(hubbard_t h, int32_t n_layers, int32_t n_starts)
+{
+    const size_t P = (size_t)n_layers * h->m.params_per_layer();
+    return align256((size_t)n_starts * sizeof(double)) +
+           align256((size_t)n_starts * P * sizeof(double));
+}
+
+hubbard_status vqe_engine_bytes(hubbard_t h, int32_t n_layers, int32_t n_starts, size_t *bytes)
+{
+    if (n_starts == 1)
+        return hubbard_workspace_size(h, n_layers, HUBBARD_OP_ENERGY_GRAD, bytes);
+    std::vector<hubbard_t> hs(n_starts, h);
+    std::vector<int32_t> ls(n_starts, n_layers);
+    return hubbard_batch_workspace_size(hs.data(), n_starts, ls.data(), bytes);
+}
+
+}  // namespace
+
+extern "C" {
+
+hubbard_status hubbard_vqe_workspace_size(hubbard_t h, int32_t n_layers, int32_t n_starts,
+                                          size_t *bytes)
+{
+    if (!h || !bytes || n_layers < 1 || n_starts < 1)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_vqe_workspace_size");
+    size_t eng = 0;
+    hubbard_status st = vqe_engine_bytes(h, n_layers, n_starts, &eng);
+    if (st != HUBBARD_OK)
+        return st;
+    *bytes = align256(eng) + vqe_eval_bytes(h, n_layers, n_starts);
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_vqe(hubbard_t h, int32_t n_layers, int32_t n_starts, double *theta_dev,
+                           const hubbard_vqe_opts *opts, hubbard_vqe_result *results,
+                           void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (!h || n_layers < 1 || n_starts < 1 || !theta_dev || !results || !ws_dev)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_vqe");
+    if (opts && (opts->history < 1 || opts->max_steps < 0 || !(opts->e_tol >= 0.0) ||
+                 !(opts->g_tol >= 0.0)))
+        return fail(HUBBARD_ERR_ARG, "bad hubbard_vqe_opts");
+    size_t eng = 0, need = 0;
+    hubbard_status st = vqe_engine_bytes(h, n_layers, n_starts, &eng);
+    if (st != HUBBARD_OK)
+        return st;
+    eng = align256(eng);
+    need = eng + vqe_eval_bytes(h, n_layers, n_starts);
+    if (ws_bytes < need)
+        return fail(HUBBARD_ERR_SIZE, "workspace too small for hubbard_vqe");
+    const int P = n_layers * h->m.params_per_layer();
+    hipStream_t s = (hipStream_t)stream;
+    double *E_dev = (double *)((char *)ws_dev + eng);
+    double *G_dev = (double *)((char *)E_dev + align256((size_t)n_starts * sizeof(double)));
+    std::vector<double> th((size_t)n_starts * P), E(n_starts), G((size_t)n_starts * P);
+    hipError_t e = hipMemcpyAsync(th.data(), theta_dev, th.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("vqe: reading theta: ") + hipGetErrorString(e));
+    const LbfgsOptions lo = vqe_options(opts);
+    std::vector<Lbfgs> opt;
+    opt.reserve(n_starts);
+    for (int i = 0; i < n_starts; ++i)
+        opt.emplace_back(th.data() + (size_t)i * P, P, lo);
+    std::vector<int64_t> toff(n_starts);
+    std::vector<int32_t> lay(n_starts, n_layers);
+    std::vector<hubbard_t> hs(n_starts, h);
+    for (int i = 0; i < n_starts; ++i)
+        toff[i] = (int64_t)i * P;
+    for (;;) {
+        bool active = false;
+        for (int i = 0; i < n_starts; ++i) {
+            // finished starts stay at their final iterate (evaluated with the
+            // others: one launch sequence for all)
+            const std::vector<double> &t = opt[i].trial_point();
+            std::copy(t.begin(), t.end(), th.begin() + (size_t)i * P);
+            active = active || opt[i].state() == LBFGS_EVALUATE;
+        }
+        if (!active)
+            break;
+        e = hipMemcpyAsync(theta_dev, th.data(), th.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return fail(HUBBARD_ERR_DEVICE, std::string("vqe: theta: ") + hipGetErrorString(e));
+        st = n_starts == 1
+                 ? energy_grad(h, theta_dev, n_layers, E_dev, G_dev, ws_dev, eng, stream)
+                 : energy_grad_batch(hs.data(), n_starts, theta_dev, toff.data(), lay.data(),
+                                     E_dev, G_dev, ws_dev, eng, stream);
+        if (st != HUBBARD_OK)
+            return st;
+        e = hipMemcpyAsync(E.data(), E_dev, E.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(G.data(), G_dev, G.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return fail(HUBBARD_ERR_DEVICE, std::string("vqe: evaluation: ") +
+                                                hipGetErrorString(e));
+        for (int i = 0; i < n_starts; ++i)
+            if (opt[i].state() == LBFGS_EVALUATE)
+                opt[i].tell(E[i], G.data() + (size_t)i * P);
+    }
+    for (int i = 0; i < n_starts; ++i) {
+        const std::vector<double> &x = opt[i].iterate();
+        std::copy(x.begin(), x.end(), th.begin() + (size_t)i * P);
+        hubbard_vqe_result &r = results[i];
+        std::memset(&r, 0, sizeof(r));
+        r.E = opt[i].value();
+        r.grad_norm = opt[i].grad_norm();
+        r.steps = opt[i].n_steps();
+        r.evals = opt[i].n_evals();
+        r.reason = opt[i].state();
+    }
+    e = hipMemcpyAsync(theta_dev, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("vqe: writing theta: ") + hipGetErrorString(e));
+    return HUBBARD_OK;
+}
+
+struct hubbard_lbfgs {
+    Lbfgs opt;
+    hubbard_lbfgs(const double *x0, int n, const LbfgsOptions &o) : opt(x0, n, o) {}
+};
+
+hubbard_status hubbard_lbfgs_create(const double *x0, int32_t n, const hubbard_vqe_opts *opts,
+                                    hubbard_lbfgs_t *out)
+{
+    if (!x0 || n < 1 || !out)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_lbfgs_create");
+    try {
+        *out = new hubbard_lbfgs(x0, n, vqe_options(opts));
+    } catch (...) {
+        return fail(HUBBARD_ERR_NOMEM, "allocating the optimiser");
+    }
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_lbfgs_tell(hubbard_lbfgs_t L, double f, const double *g, int32_t *state,
+                                  double *x_next)
+{
+    if (!L || !g || !state || !x_next)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_lbfgs_tell");
+    *state = L->opt.tell(f, g);
+    const std::vector<double> &t = L->opt.trial_point();
+    std::copy(t.begin(), t.end(), x_next);
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_lbfgs_result(hubbard_lbfgs_t L, hubbard_vqe_result *res)
+{
+    if (!L || !res)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_lbfgs_result");
+    std::memset(res, 0, sizeof(*res));
+    res->E = L->opt.value();
+    res->grad_norm = L->opt.grad_norm();
+    res->steps = L->opt.n_steps();
+    res->evals = L->opt.n_evals();
+    res->reason = L->opt.state();
+    return HUBBARD_OK;
+}
+
+void hubbard_lbfgs_destroy(hubbard_lbfgs_t L) { delete L; }
+
+}  // extern "C"

@@ -228,6 +228,55 @@ struct Model {
 // component positive).  m >= 1.
 double tridiag_lowest(const double *a, const double *b, int m, double *vec);
 
+// L-BFGS with a strong-Wolfe line search as a reverse-communication state
+// machine (lbfgs.cpp): construct with the start point, evaluate trial(),
+// pass the value and gradient to tell(); repeat while it returns
+// LBFGS_EVALUATE.  x() is the current iterate, trial() the point to
+// evaluate next (the final iterate once finished).
+enum LbfgsStatus {
+    LBFGS_EVALUATE = 0,
+    LBFGS_ENERGY_TOL = 1,   // |E_k - E_{k-1}| < e_tol
+    LBFGS_GRAD_TOL = 2,     // ||g||_2 < g_tol
+    LBFGS_MAX_STEPS = 3,
+    LBFGS_LINE_SEARCH = 4,  // no acceptable step along the search direction
+    LBFGS_NOT_FINITE = 5    // the start point's value or gradient is not finite
+};
+struct LbfgsOptions {
+    int max_steps = 1000;
+    int history = 10;
+    double e_tol = 1e-7;
+    double g_tol = 1e-6;
+};
+class Lbfgs {
+  public:
+    Lbfgs(const double *x0, int n, const LbfgsOptions &o);
+    int tell(double f, const double *g);
+    const std::vector<double> &trial_point() const { return trial; }
+    const std::vector<double> &iterate() const { return x; }
+    double value() const { return f; }
+    double grad_norm() const { return gnorm; }
+    int state() const { return status; }
+    int n_steps() const { return steps; }
+    int n_evals() const { return evals; }
+
+  private:
+    void direction();
+    void start_line_search();
+    void request(double a);
+    int accept(double ft, const double *gt);
+    int finish(int reason);
+    LbfgsOptions opt;
+    int n;
+    std::vector<double> x, g, d, trial;
+    std::vector<std::vector<double>> S, Y;
+    std::vector<double> rho;
+    double f = 0.0, gnorm = 0.0, dphi0 = 0.0, alpha = 0.0;
+    double a_prev = 0.0, f_prev = 0.0, df_prev = 0.0;
+    double a_lo = 0.0, f_lo = 0.0, df_lo = 0.0, a_hi = 0.0;
+    bool first = true, zooming = false, give_up = false;
+    int line_evals = 0, steps = 0, evals = 0, status = LBFGS_EVALUATE;
+};
+
 // Build and validate a model; returns an empty string or an error message.
 std::string build_model(int nx, int ny, int px, int py, const double *t, double U,
                         const double *V, const double *eps, const int32_t *groups, Model &m);

@@ -39,6 +39,8 @@ class Hubbard:
         lattice and GPU when the cache has one (else the library defaults)."""
         self.handle = (_handle if _handle is not None else
                        abi.hubbard_create(nx, ny, periodic_x, periodic_y, t, U, V, eps, groups))
+        self._ctor = dict(nx=nx, ny=ny, periodic_x=periodic_x, periodic_y=periodic_y, t=t, U=U,
+                          V=V, eps=eps, groups=groups)
         self.nx, self.ny = nx, ny
         self.periodic_x, self.periodic_y = bool(periodic_x), bool(periodic_y)
         # the diagonal has eps or V terms besides U (selects the general kernels)
@@ -64,7 +66,19 @@ class Hubbard:
               groups=None, site_spin=None) -> "Hubbard":
         """The model on an arbitrary graph of sites (see hubbard_create_graph)."""
         h = abi.hubbard_create_graph(n_sites, bonds, t, U, V, eps, groups, site_spin)
-        return cls(1, n_sites, V=V, eps=eps, tuned=False, _handle=h)
+        m = cls(1, n_sites, V=V, eps=eps, tuned=False, _handle=h)
+        m._ctor = dict(graph=True, n_sites=n_sites, bonds=bonds, t=t, U=U, V=V, eps=eps,
+                       groups=groups, site_spin=site_spin)
+        return m
+
+    def noninteracting(self) -> "Hubbard":
+        """The same lattice, hoppings and on-site energies with U = V = 0 (the
+        non-interacting model whose optimum starts the interacting VQE,
+        Sec. 2.1)."""
+        a = dict(self._ctor, U=0.0, V=None)
+        if a.pop("graph", False):
+            return Hubbard.graph(**a)
+        return Hubbard(**a)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -196,6 +210,19 @@ class Hubbard:
                                           gs.data_ptr() if gs is not None else None,
                                           ws.data_ptr(), ws.numel(), _stream())
         return dict(E0=E0, iters=it, residual=res, state=gs)
+
+    def vqe(self, theta0, layers: int, opts: dict | None = None):
+        """L-BFGS minimisation of E(theta) (hubbard_vqe) from each row of
+        theta0 (n_starts x P); several starts run in lockstep, one batched
+        evaluation per round.  Returns (final thetas on the device, results)."""
+        th = torch.as_tensor(np.asarray(theta0, dtype=np.float64), device="cuda")
+        th = th.reshape(-1, self.n_params(layers)).contiguous()
+        n = th.shape[0]
+        nb = abi.hubbard_vqe_workspace_size(self.handle, layers, n)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        res = abi.hubbard_vqe(self.handle, layers, n, th.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream(), opts)
+        return th, res
 
     def workspace_views(self, layers: int):
         """Two plain vector buffers carved out of the energy_grad workspace

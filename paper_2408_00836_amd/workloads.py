@@ -137,3 +137,11 @@ def random_instance(nx: int, ny: int, layers: int, per: int, seed: int, *,
     eps = rng.uniform(-eps_width, eps_width, nx * ny)
     return Workload(name or f"{nx}x{ny} seed {seed}", nx, ny, periodic_x, periodic_y, U, layers,
                     per, _theta(rng, layers, per), t=t, V=np.full(nb, V), eps=eps)
+
+
+def vqe_starts(n_params: int, n_starts: int = 10, seed: int = 0) -> np.ndarray:
+    """Random initial parameters of the VQE runs (Sec. 2.1): independent
+    draws from a normal distribution of mean 0 and variance 1e-5, one row
+    per start."""
+    rng = np.random.default_rng(30000 + seed)
+    return rng.normal(0.0, np.sqrt(1e-5), (n_starts, n_params))
