@@ -78,6 +78,9 @@ def lib():
         L.orc_energy_grad.argtypes = [P(_Model), vp, ci, cu64, P(cd), vp]
         L.orc_energy_grad.restype = ci
         L.orc_threads.restype = ci
+        L.orc_overlap_grad.argtypes = [P(_Model), vp, ci, cu64, vp, vp, vp]
+        L.orc_overlap_grad.restype = ci
+        L.orc_spin_correlation.argtypes = [P(_Model), vp, vp, vp]
         L.orc_set_threads.argtypes = [ci]
         _lib = L
     return _lib
@@ -240,3 +243,27 @@ def ham_matrix(m: OracleModel, basis_states) -> np.ndarray:
                 raise ValueError("basis set is not closed under H")
             Hm[pos[int(r)], k] = col[r]
     return Hm
+
+
+def overlap_grad(m: OracleModel, theta, layers: int, ref: np.ndarray, b0: int | None = None):
+    """(f, F, df/dtheta): f = log10(1 - F), F = |<ref|psi(theta)>|^2 (Eq. (5)/(6))."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    ref = np.ascontiguousarray(ref, dtype=np.complex128)
+    if ref.size != 1 << m.nqubits:
+        raise ValueError("ref must hold 2^n amplitudes")
+    out = np.zeros(2)
+    g = np.zeros(th.size)
+    b0 = m.neel_index() if b0 is None else b0
+    if lib().orc_overlap_grad(ctypes.byref(_cmodel(m)), _ptr(th), layers, b0, _ptr(ref),
+                              _ptr(out), _ptr(g)):
+        raise MemoryError("oracle overlap_grad: allocation failed")
+    return out[0], out[1], g
+
+
+def spin_correlation(m: OracleModel, psi: np.ndarray):
+    """(C, Sz): C[i, j] = <S^z_i S^z_j> - <S^z_i><S^z_j> (Eq. (17)), Sz[i] = <S^z_i>."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    C = np.zeros((m.nsites, m.nsites))
+    Sz = np.zeros(m.nsites)
+    lib().orc_spin_correlation(ctypes.byref(_cmodel(m)), _ptr(psi), _ptr(C), _ptr(Sz))
+    return C, Sz

@@ -707,3 +707,83 @@ int orc_sector_energy_grad(const orc_model *m, const double *theta, int layers, 
     sector_free(&S);
     return 0;
 }
+
+/* ------------------------------------------- overlap loss, Eq. (5)/(6) --- */
+
+/* f = log10(1 - F), F = |<ref|psi(theta)>|^2 (the logarithm of the
+ * infidelity with a reference state), and df/dtheta_k.  F = <psi|P|psi> with
+ * the projector P = |ref><ref|, so the adjoint recursion of the energy
+ * applies with H replaced by P: lambda_P = P psi = <ref|psi> ref, and
+ * dF/dtheta_k = 2 Im <lambda_k|G_k|psi_k>; then df = -dF / ((1 - F) ln 10).
+ * out[0] = f, out[1] = F.  Returns 0 or -1 (allocation). */
+int orc_overlap_grad(const orc_model *m, const double *theta, int layers, uint64_t b0,
+                     const cplx *ref, double *out, double *grad)
+{
+    const int n = nqubits(m);
+    const uint64_t dim = (uint64_t)1 << n;
+    const int per = 1 + m->ngroups;
+    cplx *psi = malloc(dim * sizeof(cplx));
+    cplx *lam = malloc(dim * sizeof(cplx));
+    cplx *tmp = malloc(dim * sizeof(cplx));
+    if (!psi || !lam || !tmp) {
+        free(psi);
+        free(lam);
+        free(tmp);
+        return -1;
+    }
+    orc_ansatz(m, theta, layers, b0, psi);
+    double re, im;
+    orc_inner(n, ref, psi, &re, &im);   /* c = <ref|psi> */
+    const cplx c = re + I * im;
+    const double F = re * re + im * im;
+    for (uint64_t b = 0; b < dim; b++)
+        lam[b] = c * ref[b];
+    out[0] = log10(1.0 - F);
+    out[1] = F;
+    for (int k = layers * per - 1; k >= 0; k--) {
+        int slot = k % per;
+        orc_generator_apply(m, slot, psi, tmp);
+        orc_inner(n, lam, tmp, &re, &im);
+        grad[k] = -2.0 * im / ((1.0 - F) * log(10.0));
+        orc_apply_slot(m, slot, -theta[k], psi);
+        orc_apply_slot(m, slot, -theta[k], lam);
+    }
+    free(psi);
+    free(lam);
+    free(tmp);
+    return 0;
+}
+
+/* ------------------------------------- spin correlations, Eq. (17) ------ */
+
+/* C[i*ns + j] = <S^z_i S^z_j> - <S^z_i><S^z_j> and Sz[i] = <S^z_i> of a
+ * state, S^z_i = (n_i,up - n_i,dn) / 2, every expectation a sum over all
+ * amplitudes of |psi_b|^2 times the operator's (diagonal) value at b. */
+void orc_spin_correlation(const orc_model *m, const cplx *psi, double *C, double *Sz)
+{
+    const int ns = m->nsites;
+    const uint64_t dim = (uint64_t)1 << nqubits(m);
+    nsum *ss = calloc((size_t)ns * ns, sizeof(nsum));
+    nsum *s1 = calloc((size_t)ns, sizeof(nsum));
+    double *sz = malloc((size_t)ns * sizeof(double));
+    for (uint64_t b = 0; b < dim; b++) {
+        const double p = creal(psi[b]) * creal(psi[b]) + cimag(psi[b]) * cimag(psi[b]);
+        if (p == 0.0)
+            continue;
+        for (int i = 0; i < ns; i++)
+            sz[i] = 0.5 * (double)(bit(b, qubit_of(m, i, 0)) - bit(b, qubit_of(m, i, 1)));
+        for (int i = 0; i < ns; i++) {
+            nsum_add(&s1[i], p * sz[i]);
+            for (int j = 0; j < ns; j++)
+                nsum_add(&ss[i * ns + j], p * sz[i] * sz[j]);
+        }
+    }
+    for (int i = 0; i < ns; i++)
+        Sz[i] = nsum_value(&s1[i]);
+    for (int i = 0; i < ns; i++)
+        for (int j = 0; j < ns; j++)
+            C[i * ns + j] = nsum_value(&ss[i * ns + j]) - Sz[i] * Sz[j];
+    free(ss);
+    free(s1);
+    free(sz);
+}
