@@ -160,7 +160,9 @@ enum {
     HUBBARD_OP_ENERGY = 0,       /* energy():      psi + reduction partials */
     HUBBARD_OP_ENERGY_GRAD = 1,  /* energy_grad(): psi + lambda + partials */
     HUBBARD_OP_OVERLAP = 2,      /* hubbard_overlap(): partial sums (hubbard_vector_workspace_size) */
-    HUBBARD_OP_LANCZOS = 3       /* hubbard_lanczos(): three vectors + partial sums (same) */
+    HUBBARD_OP_LANCZOS = 3,      /* hubbard_lanczos(): three vectors + partial sums (same) */
+    HUBBARD_OP_OVERLAP_GRAD = 4, /* overlap_grad(): as energy_grad + overlap partials */
+    HUBBARD_OP_SPIN_CORR = 5     /* hubbard_spin_correlation(): moment partials (vector size call) */
 };
 
 /* Bytes of device workspace needed by energy()/energy_grad() for n_layers. */
@@ -235,6 +237,29 @@ hubbard_status hubbard_overlap(hubbard_t h, const void *a_dev, const void *b_dev
 hubbard_status hubbard_lanczos(hubbard_t h, const void *start_dev, int32_t max_iter, double tol,
                                double *E0, int32_t *iters, double *residual, void *gs_dev,
                                void *ws_dev, size_t ws_bytes, void *stream);
+
+/* The overlap loss of Eq. (5)/(6) and its gradient: with F(theta) =
+ * |<ref|psi(theta)>|^2, out_dev[0] = f = log10(1 - F) and out_dev[1] = F,
+ * grad_dev[k] = df/dtheta_k = -(dF/dtheta_k) / ((1 - F) ln 10).  F is the
+ * expectation of the projector P = |ref><ref|, so dF/dtheta_k comes from
+ * energy_grad's reverse sweep seeded with lambda = P psi = <ref|psi> ref
+ * instead of H psi (the intermediate states of Sec. 2.1, one reduction per
+ * parameter).  ref_dev: 2^n complex128 of unit norm (caller-owned, not
+ * overlapping the workspace); ws_dev: hubbard_workspace_size(...,
+ * HUBBARD_OP_OVERLAP_GRAD) bytes.  F = 1 gives f = -inf.  Asynchronous. */
+hubbard_status overlap_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                            const void *ref_dev, double *out_dev, double *grad_dev, void *ws_dev,
+                            size_t ws_bytes, void *stream);
+
+/* Spin correlations of Eq. (17) of a state vector: C_dev[i * n_sites + j] =
+ * <S^z_i S^z_j> - <S^z_i><S^z_j> and Sz_dev[i] = <S^z_i>, S^z_i =
+ * (n_i,up - n_i,dn) / 2 (device doubles), from one read of psi_dev: the
+ * occupation second moments sum_x |psi_x|^2 n_a(x) n_b(x) over all qubit
+ * pairs, in a fixed order.  ws_dev: hubbard_vector_workspace_size(...,
+ * HUBBARD_OP_SPIN_CORR) bytes.  Asynchronous. */
+hubbard_status hubbard_spin_correlation(hubbard_t h, const void *psi_dev, double *C_dev,
+                                        double *Sz_dev, void *ws_dev, size_t ws_bytes,
+                                        void *stream);
 
 /* The VQE optimisation of Sec. 2.1: minimise E(theta) = <psi(theta)|H|psi(theta)>
  * by L-BFGS (limited-memory BFGS, strong-Wolfe line search) on energy_grad

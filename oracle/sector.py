@@ -120,3 +120,26 @@ def energy_grad(m: OracleModel, theta, layers: int, b0: int | None = None, grad:
                                      ctypes.byref(E), core._ptr(g) if grad else None):
         raise MemoryError("sector energy_grad")
     return E.value, g
+
+
+def spin_correlation(m: OracleModel, psi: np.ndarray, b0: int | None = None, chunk: int = 1 << 22):
+    """(C, Sz) of Eq. (17) from a sector vector: C[i, j] = <Sz_i Sz_j> -
+    <Sz_i><Sz_j>, Sz_i = (n_i,up - n_i,dn)/2, each expectation summed over the
+    sector's amplitudes (|psi_x|^2 times the operator's value at x), in
+    chunks."""
+    b0 = _b0(m, b0)
+    idx = indices(m, b0)
+    ns = m.nsites
+    ss = np.zeros((ns, ns))
+    s1 = np.zeros(ns)
+    for a in range(0, idx.size, chunk):
+        x = idx[a:a + chunk]
+        p = np.abs(psi[a:a + chunk]) ** 2
+        sz = np.empty((x.size, ns))
+        for i in range(ns):
+            up = ((x >> np.uint64(m.qubit(i, 0))) & np.uint64(1)).astype(np.float64)
+            dn = ((x >> np.uint64(m.qubit(i, 1))) & np.uint64(1)).astype(np.float64)
+            sz[:, i] = 0.5 * (up - dn)
+        ss += (sz * p[:, None]).T @ sz
+        s1 += p @ sz
+    return ss - np.outer(s1, s1), s1

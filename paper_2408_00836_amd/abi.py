@@ -25,6 +25,8 @@ HUBBARD_OP_ENERGY = 0
 HUBBARD_OP_ENERGY_GRAD = 1
 HUBBARD_OP_OVERLAP = 2
 HUBBARD_OP_LANCZOS = 3
+HUBBARD_OP_OVERLAP_GRAD = 4
+HUBBARD_OP_SPIN_CORR = 5
 
 # Every symbol the headers in include/ declare.
 EXPORTED = [
@@ -37,7 +39,8 @@ EXPORTED = [
     "hubbard_batch_cached", "hubbard_batch_set_config", "hubbard_batch_get_config",
     "energy_grad_noalloc", "hubbard_vector_workspace_size", "hubbard_overlap", "hubbard_lanczos",
     "hubbard_tridiag_lowest", "hubbard_vqe_workspace_size", "hubbard_vqe", "hubbard_lbfgs_create",
-    "hubbard_lbfgs_tell", "hubbard_lbfgs_result", "hubbard_lbfgs_destroy",
+    "hubbard_lbfgs_tell", "hubbard_lbfgs_result", "hubbard_lbfgs_destroy", "overlap_grad",
+    "hubbard_spin_correlation",
 ]
 
 
@@ -144,6 +147,8 @@ def lib() -> ctypes.CDLL:
                                     P(ctypes.c_double)], st),
             "hubbard_lbfgs_result": ([vp, P(hubbard_vqe_result)], st),
             "hubbard_lbfgs_destroy": ([vp], None),
+            "overlap_grad": ([vp, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp], st),
+            "hubbard_spin_correlation": ([vp, vp, vp, vp, vp, ctypes.c_size_t, vp], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -479,3 +484,15 @@ class Lbfgs:
         if getattr(self, "_h", None) and self._h.value:
             lib().hubbard_lbfgs_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+
+def overlap_grad(h: int, theta_dev: int, n_layers: int, ref_dev: int, out_dev: int,
+                 grad_dev: int, ws_dev: int, ws_bytes: int, stream: int = 0) -> None:
+    _check(lib().overlap_grad(h, theta_dev, int(n_layers), ref_dev, out_dev, grad_dev, ws_dev,
+                              int(ws_bytes), stream))
+
+
+def hubbard_spin_correlation(h: int, psi_dev: int, C_dev: int, Sz_dev: int, ws_dev: int,
+                             ws_bytes: int, stream: int = 0) -> None:
+    _check(lib().hubbard_spin_correlation(h, psi_dev, C_dev, Sz_dev, ws_dev, int(ws_bytes),
+                                          stream))

@@ -37,6 +37,11 @@ __global__ void k_krylov_update(double2 *, const double2 *, const double2 *, dou
 __global__ void k_vscale(double2 *, const double2 *, double, uint64_t);
 __global__ void k_vaxpy(double2 *, const double2 *, double, uint64_t);
 __global__ void k_vsum(const double2 *, int, double2 *);
+__global__ void k_vscale_dev(double2 *, const double2 *, const double2 *, uint64_t);
+__global__ void k_overlap_finish(const double2 *, double *, int, double *);
+__global__ void k_bit_moments(const double2 *, int, int, double *);
+__global__ void k_moments_final(const double *, int, int, int, double *);
+__global__ void k_spin_corr(const double *, int, double *, double *);
 }  // namespace hv
 
 using namespace hv;
@@ -1288,23 +1293,25 @@ hubbard_status hubbard_workspace_size(hubbard_t h, int32_t n_layers, int32_t op,
 {
     if (!h || !bytes || n_layers < 0)
         return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_workspace_size");
-    if (op != HUBBARD_OP_ENERGY && op != HUBBARD_OP_ENERGY_GRAD)
+    if (op != HUBBARD_OP_ENERGY && op != HUBBARD_OP_ENERGY_GRAD && op != HUBBARD_OP_OVERLAP_GRAD)
         return fail(HUBBARD_ERR_ARG, "unknown op");
     Program pr;
     try {
         plan_program(h, op == HUBBARD_OP_ENERGY ? PROG_ENERGY : PROG_GRAD, n_layers,
-                     max_smem_per_block(), pr);
+                     max_smem_per_block(), pr);   // overlap_grad runs the gradient program
     } catch (const std::exception &ex) {
         return fail(HUBBARD_ERR_NOMEM, ex.what());
     }
     Builder b(h->m);
     b.add(pr.h_fwd, 0, false, true);
-    b.add(pr.h_ham, op == HUBBARD_OP_ENERGY_GRAD ? 2 : 0, true);
+    b.add(pr.h_ham, op != HUBBARD_OP_ENERGY ? 2 : 0, true);
     b.add(pr.h_rev, 1, false);
     b.add(pr.h_exp, 2, false);
     size_t partial = align256(b.row_param.size() * (size_t)kGridMax * sizeof(double));
     size_t nvec = (op == HUBBARD_OP_ENERGY) ? 1 : 2;
     *bytes = nvec * align256(vec_bytes(h)) + partial;
+    if (op == HUBBARD_OP_OVERLAP_GRAD)   // the overlap's partial sums, its value, one spare
+        *bytes += align256((size_t)kVecBlocks * sizeof(double2)) + 256;
     return HUBBARD_OK;
 }
 
@@ -1917,6 +1924,23 @@ namespace {
 
 size_t vec_partial_bytes() { return align256((size_t)kVecBlocks * sizeof(double2)); }
 
+// Workgroup split of k_bit_moments for an n-qubit vector.
+struct MomentLayout {
+    int lo, mid, r, n_blk, stride;
+    size_t partial_bytes;
+};
+MomentLayout moment_layout(int n)
+{
+    MomentLayout m;
+    m.lo = std::min(kMomLo, n);
+    m.mid = std::min(kMomMid, n - m.lo);
+    m.r = m.lo + m.mid;
+    m.n_blk = 1 << (n - m.r);
+    m.stride = 1 + m.r * (m.r + 1) / 2;
+    m.partial_bytes = align256((size_t)m.n_blk * m.stride * sizeof(double));
+    return m;
+}
+
 unsigned vec_grid(uint64_t n)
 {
     return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)kVecBlocks,
@@ -1985,8 +2009,14 @@ extern "C" {
 
 hubbard_status hubbard_vector_workspace_size(hubbard_t h, int32_t op, size_t *bytes)
 {
-    if (!h || !bytes || (op != HUBBARD_OP_OVERLAP && op != HUBBARD_OP_LANCZOS))
+    if (!h || !bytes ||
+        (op != HUBBARD_OP_OVERLAP && op != HUBBARD_OP_LANCZOS && op != HUBBARD_OP_SPIN_CORR))
         return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_vector_workspace_size");
+    if (op == HUBBARD_OP_SPIN_CORR) {
+        const MomentLayout ml = moment_layout(h->m.nq);
+        *bytes = ml.partial_bytes + align256((size_t)h->m.nq * h->m.nq * sizeof(double));
+        return HUBBARD_OK;
+    }
     const size_t vb = align256(vec_bytes(h));
     *bytes = (op == HUBBARD_OP_LANCZOS ? 3 * vb : 0) + vec_partial_bytes();
     return HUBBARD_OK;
@@ -2303,5 +2333,101 @@ hubbard_status hubbard_lbfgs_result(hubbard_lbfgs_t L, hubbard_vqe_result *res)
 }
 
 void hubbard_lbfgs_destroy(hubbard_lbfgs_t L) { delete L; }
+
+}  // extern "C"
+
+// ========================================================== observables
+// The overlap loss of Eq. (5)/(6) with its adjoint gradient, and the spin
+// correlations of Eq. (17).
+
+extern "C" {
+
+hubbard_status overlap_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                            const void *ref_dev, double *out_dev, double *grad_dev, void *ws_dev,
+                            size_t ws_bytes, void *stream)
+{
+    if (!h || !ref_dev || !out_dev || !ws_dev || n_layers < 0 ||
+        (n_layers > 0 && (!theta_dev || !grad_dev)))
+        return fail(HUBBARD_ERR_ARG, "bad arguments to overlap_grad");
+    Program *pr;
+    DeviceState *ds;
+    hubbard_status st = get_program(h, PROG_GRAD, n_layers, &pr, &ds);
+    if (st != HUBBARD_OK)
+        return st;
+    const size_t vb = align256(vec_bytes(h));
+    const size_t need = 2 * vb + pr->partial_bytes + vec_partial_bytes() + 256;
+    if (ws_bytes < need)
+        return fail(HUBBARD_ERR_SIZE, "workspace too small for overlap_grad");
+    const char *ws = (const char *)ws_dev, *rf = (const char *)ref_dev;
+    if (rf < ws + need && ws < rf + vec_bytes(h))
+        return fail(HUBBARD_ERR_ARG, "ref_dev overlaps the workspace");
+    hipStream_t s = (hipStream_t)stream;
+    double2 *psi = (double2 *)ws_dev;
+    double2 *lam = (double2 *)((char *)ws_dev + vb);
+    double *partial = (double *)((char *)ws_dev + 2 * vb);
+    double2 *vpart = (double2 *)((char *)partial + pr->partial_bytes);
+    double2 *c = (double2 *)((char *)vpart + vec_partial_bytes());
+    double *spare = (double *)(c + 1);
+    const uint64_t n = (uint64_t)1 << h->m.nq;
+    const unsigned g = vec_grid(n);
+    // psi(theta), plain layout
+    const bool from_start = !pr->fwd.pass.empty();
+    if (!from_start && (st = run_init(h, psi, s)) != HUBBARD_OK)
+        return st;
+    h->ev_used = 0;
+    h->kmode.clear();
+    if ((st = run_forward(*pr, *ds, theta_dev, psi, s, h, VecLayout(), from_start)) != HUBBARD_OK)
+        return st;
+    // c = <ref|psi>, lambda = c ref = P psi (P the projector on ref)
+    hipLaunchKernelGGL(k_vdot, dim3(g), dim3(kVecThreads), 0, s, (const double2 *)ref_dev,
+                       (const double2 *)psi, n, vpart);
+    hipLaunchKernelGGL(k_vsum, dim3(1), dim3(kVecThreads), 0, s, vpart, (int)g, c);
+    hipLaunchKernelGGL(k_vscale_dev, dim3(g), dim3(kVecThreads), 0, s, lam,
+                       (const double2 *)ref_dev, (const double2 *)c, n);
+    // the energy's reverse sweep with H replaced by P: dF/dtheta (the
+    // reduction's energy output reads rows of H passes that did not run and
+    // goes to a spare slot)
+    launch_list<M_REV>(*pr, *ds, pr->rev, theta_dev, psi, lam, partial, s, h, VecLayout(), 0,
+                       PF_NO_STORE);
+    if ((st = check_launch("overlap reverse pass")) != HUBBARD_OK)
+        return st;
+    if ((st = run_reduce(*pr, partial, spare, grad_dev, s)) != HUBBARD_OK)
+        return st;
+    const int P = n_layers * h->m.params_per_layer();
+    hipLaunchKernelGGL(k_overlap_finish, dim3(1), dim3(kVecThreads), 0, s, (const double2 *)c,
+                       grad_dev, P, out_dev);
+    return check_launch("overlap_grad");
+}
+
+hubbard_status hubbard_spin_correlation(hubbard_t h, const void *psi_dev, double *C_dev,
+                                        double *Sz_dev, void *ws_dev, size_t ws_bytes,
+                                        void *stream)
+{
+    if (!h || !psi_dev || !C_dev || !Sz_dev || !ws_dev)
+        return fail(HUBBARD_ERR_ARG, "NULL argument to hubbard_spin_correlation");
+    size_t need = 0;
+    hubbard_vector_workspace_size(h, HUBBARD_OP_SPIN_CORR, &need);
+    if (ws_bytes < need)
+        return fail(HUBBARD_ERR_SIZE, "workspace too small for hubbard_spin_correlation");
+    const int n = h->m.nq;
+    const MomentLayout ml = moment_layout(n);
+    hipStream_t s = (hipStream_t)stream;
+    double *partial = (double *)ws_dev;
+    double *Q = (double *)((char *)ws_dev + ml.partial_bytes);
+    const int W = 1 + kMomMid + kMomMid * (kMomMid - 1) / 2;
+    const int smem = (1 << ml.lo) * W * (int)sizeof(double);
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        (void)hipFuncSetAttribute((const void *)k_bit_moments,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  max_smem_per_block());
+    });
+    hipLaunchKernelGGL(k_bit_moments, dim3(ml.n_blk), dim3(1 << ml.lo), smem, s,
+                       (const double2 *)psi_dev, ml.lo, ml.mid, partial);
+    hipLaunchKernelGGL(k_moments_final, dim3(n * (n + 1) / 2), dim3(kVecThreads), 0, s, partial,
+                       ml.n_blk, ml.r, n, Q);
+    hipLaunchKernelGGL(k_spin_corr, dim3(1), dim3(kVecThreads), 0, s, Q, h->m.ns, C_dev, Sz_dev);
+    return check_launch("spin correlation");
+}
 
 }  // extern "C"

@@ -207,6 +207,10 @@ __host__ __device__ inline SmemPlan smem_plan(int k, int n_ops, int n_diag, int 
 // a launch uses (also the number of reduction partials).
 constexpr int kVecThreads = 256;
 constexpr int kVecBlocks = 1024;
+// Occupation moments (k_bit_moments): a workgroup covers 2^(LO+MID)
+// amplitudes, LO <= kMomLo bits from the thread id, MID <= kMomMid from a loop.
+constexpr int kMomLo = 8;
+constexpr int kMomMid = 10;
 
 // ------------------------------------------------------------------ host --
 

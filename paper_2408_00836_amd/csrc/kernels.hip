@@ -992,6 +992,184 @@ k_vsum(const double2 *__restrict__ partial, int nblk, double2 *__restrict__ out)
         out[0] = t;
 }
 
+// dst <- c * src with the complex scalar c read from device memory (the
+// adjoint seed of the overlap loss: lambda = <ref|psi> ref).
+__global__ void __launch_bounds__(kVecThreads)
+k_vscale_dev(double2 *__restrict__ dst, const double2 *__restrict__ src,
+             const double2 *__restrict__ c, uint64_t n)
+{
+    const double2 z = c[0];
+    const uint64_t stride = (uint64_t)gridDim.x * kVecThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride)
+        dst[i] = cmul(z, src[i]);
+}
+
+// Overlap loss from F = |c|^2, c = <ref|psi>: out = (f, F) with
+// f = log10(1 - F), and the gradient of F (adjoint sweep) turned into the
+// gradient of f: df = -dF / ((1 - F) ln 10).
+__global__ void __launch_bounds__(kVecThreads)
+k_overlap_finish(const double2 *__restrict__ c, double *__restrict__ grad, int P,
+                 double *__restrict__ out)
+{
+    const double F = c[0].x * c[0].x + c[0].y * c[0].y;
+    const double s = -1.0 / ((1.0 - F) * 2.302585092994045684);   // ln 10
+    for (int k = threadIdx.x; k < P; k += blockDim.x)
+        grad[k] *= s;
+    if (threadIdx.x == 0) {
+        out[0] = log10(1.0 - F);
+        out[1] = F;
+    }
+}
+
+// ----------------------------------------------- occupation second moments --
+// Q[a][b] = sum over amplitudes of |psi_x|^2 bit_a(x) bit_b(x) for every pair
+// of qubits (the diagonal holds the occupations <n_a>): every diagonal
+// observable quadratic in occupations -- the spin correlations of Eq. (17)
+// among them -- follows from Q.  One HBM read of psi.
+//
+// A workgroup covers 2^(LO+MID) consecutive amplitudes: the thread id gives
+// the LO low bits, a loop over j gives the MID bits above them, and the bits
+// above LO+MID (the block index) are fixed in the workgroup.  Because j is
+// uniform across the workgroup, a thread accumulates the mass c, the
+// moments M[a] of the loop bits and their pair moments Qm[a][b] with
+// branches that never diverge; the workgroup then forms the moment matrix of
+// its LO+MID low bits and its mass, and k_moments_final combines the
+// workgroups with their fixed high bits.  Fixed summation orders throughout.
+constexpr int kMomPairs = kMomMid * (kMomMid - 1) / 2;
+__device__ __forceinline__ int mom_pair(int a, int b)   // a < b < kMomMid
+{
+    return a * (2 * kMomMid - a - 1) / 2 + (b - a - 1);
+}
+
+// partial[blk * (1 + R*(R+1)/2)]: the mass, then the upper triangle (row
+// major, diagonal included) of the workgroup's R x R moment matrix, R = LO + MID.
+__global__ void __launch_bounds__(256)
+k_bit_moments(const double2 *__restrict__ psi, int LO, int MID, double *__restrict__ partial)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int T = 1 << LO, t = threadIdx.x;
+    const int R = LO + MID, stride = 1 + R * (R + 1) / 2;
+    double c = 0.0, M[kMomMid], Q[kMomPairs];
+#pragma unroll
+    for (int a = 0; a < kMomMid; ++a)
+        M[a] = 0.0;
+#pragma unroll
+    for (int a = 0; a < kMomPairs; ++a)
+        Q[a] = 0.0;
+    const uint64_t base = (uint64_t)blockIdx.x << R;
+    for (uint32_t j = 0; j < (1u << MID); ++j) {
+        const double2 v = psi[base | ((uint64_t)j << LO) | (uint32_t)t];
+        const double p = v.x * v.x + v.y * v.y;
+        c += p;
+#pragma unroll
+        for (int a = 0; a < kMomMid; ++a) {
+            if (!((j >> a) & 1u))
+                continue;
+            M[a] += p;
+#pragma unroll
+            for (int b = a + 1; b < kMomMid; ++b)
+                if ((j >> b) & 1u)
+                    Q[mom_pair(a, b)] += p;
+        }
+    }
+    // per-thread values to LDS: [T][1 + MID + pairs]
+    const int W = 1 + kMomMid + kMomPairs;
+    double *lds = (double *)smem;
+    lds[t * W] = c;
+#pragma unroll
+    for (int a = 0; a < kMomMid; ++a)
+        lds[t * W + 1 + a] = M[a];
+#pragma unroll
+    for (int a = 0; a < kMomPairs; ++a)
+        lds[t * W + 1 + kMomMid + a] = Q[a];
+    __syncthreads();
+    double *out = partial + (size_t)blockIdx.x * stride;
+    // entry e: 0 = mass, then (a, b), a <= b < R, row major
+    for (int e = t; e < stride; e += T) {
+        int a = 0, b = 0;
+        if (e > 0) {
+            int r = e - 1;
+            while (r >= R - a) {
+                r -= R - a;
+                ++a;
+            }
+            b = a + r;
+        }
+        double acc = 0.0;
+        for (int u = 0; u < T; ++u) {
+            const double *row = lds + u * W;
+            double v;
+            if (e == 0)
+                v = row[0];
+            else if (b < LO)        // both in the thread id
+                v = ((u >> a) & (u >> b) & 1) ? row[0] : 0.0;
+            else if (a < LO)        // thread bit a, loop bit b
+                v = ((u >> a) & 1) ? row[1 + (b - LO)] : 0.0;
+            else if (a == b)        // loop bit a
+                v = row[1 + (a - LO)];
+            else                    // loop bits a < b
+                v = row[1 + kMomMid + mom_pair(a - LO, b - LO)];
+            acc += v;
+        }
+        out[e] = acc;
+    }
+}
+
+// Q (n x n, both triangles) from the workgroup partials: block e handles one
+// pair a <= b; bits >= R are bits of the workgroup index.
+__global__ void __launch_bounds__(kVecThreads)
+k_moments_final(const double *__restrict__ partial, int n_blk, int R, int n,
+                double *__restrict__ Q)
+{
+    __shared__ double2 sm[kVecThreads];
+    int e = blockIdx.x, a = 0;
+    while (e >= n - a) {
+        e -= n - a;
+        ++a;
+    }
+    const int b = a + e;
+    const int stride = 1 + R * (R + 1) / 2;
+    // index of (a, b) in a workgroup's upper triangle
+    auto tri = [R](int x, int y) { return 1 + x * R - x * (x - 1) / 2 + (y - x); };
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < n_blk; k += kVecThreads) {
+        const double *row = partial + (size_t)k * stride;
+        double v;
+        if (b < R)
+            v = row[tri(a, b)];
+        else if (a < R)
+            v = ((k >> (b - R)) & 1) ? row[tri(a, a)] : 0.0;
+        else
+            v = ((k >> (a - R)) & (k >> (b - R)) & 1) ? row[0] : 0.0;
+        acc += v;
+    }
+    const double2 tot = block_sum2(acc, 0.0, sm);
+    if (threadIdx.x == 0) {
+        Q[a * n + b] = tot.x;
+        Q[b * n + a] = tot.x;
+    }
+}
+
+// Eq. (17) from Q (spin-blocked qubits: site i up = i, down = i + ns):
+// Sz_i = (<n_i,up> - <n_i,dn>)/2,
+// <Sz_i Sz_j> = (Q[iu][ju] - Q[iu][jd] - Q[id][ju] + Q[id][jd]) / 4,
+// C_ij = <Sz_i Sz_j> - Sz_i Sz_j.
+__global__ void __launch_bounds__(kVecThreads)
+k_spin_corr(const double *__restrict__ Q, int ns, double *__restrict__ C, double *__restrict__ Sz)
+{
+    const int n = 2 * ns;
+    for (int e = threadIdx.x; e < ns * ns; e += blockDim.x) {
+        const int i = e / ns, j = e % ns;
+        const int iu = i, id = i + ns, ju = j, jd = j + ns;
+        const double ss = 0.25 * (Q[iu * n + ju] - Q[iu * n + jd] - Q[id * n + ju] + Q[id * n + jd]);
+        const double si = 0.5 * (Q[iu * n + iu] - Q[id * n + id]);
+        const double sj = 0.5 * (Q[ju * n + ju] - Q[jd * n + jd]);
+        C[e] = ss - si * sj;
+        if (j == 0)
+            Sz[i] = si;
+    }
+}
+
 // ------------------------------------------------------------ misc kernels --
 
 __global__ void k_init_basis(double2 *__restrict__ psi, uint64_t dim, uint64_t b0, uint32_t ilv)

@@ -190,6 +190,35 @@ class Hubbard:
                             ws.data_ptr(), ws.numel(), _stream())
         return torch.complex(out[0], out[1])
 
+    def overlap_grad(self, theta: torch.Tensor, ref: torch.Tensor):
+        """Overlap loss of Eq. (5)/(6): (f, F, df/dtheta) with F = |<ref|psi(theta)>|^2
+        and f = log10(1 - F), the gradient by the adjoint sweep."""
+        L = self._layers(theta)
+        _require_gpu(ref, "ref", torch.complex128)
+        if ref.numel() != self.dim:
+            raise ValueError("ref must hold 2^n amplitudes")
+        nb = abi.hubbard_workspace_size(self.handle, L, abi.HUBBARD_OP_OVERLAP_GRAD)
+        ws = torch.empty(nb, dtype=torch.uint8, device=theta.device)
+        out = torch.empty(2, dtype=torch.float64, device=theta.device)
+        grad = torch.empty(theta.numel(), dtype=torch.float64, device=theta.device)
+        abi.overlap_grad(self.handle, theta.data_ptr(), L, ref.data_ptr(), out.data_ptr(),
+                         grad.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+        return out[0], out[1], grad
+
+    def spin_correlation(self, psi: torch.Tensor):
+        """Eq. (17): (C, Sz) with C[i, j] = <Sz_i Sz_j> - <Sz_i><Sz_j>, Sz[i] = <Sz_i>."""
+        _require_gpu(psi, "psi", torch.complex128)
+        if psi.numel() != self.dim:
+            raise ValueError("psi must hold 2^n amplitudes")
+        ns = self.n_qubits // 2
+        nb = abi.hubbard_vector_workspace_size(self.handle, abi.HUBBARD_OP_SPIN_CORR)
+        ws = torch.empty(nb, dtype=torch.uint8, device=psi.device)
+        C = torch.empty((ns, ns), dtype=torch.float64, device=psi.device)
+        Sz = torch.empty(ns, dtype=torch.float64, device=psi.device)
+        abi.hubbard_spin_correlation(self.handle, psi.data_ptr(), C.data_ptr(), Sz.data_ptr(),
+                                     ws.data_ptr(), ws.numel(), _stream())
+        return C, Sz
+
     def lanczos(self, start: torch.Tensor | None = None, *, max_iter: int = 400,
                 tol: float = 1e-10, want_state: bool = False, seed: int = 7):
         """Ground state of H in the particle-number sector of `start` (default:

@@ -1,5 +1,6 @@
 """Write tests/golden/c5_4x4_periodic_U8.json: the oracle's energy, full
-adjoint gradient and sampled amplitudes of the 4x4 periodic, U = 8,
+adjoint gradient, sampled amplitudes and spin correlations (Eq. (17)) of
+the 4x4 periodic, U = 8,
 16-layer (80-parameter) 32-qubit circuit at the seeded benchmark angles.
 
 Calls only oracle/ (its particle-number sector form: the state of Eq. (3)
@@ -49,6 +50,7 @@ def main():
     pos = np.searchsorted(sector.indices(om), np.array(idx, dtype=np.uint64))
     amps = psi[pos]
     norm = float(np.vdot(psi, psi).real)
+    C, Sz = sector.spin_correlation(om, psi)
     del psi
     E, g = sector.energy_grad(om, w.theta, w.layers)
     t2 = time.time()
@@ -66,6 +68,8 @@ def main():
         "amp_index": idx,
         "amp_re": [float(a.real) for a in amps],
         "amp_im": [float(a.imag) for a in amps],
+        "spin_corr": [[float(v) for v in row] for row in C],
+        "sz": [float(v) for v in Sz],
         "oracle_threads": core.threads(),
         "oracle_seconds": {"ansatz": t1 - t0, "energy_grad": t2 - t1},
     }

@@ -97,6 +97,10 @@ def test_bench_theta_vs_oracle_32q(c5):
     want = np.array(gold["amp_re"]) + 1j * np.array(gold["amp_im"])
     assert np.max(np.abs(got - want)) <= AMP_TOL
     assert np.max(np.abs(want)) > 1e-5   # the samples are not all trivial
+    say("[32q] bench theta: spin correlations (Eq. (17)) of the 64 GiB state")
+    C, Sz = m.spin_correlation(psi)
+    assert np.max(np.abs(C.cpu().numpy() - np.array(gold["spin_corr"]))) <= 1e-12
+    assert np.max(np.abs(Sz.cpu().numpy() - np.array(gold["sz"]))) <= 1e-12
 
 
 def test_free_fermion_32q(c5):

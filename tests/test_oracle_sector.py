@@ -113,3 +113,11 @@ def test_sector_periodic_4x4_low_filling(oracle_lib):
         pos = np.searchsorted(idx, cols)
         assert np.array_equal(idx[pos], cols)   # H keeps the sector
         assert abs(phi[i] - np.sum(coefs * psi[pos])) <= 1e-13
+
+
+def test_sector_spin_correlation_equals_full_space(oracle_lib):
+    om = make_model(2, 3, U=4.0, V=np.full(7, 0.3))
+    th = rng_theta(21, 2 * om.params_per_layer)
+    C, Sz = core.spin_correlation(om, core.ansatz(om, th, 2))
+    Cs, Szs = sector.spin_correlation(om, sector.ansatz(om, th, 2), chunk=100)
+    assert np.max(np.abs(C - Cs)) <= 1e-14 and np.max(np.abs(Sz - Szs)) <= 1e-14
