@@ -81,6 +81,9 @@ def lib():
         L.orc_overlap_grad.argtypes = [P(_Model), vp, ci, cu64, vp, vp, vp]
         L.orc_overlap_grad.restype = ci
         L.orc_spin_correlation.argtypes = [P(_Model), vp, vp, vp]
+        L.orc_np_ansatz.argtypes = [P(_Model), ci, vp, vp, vp, ci, cu64, vp]
+        L.orc_np_energy_grad.argtypes = [P(_Model), ci, vp, vp, vp, ci, cu64, P(cd), vp]
+        L.orc_np_energy_grad.restype = ci
         L.orc_set_threads.argtypes = [ci]
         _lib = L
     return _lib
@@ -267,3 +270,56 @@ def spin_correlation(m: OracleModel, psi: np.ndarray):
     Sz = np.zeros(m.nsites)
     lib().orc_spin_correlation(ctypes.byref(_cmodel(m)), _ptr(psi), _ptr(C), _ptr(Sz))
     return C, Sz
+
+
+def np_terms(m: OracleModel):
+    """Qubit pairs of one NP layer in application order (Sec. 2.2.1): the
+    two spin qubits of every site, then each hopping group's bonds (group
+    order, bond order), spin up then spin down."""
+    terms = [(m.qubit(i, 0), m.qubit(i, 1)) for i in range(m.nsites)]
+    slots = m.bond_slot()
+    for g in range(1, m.ngroups + 1):
+        for (i, j), s in zip(m.bonds, slots):
+            if s == g:
+                for spin in (0, 1):
+                    a, b = m.qubit(i, spin), m.qubit(j, spin)
+                    terms.append((min(a, b), max(a, b)))
+    return terms
+
+
+def np_n_params(m: OracleModel, layers: int) -> int:
+    return m.nqubits + 2 * len(np_terms(m)) * layers
+
+
+def _np_args(m):
+    t = np_terms(m)
+    pp = np.ascontiguousarray([a for a, _ in t], dtype=np.int32)
+    qq = np.ascontiguousarray([b for _, b in t], dtype=np.int32)
+    return len(t), pp, qq
+
+
+def np_ansatz(m: OracleModel, theta, layers: int, b0: int | None = None) -> np.ndarray:
+    """State of the NP circuit (R_z layer included, exact R_z)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    nt, pp, qq = _np_args(m)
+    if th.size != m.nqubits + 2 * nt * layers:
+        raise ValueError("theta must hold n_qubits + 2 * terms * layers values")
+    psi = _vec(m)
+    b0 = m.neel_index() if b0 is None else b0
+    lib().orc_np_ansatz(ctypes.byref(_cmodel(m)), nt, _ptr(pp), _ptr(qq), _ptr(th), layers, b0,
+                        _ptr(psi))
+    return psi
+
+
+def np_energy_grad(m: OracleModel, theta, layers: int, b0: int | None = None):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    nt, pp, qq = _np_args(m)
+    if th.size != m.nqubits + 2 * nt * layers:
+        raise ValueError("theta must hold n_qubits + 2 * terms * layers values")
+    g = np.zeros(th.size)
+    E = ctypes.c_double()
+    b0 = m.neel_index() if b0 is None else b0
+    if lib().orc_np_energy_grad(ctypes.byref(_cmodel(m)), nt, _ptr(pp), _ptr(qq), _ptr(th),
+                                layers, b0, ctypes.byref(E), _ptr(g)):
+        raise MemoryError("oracle np_energy_grad: allocation failed")
+    return E.value, g

@@ -787,3 +787,128 @@ void orc_spin_correlation(const orc_model *m, const cplx *psi, double *C, double
     free(s1);
     free(sz);
 }
+
+/* ------------------------------------------- NP ansatz, Eq. (8) -------- */
+
+/* The number-preserving (NP) ansatz of Sec. 2.2.1: R_z(theta) on every qubit
+ * before the first layer, then per layer one two-qubit gate U_NP(theta, phi)
+ * (Eq. (8)) on every pair of qubits that a term of Eq. (1) couples: the two
+ * spin qubits of every site (on-site terms), then every bond of every
+ * hopping group, spin up then spin down.  In fermionic form, with the
+ * Jordan-Wigner string that the paper's fermionic swaps supply,
+ *   U_NP(theta, phi) = exp(i theta (a+_p a_q + a+_q a_p)) exp(i phi n_p n_q),
+ * the rotation acting on the one-electron pair states and the phase on the
+ * doubly occupied one; R_z(theta) = exp(-i theta Z / 2), Z = 1 - 2 n.
+ * Parameters: [R_z of qubit 0..n-1], then per layer per term (theta, phi) in
+ * the order above.  The term list (pairs of qubits) is passed in: np_p[k],
+ * np_q[k] for k < n_terms (one layer). */
+
+/* psi <- exp(-i theta coef [all bits of mask set]) psi */
+static void apply_mask_phase(int n, uint64_t mask, double coef, double theta, cplx *psi)
+{
+    const uint64_t dim = (uint64_t)1 << n;
+    const cplx ph = cos(theta * coef) - I * sin(theta * coef);
+#pragma omp parallel for schedule(static)
+    for (int64_t bs = 0; bs < (int64_t)dim; bs++)
+        if (((uint64_t)bs & mask) == mask)
+            psi[bs] *= ph;
+}
+
+/* psi <- R_z(theta) on qubit q: exp(-i theta/2) on |0>, exp(i theta/2) on |1> */
+static void apply_rz(int n, int q, double theta, cplx *psi)
+{
+    const uint64_t dim = (uint64_t)1 << n;
+    const cplx p0 = cos(0.5 * theta) - I * sin(0.5 * theta);
+    const cplx p1 = cos(0.5 * theta) + I * sin(0.5 * theta);
+#pragma omp parallel for schedule(static)
+    for (int64_t bs = 0; bs < (int64_t)dim; bs++)
+        psi[bs] *= bit((uint64_t)bs, q) ? p1 : p0;
+}
+
+/* Gate k of the NP circuit (k indexes theta): k < n is R_z of qubit k; then
+ * per layer per term two gates, the rotation (even k - n) and the phase. */
+static void np_apply(const orc_model *m, int nt, const int32_t *np_p, const int32_t *np_q, int k,
+                     double theta, cplx *psi)
+{
+    const int n = nqubits(m);
+    if (k < n) {
+        apply_rz(n, k, theta, psi);
+        return;
+    }
+    const int r = (k - n) % (2 * nt), term = r / 2;
+    const int p = np_p[term], q = np_q[term];
+    if (r % 2 == 0)
+        apply_hop_term(n, p, q, -1.0, theta, psi);   /* exp(i theta K) */
+    else
+        apply_mask_phase(n, ((uint64_t)1 << p) | ((uint64_t)1 << q), -1.0, theta, psi);
+}
+
+/* out = G_k psi, the generator of gate k written as exp(-i theta G_k):
+ * Z/2 for R_z, -K for the rotation, -n_p n_q for the phase. */
+static void np_generator(const orc_model *m, int nt, const int32_t *np_p, const int32_t *np_q,
+                         int k, const cplx *psi, cplx *out)
+{
+    const int n = nqubits(m);
+    const uint64_t dim = (uint64_t)1 << n;
+    if (k < n) {
+#pragma omp parallel for schedule(static)
+        for (int64_t bs = 0; bs < (int64_t)dim; bs++)
+            out[bs] = (bit((uint64_t)bs, k) ? -0.5 : 0.5) * psi[bs];
+        return;
+    }
+    const int r = (k - n) % (2 * nt), term = r / 2;
+    const int p = np_p[term], q = np_q[term];
+    if (r % 2 == 0) {
+        memset(out, 0, dim * sizeof(cplx));
+        add_hop_term(n, p, q, -1.0, psi, out);
+    } else {
+        const uint64_t mask = ((uint64_t)1 << p) | ((uint64_t)1 << q);
+#pragma omp parallel for schedule(static)
+        for (int64_t bs = 0; bs < (int64_t)dim; bs++)
+            out[bs] = (((uint64_t)bs & mask) == mask) ? -psi[bs] : 0.0;
+    }
+}
+
+void orc_np_ansatz(const orc_model *m, int nt, const int32_t *np_p, const int32_t *np_q,
+                   const double *theta, int layers, uint64_t b0, cplx *psi)
+{
+    const int P = nqubits(m) + 2 * nt * layers;
+    orc_init_basis(m, b0, psi);
+    for (int k = 0; k < P; k++)
+        np_apply(m, nt, np_p, np_q, k, theta[k], psi);
+}
+
+/* E and dE/dtheta of the NP circuit by the adjoint recursion (as
+ * orc_energy_grad).  Returns 0 or -1 (allocation). */
+int orc_np_energy_grad(const orc_model *m, int nt, const int32_t *np_p, const int32_t *np_q,
+                       const double *theta, int layers, uint64_t b0, double *E, double *grad)
+{
+    const int n = nqubits(m);
+    const uint64_t dim = (uint64_t)1 << n;
+    const int P = n + 2 * nt * layers;
+    cplx *psi = malloc(dim * sizeof(cplx));
+    cplx *lam = malloc(dim * sizeof(cplx));
+    cplx *tmp = malloc(dim * sizeof(cplx));
+    if (!psi || !lam || !tmp) {
+        free(psi);
+        free(lam);
+        free(tmp);
+        return -1;
+    }
+    orc_np_ansatz(m, nt, np_p, np_q, theta, layers, b0, psi);
+    orc_ham_apply(m, psi, lam);
+    double re, im;
+    orc_inner(n, psi, lam, &re, &im);
+    *E = re;
+    for (int k = P - 1; k >= 0 && grad; k--) {
+        np_generator(m, nt, np_p, np_q, k, psi, tmp);
+        orc_inner(n, lam, tmp, &re, &im);
+        grad[k] = 2.0 * im;
+        np_apply(m, nt, np_p, np_q, k, -theta[k], psi);
+        np_apply(m, nt, np_p, np_q, k, -theta[k], lam);
+    }
+    free(psi);
+    free(lam);
+    free(tmp);
+    return 0;
+}
