@@ -18,6 +18,9 @@
  * groups split the bonds into sets of mutually commuting terms.  Parameters
  * are layer-major: theta[l * params_per_layer + slot], slot 0 = D.
  *
+ * hubbard_set_ansatz selects the number-preserving ansatz of Eq. (8)
+ * instead (its parameter layout is described there).
+ *
  * Encoding (Sec. 2.2.1): Jordan-Wigner with a_q = (prod_{r<q} Z_r) sigma^-_q;
  * sites are row-major s = x*ny + y; qubit q = s + nsites*spin (spin 0 = up),
  * i.e. all spin-up qubits below all spin-down qubits; bit q of an amplitude
@@ -139,6 +142,28 @@ typedef struct {
 } hubbard_graph_desc;
 
 hubbard_status hubbard_create_graph(const hubbard_graph_desc *desc, hubbard_t *out);
+
+/* The ansatz of the circuit (every later call that applies it):
+ *   HUBBARD_ANSATZ_HVA (default)  the Hamiltonian-variational layer of
+ *       Eq. (7): params_per_layer = 1 + n_groups, no leading parameters.
+ *   HUBBARD_ANSATZ_NP  the number-preserving ansatz of Eq. (8) (Sec. 2.2.1):
+ *       before the first layer R_z on every qubit, applied as the phase gate
+ *       exp(i th n_q) (R_z up to a global phase, which changes no energy,
+ *       gradient or overlap magnitude); then per layer one
+ *       U_NP(theta, phi) = exp(i theta (a+_p a_q + a+_q a_p)) exp(i phi n_p n_q)
+ *       (the matrix of Eq. (8) in Jordan-Wigner form, the fermionic swaps
+ *       of the paper's circuit supplied by the string sign) on every pair
+ *       of qubits that a term of Eq. (1) couples: the up and down qubits of
+ *       every site (in site order), then every bond of every hopping group
+ *       in group and bond order, spin up then spin down.  Parameters:
+ *       n_qubits R_z angles, then per layer (theta, phi) of each term in
+ *       that order: params_per_layer = 2 (n_sites + 2 n_bonds).
+ * The parameter count of n_layers is hubbard_param_count (energy,
+ * energy_grad, the batch and the optimiser use it).  Drops the handle's
+ * plans and every planned batch that includes it (like hubbard_set_tiles). */
+enum { HUBBARD_ANSATZ_HVA = 0, HUBBARD_ANSATZ_NP = 1 };
+hubbard_status hubbard_set_ansatz(hubbard_t h, int32_t ansatz);
+hubbard_status hubbard_param_count(hubbard_t h, int32_t n_layers, int64_t *count);
 
 /* Release the handle and its device tables (synchronises nothing; the caller
  * must not destroy a handle with work still queued on a stream). */

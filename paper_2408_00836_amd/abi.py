@@ -27,6 +27,8 @@ HUBBARD_OP_OVERLAP = 2
 HUBBARD_OP_LANCZOS = 3
 HUBBARD_OP_OVERLAP_GRAD = 4
 HUBBARD_OP_SPIN_CORR = 5
+HUBBARD_ANSATZ_HVA = 0
+HUBBARD_ANSATZ_NP = 1
 
 # Every symbol the headers in include/ declare.
 EXPORTED = [
@@ -40,7 +42,7 @@ EXPORTED = [
     "energy_grad_noalloc", "hubbard_vector_workspace_size", "hubbard_overlap", "hubbard_lanczos",
     "hubbard_tridiag_lowest", "hubbard_vqe_workspace_size", "hubbard_vqe", "hubbard_lbfgs_create",
     "hubbard_lbfgs_tell", "hubbard_lbfgs_result", "hubbard_lbfgs_destroy", "overlap_grad",
-    "hubbard_spin_correlation",
+    "hubbard_spin_correlation", "hubbard_set_ansatz", "hubbard_param_count",
 ]
 
 
@@ -149,6 +151,8 @@ def lib() -> ctypes.CDLL:
             "hubbard_lbfgs_destroy": ([vp], None),
             "overlap_grad": ([vp, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp], st),
             "hubbard_spin_correlation": ([vp, vp, vp, vp, vp, ctypes.c_size_t, vp], st),
+            "hubbard_set_ansatz": ([vp, i32], st),
+            "hubbard_param_count": ([vp, i32, P(i64)], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -496,3 +500,13 @@ def hubbard_spin_correlation(h: int, psi_dev: int, C_dev: int, Sz_dev: int, ws_d
                              ws_bytes: int, stream: int = 0) -> None:
     _check(lib().hubbard_spin_correlation(h, psi_dev, C_dev, Sz_dev, ws_dev, int(ws_bytes),
                                           stream))
+
+
+def hubbard_set_ansatz(h: int, ansatz: int) -> None:
+    _check(lib().hubbard_set_ansatz(h, int(ansatz)))
+
+
+def hubbard_param_count(h: int, n_layers: int) -> int:
+    n = ctypes.c_int64()
+    _check(lib().hubbard_param_count(h, int(n_layers), ctypes.byref(n)))
+    return n.value

@@ -194,7 +194,8 @@ struct Builder {
             P.flags = hp.flags;
             P.op_begin = (int)ops.size();
             const uint64_t ntiles = (uint64_t)1 << nf;
-            const bool two = dual && !m.general && P.k >= kRegBits && nf >= 1;
+            // (the HVA circuit only: NP passes carry many per-register phases)
+            const bool two = dual && !m.general && m.ansatz == 0 && P.k >= kRegBits && nf >= 1;
             const int grid = (int)pass_grid(two ? ntiles / 2 : ntiles);
             std::map<int, int> red_of;
             P.red_base = (int)row_param.size();
@@ -240,6 +241,11 @@ struct Builder {
                     for (int b = lo + 1; b < hi; ++b)
                         bw |= 1u << b;
                     o.between = bw;
+                    o.t = h.t;
+                } else if (h.kind == OP_MASK) {
+                    op_pl.push_back(-1);
+                    op_ql.push_back(-1);
+                    o.between = h.qmask;
                     o.t = h.t;
                 } else {
                     op_pl.push_back(-1);
@@ -454,7 +460,7 @@ hubbard_status upload_program(hubbard_model *h, DeviceState &ds, Program &pr)
         if (max_of(*l) > lim)
             return fail(HUBBARD_ERR_ARG, "a pass needs more LDS than a workgroup may use; "
                                          "choose smaller tiles");
-    const int P = pr.layers * m.params_per_layer();
+    const int P = m.n_params(pr.layers);
     // reduction map: output 0 = E, outputs 1..P = gradient
     pr.n_out = (pr.kind == PROG_GRAD) ? 1 + P : 1;
     std::vector<std::vector<int>> rows_of(pr.n_out);
@@ -855,7 +861,7 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
     size_t n_out = n;
     for (int i = 0; i < n; ++i) {
         gbase[i] = n_out;
-        n_out += (size_t)progs[i]->layers * hs[i]->m.params_per_layer();
+        n_out += (size_t)hs[i]->m.n_params(progs[i]->layers);
     }
     std::vector<std::vector<std::pair<int64_t, int32_t>>> segs(n_out);
     L.scale.assign(n_out, 2.0);
@@ -863,7 +869,7 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
     for (int i = 0; i < n; ++i) {
         L.scale[i] = 1.0;
         L.out_idx[i] = i;
-        const size_t P = (size_t)progs[i]->layers * hs[i]->m.params_per_layer();
+        const size_t P = (size_t)hs[i]->m.n_params(progs[i]->layers);
         for (size_t p = 0; p < P; ++p)
             L.out_idx[gbase[i] + p] = toff[i] + (int64_t)p;
     }
@@ -1729,6 +1735,31 @@ hubbard_status hubbard_set_tiles(hubbard_t h, int32_t fwd_k, int32_t rev_k, int3
     return HUBBARD_OK;
 }
 
+hubbard_status hubbard_set_ansatz(hubbard_t h, int32_t ansatz)
+{
+    if (!h || (ansatz != HUBBARD_ANSATZ_HVA && ansatz != HUBBARD_ANSATZ_NP))
+        return fail(HUBBARD_ERR_ARG, "ansatz must be HUBBARD_ANSATZ_HVA or HUBBARD_ANSATZ_NP");
+    evict_batches_of(h->uid);   // lock order: the batch cache before a handle
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (h->m.ansatz == ansatz)
+        return HUBBARD_OK;
+    h->m.ansatz = ansatz;
+    ++h->gen;
+    for (auto &kv : h->dev)
+        kv.second.progs.clear();
+    std::lock_guard<std::mutex> lk2(h->plan_mu);
+    h->fwd_plans.clear();
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_param_count(hubbard_t h, int32_t n_layers, int64_t *count)
+{
+    if (!h || n_layers < 0 || !count)
+        return fail(HUBBARD_ERR_ARG, "bad arguments to hubbard_param_count");
+    *count = h->m.n_params(n_layers);
+    return HUBBARD_OK;
+}
+
 hubbard_status hubbard_get_tiles(hubbard_t h, int32_t *cfg)
 {
     if (!h || !cfg)
@@ -1761,7 +1792,7 @@ hubbard_status hubbard_tune(hubbard_t h, int32_t n_layers, const double *theta_d
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(HUBBARD_ERR_DEVICE, "creating tuning events");
     double *E = nullptr, *g = nullptr;
-    const int P = n_layers * h->m.params_per_layer();
+    const int P = h->m.n_params(n_layers);
     if (hipMalloc((void **)&E, sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&g, sizeof(double) * (size_t)P) != hipSuccess) {
         (void)hipFree(E);
@@ -2168,7 +2199,7 @@ LbfgsOptions vqe_options(const hubbard_vqe_opts *o)
 
 size_t vqe_eval_bytes(hubbard_t h, int32_t n_layers, int32_t n_starts)
 {
-    const size_t P = (size_t)n_layers * h->m.params_per_layer();
+    const size_t P = (size_t)h->m.n_params(n_layers);
     return align256((size_t)n_starts * sizeof(double)) +
            align256((size_t)n_starts * P * sizeof(double));
 }
@@ -2216,7 +2247,7 @@ hubbard_status hubbard_vqe(hubbard_t h, int32_t n_layers, int32_t n_starts, doub
     need = eng + vqe_eval_bytes(h, n_layers, n_starts);
     if (ws_bytes < need)
         return fail(HUBBARD_ERR_SIZE, "workspace too small for hubbard_vqe");
-    const int P = n_layers * h->m.params_per_layer();
+    const int P = h->m.n_params(n_layers);
     hipStream_t s = (hipStream_t)stream;
     double *E_dev = (double *)((char *)ws_dev + eng);
     double *G_dev = (double *)((char *)E_dev + align256((size_t)n_starts * sizeof(double)));
@@ -2393,7 +2424,7 @@ hubbard_status overlap_grad(hubbard_t h, const double *theta_dev, int32_t n_laye
         return st;
     if ((st = run_reduce(*pr, partial, spare, grad_dev, s)) != HUBBARD_OK)
         return st;
-    const int P = n_layers * h->m.params_per_layer();
+    const int P = h->m.n_params(n_layers);
     hipLaunchKernelGGL(k_overlap_finish, dim3(1), dim3(kVecThreads), 0, s, (const double2 *)c,
                        grad_dev, P, out_dev);
     return check_launch("overlap_grad");

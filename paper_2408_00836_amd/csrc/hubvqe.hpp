@@ -26,7 +26,8 @@ constexpr int kDiagTab = kMaxSites + 1;   // U-count phase table entries
 
 enum OpKind : int32_t {
     OP_DIAG = 0,   // diagonal sub-term: U and eps of a set of sites, V of a set of bonds
-    OP_HOP = 1     // one hopping term (a+_p a_q + h.c.) of one bond and spin
+    OP_HOP = 1,    // one hopping term (a+_p a_q + h.c.) of one bond and spin
+    OP_MASK = 2    // diagonal coef * [every qubit of a mask occupied] (NP phases, R_z)
 };
 
 enum PassFlags : int32_t {
@@ -44,10 +45,11 @@ struct DevOp {
     int32_t kind;
     int32_t pair;       // HOP: register-bit pair (0..5: 01 02 03 12 13 23) in its phase
     uint32_t flip;      // HOP: bit j = parity of register j's global bits in `between`
-    uint32_t between;   // HOP: global bits strictly between p and q (Jordan-Wigner string)
+    uint32_t between;   // HOP: global bits strictly between p and q (Jordan-Wigner string);
+                        // MASK: the global bits that must all be set
     int32_t red;        // reduction row within the pass (-1: none)
     int32_t dtab;       // DIAG: index of its phase table within the pass
-    double t;           // HOP: bond hopping t_b
+    double t;           // HOP: bond hopping t_b; MASK: coefficient
     int32_t param;      // theta index (-1 for Hamiltonian terms)
     uint32_t umask;     // DIAG: spin-up qubits of the sites whose U term it carries
     uint32_t emask;     // DIAG: qubits whose eps term it carries
@@ -222,8 +224,14 @@ struct Model {
     double U = 0.0;
     uint64_t neel = 0;
     bool general = false;            // any eps or V nonzero
+    int ansatz = 0;                  // 0: HVA layer of Eq. (7); 1: NP ansatz of Eq. (8)
     int qubit(int site, int spin) const { return site + ns * spin; }
-    int params_per_layer() const { return 1 + ngroups; }
+    // NP: one U_NP(theta, phi) per on-site pair and per bond and spin
+    int np_terms() const { return ns + 2 * nb; }
+    int params_per_layer() const { return ansatz == 1 ? 2 * np_terms() : 1 + ngroups; }
+    // NP: R_z angles of every qubit before the first layer
+    int lead_params() const { return ansatz == 1 ? nq : 0; }
+    int n_params(int layers) const { return lead_params() + layers * params_per_layer(); }
 };
 
 // Lowest eigenvalue of the symmetric tridiagonal matrix with diagonal
@@ -292,9 +300,9 @@ std::string build_graph_model(int n_sites, int n_bonds, const int32_t *bi, const
 struct HostOp {
     int kind = OP_DIAG;
     int param = -1;
-    uint32_t qmask = 0;     // qubits it touches (ordering constraints)
+    uint32_t qmask = 0;     // qubits it touches (ordering constraints); MASK: its mask
     int p = -1, q = -1;     // HOP qubits, p < q
-    double t = 0.0;
+    double t = 0.0;         // HOP: t_b; MASK: coefficient
     uint32_t umask = 0, emask = 0;
     std::vector<int> vbonds;
 };

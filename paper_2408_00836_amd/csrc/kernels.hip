@@ -474,6 +474,11 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const PhT *__restrict
                     double s, c;
                     sincos(theta[op.param] * op.t, &s, &c);
                     opc[o] = make_double2(c, sign * s);
+                } else if (op.kind == OP_MASK) {
+                    // exp(-i sign th coef) on the amplitudes with every mask bit set
+                    double s, c;
+                    sincos(theta[op.param] * op.t, &s, &c);
+                    opc[o] = make_double2(c, -sign * s);
                 }
             }
             if constexpr (!GEN) {
@@ -669,6 +674,42 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const PhT *__restrict
                             } else {
                                 eacc += diag_value<GEN>(op, g, M, vb, etab + op.dtab * 128) *
                                         (a.x * a.x + a.y * a.y);
+                            }
+                        }
+                    }
+                } else if (op.kind == OP_MASK) {
+                    // coef * [every bit of the mask set]: the phase (fwd/rev)
+                    // on those registers, and in the reverse the bracket
+                    // coef * sum Im(conj(lambda) psi) over them
+                    if constexpr (MODE == M_FWD || MODE == M_REV) {
+                        const double2 ph = opc[o];
+                        const uint32_t mask = op.between;
+                        // the mask's bits among the phase's register bits
+                        // select registers (uniform), the rest select threads
+                        uint32_t mreg = 0, rbits = 0;
+#pragma unroll
+                        for (int i = 0; i < kRegBits; ++i) {
+                            rbits |= L.gb[i];
+                            if (L.gb[i] & mask)
+                                mreg |= 1u << i;
+                        }
+                        const uint32_t mthr = mask & ~rbits;
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            if ((gthr[t] & mthr) != mthr)
+                                continue;
+#pragma unroll
+                            for (int j = 0; j < kRegs; ++j) {
+                                if (((uint32_t)j & mreg) != mreg)
+                                    continue;
+                                if (!FULL && !((valid >> j) & 1u))
+                                    continue;
+                                double2 &a = v[t * NV][j];
+                                if constexpr (MODE == M_REV) {
+                                    racc += op.t * im_conj_mul(v[1][j], a);
+                                    v[1][j] = cmul(v[1][j], ph);
+                                }
+                                a = cmul(a, ph);
                             }
                         }
                     }

@@ -28,9 +28,12 @@ namespace {
 
 inline uint32_t qbit(int q) { return 1u << q; }
 
+// Diagonal ops (OP_DIAG, OP_MASK) commute with each other and fit any tile.
+inline bool diagonal(const HostOp &o) { return o.kind != OP_HOP; }
+
 bool conflicts(const HostOp &a, const HostOp &b)
 {
-    if (a.kind == OP_DIAG && b.kind == OP_DIAG)
+    if (diagonal(a) && diagonal(b))
         return false;
     return (a.qmask & b.qmask) != 0;
 }
@@ -59,7 +62,7 @@ Closure grow(const std::vector<HostOp> &ops, const std::vector<int> &active,
             if (in[i])
                 continue;
             const HostOp &o = ops[i];
-            if (o.kind == OP_DIAG) {
+            if (diagonal(o)) {
                 if (o.qmask & bg)
                     bd |= o.qmask;
                 else
@@ -88,12 +91,12 @@ Closure grow(const std::vector<HostOp> &ops, const std::vector<int> &active,
     uint32_t bg = 0, bd = 0;
     for (int i : active) {
         const HostOp &o = ops[i];
-        bool ok = in[i] && !(o.qmask & bg) && (o.kind == OP_DIAG || !(o.qmask & bd));
+        bool ok = in[i] && !(o.qmask & bg) && (diagonal(o) || !(o.qmask & bd));
         if (ok) {
             cl.inc.push_back(i);
             if (o.kind == OP_HOP)
                 ++cl.hops;
-        } else if (o.kind == OP_DIAG) {
+        } else if (diagonal(o)) {
             bd |= o.qmask;
         } else {
             bg |= o.qmask;
@@ -149,8 +152,56 @@ void merge_diagonals(std::vector<HostOp> &ops)
 
 }  // namespace
 
+// The NP circuit of Eq. (8) (Sec. 2.2.1): R_z on every qubit, as the phase
+// gate exp(i th n_q) (R_z up to a global phase), then per layer, for every
+// on-site pair and then every bond of every hopping group (spin up, then
+// spin down), U_NP(theta, phi) = exp(i theta K_pq) exp(i phi n_p n_q): a
+// hopping rotation with t = 1 and a MASK phase with coefficient -1.
+std::vector<HostOp> np_circuit_ops(const Model &m, int layers)
+{
+    std::vector<HostOp> ops;
+    for (int q = 0; q < m.nq; ++q) {
+        HostOp d;
+        d.kind = OP_MASK;
+        d.param = q;
+        d.qmask = qbit(q);
+        d.t = -1.0;
+        ops.push_back(d);
+    }
+    int k = m.lead_params();
+    auto term = [&](int a, int c) {
+        HostOp h;
+        h.kind = OP_HOP;
+        h.param = k;
+        h.p = std::min(a, c);
+        h.q = std::max(a, c);
+        h.qmask = qbit(a) | qbit(c);
+        h.t = 1.0;
+        ops.push_back(h);
+        HostOp d;
+        d.kind = OP_MASK;
+        d.param = k + 1;
+        d.qmask = qbit(a) | qbit(c);
+        d.t = -1.0;
+        ops.push_back(d);
+        k += 2;
+    };
+    for (int l = 0; l < layers; ++l) {
+        for (int i = 0; i < m.ns; ++i)
+            term(m.qubit(i, 0), m.qubit(i, 1));
+        for (int s = 1; s <= m.ngroups; ++s)
+            for (int b = 0; b < m.nb; ++b)
+                if (m.slot[b] == s)
+                    for (int spin = 0; spin < 2; ++spin)
+                        term(m.qubit(m.bi[b], spin), m.qubit(m.bj[b], spin));
+    }
+    return ops;
+}
+
 std::vector<HostOp> circuit_ops(const Model &m, int layers)
 {
+    if (m.ansatz == 1)
+        return np_circuit_ops(m, layers);
     std::vector<HostOp> ops;
     const int per = m.params_per_layer();
     for (int l = 0; l < layers; ++l) {
@@ -235,7 +286,7 @@ std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig 
         uint32_t bg = 0, bd = 0;
         for (int i : active) {
             const HostOp &o = ops[i];
-            if (o.kind == OP_DIAG) {
+            if (diagonal(o)) {
                 if (o.qmask & bg)
                     bd |= o.qmask;
                 continue;
@@ -521,7 +572,7 @@ void plan_phases(HostPass &p)
             uint32_t bg = 0, bd = 0;
             for (int i : active) {
                 const HostOp &o = lops[i];
-                if (o.kind == OP_DIAG) {
+                if (diagonal(o)) {
                     if (o.qmask & bg)
                         bd |= o.qmask;
                     continue;

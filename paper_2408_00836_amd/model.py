@@ -33,14 +33,22 @@ class Hubbard:
     """One Hubbard model instance (Eq. (1)/(2)/(15)/(16)) and its HVA circuit."""
 
     def __init__(self, nx: int, ny: int, *, periodic_x: bool = False, periodic_y: bool = False,
-                 t=None, U: float = 0.0, V=None, eps=None, groups=None, tuned: bool = True,
-                 _handle=None):
-        """tuned: apply the autotuner's cached tile configuration for this
-        lattice and GPU when the cache has one (else the library defaults)."""
+                 t=None, U: float = 0.0, V=None, eps=None, groups=None, ansatz: str = "hva",
+                 tuned: bool = True, _handle=None):
+        """ansatz: "hva" (the Hamiltonian-variational layer of Eq. (7)) or "np"
+        (the number-preserving ansatz of Eq. (8), see hubbard_set_ansatz).
+        tuned: apply the autotuner's cached tile configuration for this
+        lattice, ansatz and GPU when the cache has one (else the library
+        defaults)."""
         self.handle = (_handle if _handle is not None else
                        abi.hubbard_create(nx, ny, periodic_x, periodic_y, t, U, V, eps, groups))
+        if ansatz not in ("hva", "np"):
+            raise ValueError("ansatz must be 'hva' or 'np'")
+        self.ansatz_kind = ansatz
+        if ansatz == "np":
+            abi.hubbard_set_ansatz(self.handle, abi.HUBBARD_ANSATZ_NP)
         self._ctor = dict(nx=nx, ny=ny, periodic_x=periodic_x, periodic_y=periodic_y, t=t, U=U,
-                          V=V, eps=eps, groups=groups)
+                          V=V, eps=eps, groups=groups, ansatz=ansatz)
         self.nx, self.ny = nx, ny
         self.periodic_x, self.periodic_y = bool(periodic_x), bool(periodic_y)
         # the diagonal has eps or V terms besides U (selects the general kernels)
@@ -71,13 +79,27 @@ class Hubbard:
                        groups=groups, site_spin=site_spin)
         return m
 
+    def set_ansatz(self, ansatz: str) -> None:
+        """Switch between "hva" and "np" (drops plans and cached workspaces)."""
+        if ansatz not in ("hva", "np"):
+            raise ValueError("ansatz must be 'hva' or 'np'")
+        abi.hubbard_set_ansatz(self.handle, abi.HUBBARD_ANSATZ_NP if ansatz == "np"
+                               else abi.HUBBARD_ANSATZ_HVA)
+        self.ansatz_kind = ansatz
+        self.params_per_layer = abi.hubbard_query(self.handle)["params_per_layer"]
+        self._ctor["ansatz"] = ansatz
+        self._ws.clear()
+        self._ws_bytes.clear()
+
     def noninteracting(self) -> "Hubbard":
         """The same lattice, hoppings and on-site energies with U = V = 0 (the
         non-interacting model whose optimum starts the interacting VQE,
         Sec. 2.1)."""
         a = dict(self._ctor, U=0.0, V=None)
         if a.pop("graph", False):
-            return Hubbard.graph(**a)
+            m = Hubbard.graph(**a)
+            m.set_ansatz(self.ansatz_kind)
+            return m
         return Hubbard(**a)
 
     def __del__(self):
@@ -97,7 +119,8 @@ class Hubbard:
         return 1 << self.n_qubits
 
     def n_params(self, layers: int) -> int:
-        return layers * self.params_per_layer
+        """Parameters of a circuit of `layers` layers (NP: the R_z angles first)."""
+        return abi.hubbard_param_count(self.handle, layers)
 
     def bonds(self):
         return abi.hubbard_bonds(self.handle)
@@ -127,15 +150,21 @@ class Hubbard:
             if ws.numel() >= nbytes and ws.device == dev and (key[1] == op or
                                                               op == abi.HUBBARD_OP_ENERGY):
                 return ws
+        # none fits: release this device's smaller ones first (at 32 qubits
+        # two gradient workspaces do not fit in HBM together)
+        for key in [k for k, w in self._ws.items() if w.device == dev]:
+            del self._ws[key]
+        torch.cuda.empty_cache()
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self._ws[(layers, op, str(dev))] = ws
         return ws
 
     def _layers(self, theta: torch.Tensor) -> int:
         _require_gpu(theta, "theta", torch.float64)
-        if theta.numel() % self.params_per_layer:
-            raise ValueError("theta length must be a multiple of params_per_layer")
-        return theta.numel() // self.params_per_layer
+        lead = self.n_params(0)
+        if theta.numel() < lead or (theta.numel() - lead) % self.params_per_layer:
+            raise ValueError("theta must hold n_params(layers) values")
+        return (theta.numel() - lead) // self.params_per_layer
 
     def new_state(self, device="cuda") -> torch.Tensor:
         psi = torch.empty(self.dim, dtype=torch.complex128, device=device)
@@ -226,8 +255,7 @@ class Hubbard:
         `seed`, a generic vector of the start state's sector).  Returns
         dict(E0, iters, residual, state)."""
         if start is None:
-            th = np.random.default_rng(seed).uniform(-np.pi / 8, np.pi / 8,
-                                                      2 * self.params_per_layer)
+            th = np.random.default_rng(seed).uniform(-np.pi / 8, np.pi / 8, self.n_params(2))
             start = self.ansatz(torch.tensor(th, dtype=torch.float64, device="cuda"))
         _require_gpu(start, "start", torch.complex128)
         if start.numel() != self.dim:

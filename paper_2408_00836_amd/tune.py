@@ -47,8 +47,9 @@ def gpu_name() -> str:
 
 def model_key(model) -> str:
     kind = "gen" if model.general else "u"
+    ans = "" if model.ansatz_kind == "hva" else f"/{model.ansatz_kind}"
     return (f"{model.nx}x{model.ny}/p{int(model.periodic_x)}{int(model.periodic_y)}/"
-            f"q{model.n_qubits}/{kind}/{gpu_name()}")
+            f"q{model.n_qubits}/{kind}{ans}/{gpu_name()}")
 
 
 def batch_key(models, layers) -> str:
@@ -93,9 +94,10 @@ def autotune(model, theta: torch.Tensor, *, proxy_layers: int | None = None, rep
     """Time the candidate tile configurations on this GPU, leave the best on
     the model and store it."""
     per = model.params_per_layer
-    L = theta.numel() // per
+    lead = model.n_params(0)
+    L = (theta.numel() - lead) // per
     Lt = min(L, proxy_layers) if proxy_layers else L
-    th = theta[: Lt * per].contiguous()
+    th = theta[: lead + Lt * per].contiguous()
     # psi, lambda and room for the partial rows of the smallest-tile candidate
     need = abi.hubbard_workspace_size(model.handle, Lt, abi.HUBBARD_OP_ENERGY_GRAD) + (32 << 20)
     ws = next((w for w in model._ws.values() if w.numel() >= need and w.device == theta.device),
