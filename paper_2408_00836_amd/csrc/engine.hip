@@ -21,11 +21,11 @@
 #include "hubvqe.hpp"
 
 namespace hv {
-template <int MODE, bool GEN, bool FULL, int NT, bool START = false>
+template <int MODE, bool GEN, bool FULL, int NT, bool START = false, int OPS = OPS_HVA>
 __global__ void k_pass(DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,
                        const DevModel *, double2 *, double2 *, double *, int, uint32_t);
 __global__ void k_init_basis(double2 *, uint64_t, uint64_t, uint32_t);
-template <int MODE, bool GEN, bool FULL, bool START>
+template <int MODE, bool GEN, bool FULL, bool START, int OPS = OPS_HVA>
 __global__ void k_batch_pass(const DevInstance *, const DevPass *, const DevWork *, double *);
 __global__ void k_reduce_seg(const double *, const int32_t *, const int64_t *, const int32_t *,
                              const double *, const int64_t *, int, double *, double *);
@@ -88,6 +88,7 @@ struct Program {
     int kind = 0;
     int layers = 0;
     bool general = false;   // diagonal has eps or V terms
+    bool np = false;        // NP circuit: gate passes hold hopping terms and mask phases
     PassList fwd, ham, rev, exp;
     // device tables
     DevOp *d_ops = nullptr;
@@ -415,6 +416,7 @@ void plan_program(hubbard_model *h, int kind, int layers, int smem_limit, Progra
     pr.kind = kind;
     pr.layers = layers;
     pr.general = m.general;
+    pr.np = m.ansatz != 0;
     if (kind != PROG_HAM)
         pr.h_fwd = cached_forward(h, layers, h->fwd_tc);
     TileConfig tc2 = h->rev_tc;
@@ -542,7 +544,13 @@ hubbard_status ensure_model(hubbard_model *h, int dev, DeviceState &ds)
             (const void *)k_pass<M_FWD, true, true, 1, true>,
             (const void *)k_pass<M_FWD, false, false, 1, true>,
             (const void *)k_pass<M_FWD, true, false, 1, true>,
-            (const void *)k_pass<M_FWD, false, true, 2, true>};
+            (const void *)k_pass<M_FWD, false, true, 2, true>,
+            (const void *)k_pass<M_FWD, false, true, 1, false, OPS_NP>,
+            (const void *)k_pass<M_FWD, false, true, 1, true, OPS_NP>,
+            (const void *)k_pass<M_REV, false, true, 1, false, OPS_NP>,
+            (const void *)k_pass<M_FWD, false, false, 1, false, OPS_NP>,
+            (const void *)k_pass<M_FWD, false, false, 1, true, OPS_NP>,
+            (const void *)k_pass<M_REV, false, false, 1, false, OPS_NP>};
         for (const void *f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     });
@@ -658,10 +666,30 @@ void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, c
         // tiles of >= 16 amplitudes fill every register of every thread
         const bool full = pl.pass[i].k >= kRegBits;
         const bool two = pl.nt[i] == 2;
-#define HV_LAUNCH(GEN, FULL, NT, ST)                                                            \
-    hipLaunchKernelGGL((k_pass<MODE, GEN, FULL, NT, ST>), dim3(pl.grid[i]), dim3(pl.threads[i]),\
-                       pl.smem[i], s, P, pr.d_phases, pr.d_ops, pr.d_vb, theta,                 \
-                       ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax, vl.ilv)
+#define HV_LAUNCH_OPS(GEN, FULL, NT, ST, OPS)                                                   \
+    hipLaunchKernelGGL((k_pass<MODE, GEN, FULL, NT, ST, OPS>), dim3(pl.grid[i]),               \
+                       dim3(pl.threads[i]), pl.smem[i], s, P, pr.d_phases, pr.d_ops, pr.d_vb,   \
+                       theta, ds.d_model, (double2 *)a, (double2 *)b, partial, kGridMax, vl.ilv)
+#define HV_LAUNCH(GEN, FULL, NT, ST) HV_LAUNCH_OPS(GEN, FULL, NT, ST, OPS_HVA)
+        if constexpr (MODE == M_FWD || MODE == M_REV) {
+            // NP gate passes: hopping terms and mask phases, no diagonal sub-terms
+            if (pr.np) {
+                const bool st = MODE == M_FWD && (P.flags & PF_FROM_START) != 0;
+                if (st) {
+                    if (full)
+                        HV_LAUNCH_OPS(false, true, 1, true, OPS_NP);
+                    else
+                        HV_LAUNCH_OPS(false, false, 1, true, OPS_NP);
+                } else if (full) {
+                    HV_LAUNCH_OPS(false, true, 1, false, OPS_NP);
+                } else {
+                    HV_LAUNCH_OPS(false, false, 1, false, OPS_NP);
+                }
+                if (timed)
+                    launch_mark(h, MODE, s, true);
+                continue;
+            }
+        }
         if constexpr (MODE == M_FWD) {
             // the first pass from the start state has kernels of its own
             const bool st = (P.flags & PF_FROM_START) != 0;
@@ -703,6 +731,7 @@ void launch_list(const Program &pr, const DeviceState &ds, const PassList &pl, c
                 HV_LAUNCH(false, false, 1, false);
         }
 #undef HV_LAUNCH
+#undef HV_LAUNCH_OPS
         if (timed)
             launch_mark(h, MODE, s, true);
     }
@@ -839,6 +868,7 @@ struct BatchLayout {
     size_t n_partial = 0;       // doubles
     size_t ws_bytes = 0;
     bool general = false;       // any instance has eps or V terms: the general path for all
+    bool np = false;            // any instance runs the NP circuit: gate kernels decode mask phases
 };
 
 hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
@@ -848,8 +878,11 @@ hubbard_status batch_layout(const hubbard_t *hs, int n, const int64_t *toff,
     const int lim = max_smem_per_block();
     size_t at = 0;
     L.general = false;
-    for (int i = 0; i < n; ++i)
+    L.np = false;
+    for (int i = 0; i < n; ++i) {
         L.general = L.general || progs[i]->general;
+        L.np = L.np || progs[i]->np;
+    }
     L.voff.resize(n);
     for (int i = 0; i < n; ++i) {
         L.voff[i] = at;
@@ -1159,7 +1192,10 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
     (const void *)k_batch_pass<M_FWD, GEN, FULL, false>,                                        \
         (const void *)k_batch_pass<M_FWD, GEN, FULL, true>,                                     \
         (const void *)k_batch_pass<M_HAM, GEN, FULL, false>,                                    \
-        (const void *)k_batch_pass<M_REV, GEN, FULL, false>
+        (const void *)k_batch_pass<M_REV, GEN, FULL, false>,                                    \
+        (const void *)k_batch_pass<M_FWD, GEN, FULL, false, OPS_ALL>,                           \
+        (const void *)k_batch_pass<M_FWD, GEN, FULL, true, OPS_ALL>,                            \
+        (const void *)k_batch_pass<M_REV, GEN, FULL, false, OPS_ALL>
             HV_BATCH_FNS(false, false), HV_BATCH_FNS(false, true), HV_BATCH_FNS(true, false),
             HV_BATCH_FNS(true, true)};
 #undef HV_BATCH_FNS
@@ -1633,19 +1669,26 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
     for (const BatchLaunch &bl : L.launches) {
         const DevWork *w = bp->d_work + bl.item0;
         hipStream_t ls = bl.lane == 0 ? s : bp->lane_s[bl.lane];
-#define HV_BATCH_LAUNCH(MODE, GEN, FULL, START)                                                 \
-    hipLaunchKernelGGL((k_batch_pass<MODE, GEN, FULL, START>), dim3(bl.n_items),               \
+#define HV_BATCH_LAUNCH(MODE, GEN, FULL, START, OPS)                                            \
+    hipLaunchKernelGGL((k_batch_pass<MODE, GEN, FULL, START, OPS>), dim3(bl.n_items),          \
                        dim3(bl.threads), bl.smem, ls, bp->d_inst, bp->d_passes, w, partial)
+#define HV_BATCH_GATES(MODE, GEN, FULL, START)                                                  \
+    do {                                                                                        \
+        if (L.np)                                                                               \
+            HV_BATCH_LAUNCH(MODE, GEN, FULL, START, OPS_ALL);                                   \
+        else                                                                                    \
+            HV_BATCH_LAUNCH(MODE, GEN, FULL, START, OPS_HVA);                                   \
+    } while (0)
 #define HV_BATCH_MODE(GEN, FULL)                                                                \
     do {                                                                                        \
         if (bl.mode == M_FWD && bl.start)                                                       \
-            HV_BATCH_LAUNCH(M_FWD, GEN, FULL, true);                                            \
+            HV_BATCH_GATES(M_FWD, GEN, FULL, true);                                             \
         else if (bl.mode == M_FWD)                                                              \
-            HV_BATCH_LAUNCH(M_FWD, GEN, FULL, false);                                           \
+            HV_BATCH_GATES(M_FWD, GEN, FULL, false);                                            \
         else if (bl.mode == M_HAM)                                                              \
-            HV_BATCH_LAUNCH(M_HAM, GEN, FULL, false);                                           \
+            HV_BATCH_LAUNCH(M_HAM, GEN, FULL, false, OPS_HVA);                                  \
         else                                                                                    \
-            HV_BATCH_LAUNCH(M_REV, GEN, FULL, false);                                           \
+            HV_BATCH_GATES(M_REV, GEN, FULL, false);                                            \
     } while (0)
         if (L.general) {
             if (bl.full)
@@ -1659,6 +1702,7 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
                 HV_BATCH_MODE(false, false);
         }
 #undef HV_BATCH_MODE
+#undef HV_BATCH_GATES
 #undef HV_BATCH_LAUNCH
     }
     for (int l = 1; l < kBatchLanes; ++l)

@@ -30,6 +30,13 @@ enum OpKind : int32_t {
     OP_MASK = 2    // diagonal coef * [every qubit of a mask occupied] (NP phases, R_z)
 };
 
+// Op kinds a pass kernel decodes (a template argument of the pass kernels).
+enum OpSet : int {
+    OPS_HVA = 0,   // OP_HOP, OP_DIAG: the HVA circuit, H and expectations
+    OPS_NP = 1,    // OP_HOP, OP_MASK: gate passes of the NP circuit
+    OPS_ALL = 2    // all three: gate passes of a batch with NP instances
+};
+
 enum PassFlags : int32_t {
     PF_HAM_FIRST = 1,   // H pass: phi <- D psi + terms (else phi += terms)
     PF_HAM_LAST = 2,    // H pass: also reduce Re <psi|phi> into row 0

@@ -419,7 +419,11 @@ __device__ __forceinline__ void vstore(Vec *p, double2 v)
 
 // Vec and the table types: address-space qualified where the caller knows
 // more than the pointer types say (see k_batch_pass).
-template <int MODE, bool GEN, bool FULL, int NT, bool START = false, typename Vec = double2,
+// OPS: which op kinds the op loop decodes (OPS_HVA: hopping terms and
+// diagonal sub-terms; OPS_NP: hopping terms and mask phases; OPS_ALL: all
+// three).  A kind a kernel does not decode costs it no registers.
+template <int MODE, bool GEN, bool FULL, int NT, bool START = false, int OPS = OPS_HVA,
+          typename Vec = double2,
           typename PhT = DevPhase, typename OpT = DevOp, typename VbT = DevVBond,
           typename ThT = double, typename MT = DevModel>
 __device__ __forceinline__ void run_pass(const DevPass &P, const PhT *__restrict__ phases,
@@ -474,7 +478,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const PhT *__restrict
                     double s, c;
                     sincos(theta[op.param] * op.t, &s, &c);
                     opc[o] = make_double2(c, sign * s);
-                } else if (op.kind == OP_MASK) {
+                } else if (OPS != OPS_HVA && op.kind == OP_MASK) {
                     // exp(-i sign th coef) on the amplitudes with every mask bit set
                     double s, c;
                     sincos(theta[op.param] * op.t, &s, &c);
@@ -627,7 +631,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const PhT *__restrict
             for (int o = phq.op_begin; o < phq.op_end; ++o) {
                 const OpT &op = ops[P.op_begin + o];
                 double racc = 0.0;   // this op's reduction (thread part)
-                if (op.kind == OP_DIAG) {
+                if (OPS != OPS_NP && op.kind == OP_DIAG) {
                     double th_op = 0.0;
                     if constexpr (GEN && (MODE == M_FWD || MODE == M_REV))
                         th_op = theta[op.param];
@@ -677,7 +681,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const PhT *__restrict
                             }
                         }
                     }
-                } else if (op.kind == OP_MASK) {
+                } else if (OPS != OPS_HVA && op.kind == OP_MASK) {
                     // coef * [every bit of the mask set]: the phase (fwd/rev)
                     // on those registers, and in the reverse the bracket
                     // coef * sum Im(conj(lambda) psi) over them
@@ -802,7 +806,7 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const PhT *__restrict
     __syncthreads();
 }
 
-template <int MODE, bool GEN, bool FULL, int NT, bool START>
+template <int MODE, bool GEN, bool FULL, int NT, bool START, int OPS>
 __global__ void __launch_bounds__(512)
 k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__ ops,
        const DevVBond *__restrict__ vb, const double *__restrict__ theta,
@@ -811,7 +815,7 @@ k_pass(DevPass P, const DevPhase *__restrict__ phases, const DevOp *__restrict__
 {
     extern __shared__ __align__(16) char smem[];
     const Sink sink{partial + (size_t)P.red_base * stride + blockIdx.x, stride};
-    run_pass<MODE, GEN, FULL, NT, START>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x,
+    run_pass<MODE, GEN, FULL, NT, START, OPS>(P, phases, ops, vb, theta, M, v0, v1, smem, blockIdx.x,
                                   gridDim.x, (uint64_t)1 << P.nfree, ilv, sink);
 }
 
@@ -844,7 +848,7 @@ typedef const __attribute__((address_space(4))) DevModel const_model;
 
 // START (forward, first schedule position): every instance's first pass
 // builds its start state |b0> in registers; nothing is read.
-template <int MODE, bool GEN, bool FULL, bool START>
+template <int MODE, bool GEN, bool FULL, bool START, int OPS>
 __global__ void __launch_bounds__(512)
 k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ passes,
              const DevWork *__restrict__ work, double *__restrict__ partial)
@@ -854,19 +858,23 @@ k_batch_pass(const DevInstance *__restrict__ inst, const DevPass *__restrict__ p
     const DevInstance I = inst[w.inst];
     const DevPass P = passes[w.pass];
     const Sink sink{partial + w.part, w.stride};
-    run_pass<MODE, GEN, FULL, 1, START, global_double2>(
+    run_pass<MODE, GEN, FULL, 1, START, OPS, global_double2>(
         P, (const_phase *)I.phases, (const_op *)I.ops, (const_vbond *)I.vb,
         (const_double *)I.theta, (const_model *)I.model, (global_double2 *)I.psi,
         (global_double2 *)I.lam, smem, w.tile0, 1, w.tile1, 32u, sink);
 }
-#define HV_BATCH(MODE, GEN, FULL, START)                                                        \
-    template __global__ void k_batch_pass<MODE, GEN, FULL, START>(                              \
+#define HV_BATCH(MODE, GEN, FULL, START, OPS)                                                   \
+    template __global__ void k_batch_pass<MODE, GEN, FULL, START, OPS>(                         \
         const DevInstance *, const DevPass *, const DevWork *, double *);
+// batches with NP instances decode all three op kinds in their gate passes
 #define HV_BATCH_ALL(GEN, FULL)                                                                 \
-    HV_BATCH(M_FWD, GEN, FULL, false)                                                           \
-    HV_BATCH(M_FWD, GEN, FULL, true)                                                            \
-    HV_BATCH(M_HAM, GEN, FULL, false)                                                           \
-    HV_BATCH(M_REV, GEN, FULL, false)
+    HV_BATCH(M_FWD, GEN, FULL, false, OPS_HVA)                                                  \
+    HV_BATCH(M_FWD, GEN, FULL, true, OPS_HVA)                                                   \
+    HV_BATCH(M_HAM, GEN, FULL, false, OPS_HVA)                                                  \
+    HV_BATCH(M_REV, GEN, FULL, false, OPS_HVA)                                                  \
+    HV_BATCH(M_FWD, GEN, FULL, false, OPS_ALL)                                                  \
+    HV_BATCH(M_FWD, GEN, FULL, true, OPS_ALL)                                                   \
+    HV_BATCH(M_REV, GEN, FULL, false, OPS_ALL)
 HV_BATCH_ALL(false, false)
 HV_BATCH_ALL(false, true)
 HV_BATCH_ALL(true, false)
@@ -907,7 +915,9 @@ k_reduce_seg(const double *__restrict__ partial, const int32_t *__restrict__ seg
 }
 
 #define HV_INSTANTIATE(MODE, GEN, FULL, NT, ST)                                               \
-    template __global__ void k_pass<MODE, GEN, FULL, NT, ST>(                                   \
+    HV_INSTANTIATE_OPS(MODE, GEN, FULL, NT, ST, OPS_HVA)
+#define HV_INSTANTIATE_OPS(MODE, GEN, FULL, NT, ST, OPS)                                      \
+    template __global__ void k_pass<MODE, GEN, FULL, NT, ST, OPS>(                              \
         DevPass, const DevPhase *, const DevOp *, const DevVBond *, const double *,             \
         const DevModel *, double2 *, double2 *, double *, int, uint32_t);
 #define HV_INSTANTIATE_ALL(GEN, FULL)                                                           \
@@ -924,7 +934,15 @@ HV_INSTANTIATE_ALL(true, false)
 // (the general diagonal's per-amplitude sincos needs the registers)
 HV_INSTANTIATE(M_FWD, false, true, 2, false)
 HV_INSTANTIATE(M_FWD, false, true, 2, true)
+// gate passes of the NP circuit: hopping terms and mask phases only
+HV_INSTANTIATE_OPS(M_FWD, false, true, 1, false, OPS_NP)
+HV_INSTANTIATE_OPS(M_FWD, false, true, 1, true, OPS_NP)
+HV_INSTANTIATE_OPS(M_REV, false, true, 1, false, OPS_NP)
+HV_INSTANTIATE_OPS(M_FWD, false, false, 1, false, OPS_NP)
+HV_INSTANTIATE_OPS(M_FWD, false, false, 1, true, OPS_NP)
+HV_INSTANTIATE_OPS(M_REV, false, false, 1, false, OPS_NP)
 #undef HV_INSTANTIATE_ALL
+#undef HV_INSTANTIATE_OPS
 #undef HV_INSTANTIATE
 
 // ---------------------------------------------------------- vector kernels --
