@@ -400,6 +400,65 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
                                  double *E_dev, double *grad_dev, void *ws_dev, size_t ws_bytes,
                                  void *stream);
 
+/* ---- Particle-number sector form of the HVA circuit ----------------------
+ * H (Eq. (1)/(2)/(15)/(16)) and every gate of the Eq. (7) layer keep N_up and
+ * N_dn, so the circuit state prepared from the checkerboard start |b0> of
+ * Sec. 2.1 has nonzero amplitudes only on the basis states with b0's
+ * (N_up, N_dn).  These calls store only those amplitudes: a sector vector
+ * holds C(Ns, N_dn) x C(Ns, N_up) complex128 values, element
+ * r_dn * C(Ns, N_up) + r_up for the basis state whose spin-down site
+ * pattern has rank r_dn and spin-up pattern rank r_up (rank: position among
+ * the site patterns with that many electrons, in increasing numeric order;
+ * site i is bit i, as qubit i / Ns + i of the full vector).  At 4x4 half
+ * filling that is 12870^2 = 1.66e8 amplitudes (2.6 GB) instead of 2^32
+ * (64 GiB).  The results equal those of the full-vector calls on the same
+ * model and parameters (the amplitudes outside the sector are exactly zero
+ * there).  HVA circuit only: a handle switched to the NP ansatz (whose
+ * on-site gates change N_up and N_dn) gives HUBBARD_ERR_STATE.
+ * Layout: each spin's gates act along the rows of the matrix whose columns
+ * that spin indexes; between runs of gates of the two spins the state is
+ * transposed through LDS tiles (a workspace copy).  All calls are
+ * asynchronous on `stream`; the first call per handle, device and layer
+ * count builds and uploads the sector's tables (pair slots and
+ * Jordan-Wigner signs per gate and rank: 4 bytes x ranks x bonds x 2). */
+enum {
+    HUBBARD_SECTOR_ANSATZ = 0,        /* sector_ansatz_apply: one sector vector */
+    HUBBARD_SECTOR_ENERGY_GRAD = 1,   /* sector_energy_grad: four vectors + partial sums */
+    HUBBARD_SECTOR_HAMILTONIAN = 2    /* sector_hamiltonian_apply: two vectors */
+};
+
+/* C(Ns, N_up) and C(Ns, N_dn) of the handle's start state (host outputs). */
+hubbard_status hubbard_sector_dim(hubbard_t h, int64_t *n_up, int64_t *n_dn);
+
+/* Device workspace bytes of a sector call (op HUBBARD_SECTOR_*). */
+hubbard_status hubbard_sector_workspace_size(hubbard_t h, int32_t n_layers, int32_t op,
+                                             size_t *bytes);
+
+/* psi_dev (a sector vector) <- |b0>. */
+hubbard_status hubbard_sector_init_neel(hubbard_t h, void *psi_dev, void *stream);
+
+/* Eq. (3)/(7) on a sector vector, in place: psi_dev <- U(theta) psi_dev.
+ * theta_dev: n_layers * params_per_layer doubles (device); ws_dev:
+ * hubbard_sector_workspace_size(HUBBARD_SECTOR_ANSATZ) bytes, not
+ * overlapping psi_dev. */
+hubbard_status sector_ansatz_apply(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                                   void *psi_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* out_dev <- H psi_dev on sector vectors (distinct, else HUBBARD_ERR_ARG);
+ * ws_dev: HUBBARD_SECTOR_HAMILTONIAN bytes, overlapping neither. */
+hubbard_status sector_hamiltonian_apply(hubbard_t h, const void *psi_dev, void *out_dev,
+                                        void *ws_dev, size_t ws_bytes, void *stream);
+
+/* energy_grad in the sector form: E_dev[0] = <psi(theta)|H|psi(theta)> and
+ * grad_dev[k] = 2 Im <lambda_k|G_k|psi_k> (Sec. 2.1) for all
+ * n_layers * params_per_layer parameters, psi(theta) prepared from |b0> and
+ * the reverse sweep un-applying the gates to psi and lambda = H psi, one
+ * reduction per gate into its parameter (fixed order: reproducible).  The
+ * workspace (HUBBARD_SECTOR_ENERGY_GRAD bytes) is scratch. */
+hubbard_status sector_energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                                  double *E_dev, double *grad_dev, void *ws_dev, size_t ws_bytes,
+                                  void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,6 +29,9 @@ HUBBARD_OP_OVERLAP_GRAD = 4
 HUBBARD_OP_SPIN_CORR = 5
 HUBBARD_ANSATZ_HVA = 0
 HUBBARD_ANSATZ_NP = 1
+HUBBARD_SECTOR_ANSATZ = 0
+HUBBARD_SECTOR_ENERGY_GRAD = 1
+HUBBARD_SECTOR_HAMILTONIAN = 2
 
 # Every symbol the headers in include/ declare.
 EXPORTED = [
@@ -43,6 +46,8 @@ EXPORTED = [
     "hubbard_tridiag_lowest", "hubbard_vqe_workspace_size", "hubbard_vqe", "hubbard_lbfgs_create",
     "hubbard_lbfgs_tell", "hubbard_lbfgs_result", "hubbard_lbfgs_destroy", "overlap_grad",
     "hubbard_spin_correlation", "hubbard_set_ansatz", "hubbard_param_count",
+    "hubbard_sector_dim", "hubbard_sector_workspace_size", "hubbard_sector_init_neel",
+    "sector_ansatz_apply", "sector_hamiltonian_apply", "sector_energy_grad",
 ]
 
 
@@ -153,6 +158,12 @@ def lib() -> ctypes.CDLL:
             "hubbard_spin_correlation": ([vp, vp, vp, vp, vp, ctypes.c_size_t, vp], st),
             "hubbard_set_ansatz": ([vp, i32], st),
             "hubbard_param_count": ([vp, i32, P(i64)], st),
+            "hubbard_sector_dim": ([vp, P(i64), P(i64)], st),
+            "hubbard_sector_workspace_size": ([vp, i32, i32, P(ctypes.c_size_t)], st),
+            "hubbard_sector_init_neel": ([vp, vp, vp], st),
+            "sector_ansatz_apply": ([vp, vp, i32, vp, vp, ctypes.c_size_t, vp], st),
+            "sector_hamiltonian_apply": ([vp, vp, vp, vp, ctypes.c_size_t, vp], st),
+            "sector_energy_grad": ([vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -510,3 +521,37 @@ def hubbard_param_count(h: int, n_layers: int) -> int:
     n = ctypes.c_int64()
     _check(lib().hubbard_param_count(h, int(n_layers), ctypes.byref(n)))
     return n.value
+
+
+def hubbard_sector_dim(h: int):
+    """(C(Ns, N_up), C(Ns, N_dn)) of the handle's start state."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().hubbard_sector_dim(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def hubbard_sector_workspace_size(h: int, n_layers: int, op: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().hubbard_sector_workspace_size(h, int(n_layers), int(op), ctypes.byref(n)))
+    return n.value
+
+
+def hubbard_sector_init_neel(h: int, psi_dev: int, stream: int = 0) -> None:
+    _check(lib().hubbard_sector_init_neel(h, psi_dev, stream))
+
+
+def sector_ansatz_apply(h: int, theta_dev: int, n_layers: int, psi_dev: int, ws_dev: int,
+                        ws_bytes: int, stream: int = 0) -> None:
+    _check(lib().sector_ansatz_apply(h, theta_dev, int(n_layers), psi_dev, ws_dev, int(ws_bytes),
+                                     stream))
+
+
+def sector_hamiltonian_apply(h: int, psi_dev: int, out_dev: int, ws_dev: int, ws_bytes: int,
+                             stream: int = 0) -> None:
+    _check(lib().sector_hamiltonian_apply(h, psi_dev, out_dev, ws_dev, int(ws_bytes), stream))
+
+
+def sector_energy_grad(h: int, theta_dev: int, n_layers: int, E_dev: int, grad_dev: int,
+                       ws_dev: int, ws_bytes: int, stream: int = 0) -> None:
+    _check(lib().sector_energy_grad(h, theta_dev, int(n_layers), E_dev, grad_dev, ws_dev,
+                                    int(ws_bytes), stream))

@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhubvqe.so")
-SOURCES = ["model.cpp", "plan.cpp", "tridiag.cpp", "lbfgs.cpp", "engine.hip", "kernels.hip"]
+SOURCES = ["model.cpp", "plan.cpp", "tridiag.cpp", "lbfgs.cpp", "engine.hip", "kernels.hip",
+           "sector.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -1231,6 +1231,14 @@ hubbard_status build_batch(const hubbard_t *hs, int n, const double *theta, cons
 
 // ===================================================================== ABI
 
+namespace hv {
+// For the library's other translation units (the sector form).
+const Model *handle_model(hubbard_t h) { return h ? &h->m : nullptr; }
+uint64_t handle_uid(hubbard_t h) { return h ? h->uid : 0; }
+hubbard_status set_error(hubbard_status s, const std::string &msg) { return fail(s, msg); }
+void sector_forget(uint64_t uid);
+}  // namespace hv
+
 extern "C" {
 
 const char *hubbard_last_error(void) { return g_err.c_str(); }
@@ -1285,6 +1293,7 @@ void hubbard_destroy(hubbard_t h)
     if (!h)
         return;
     evict_batches_of(h->uid);
+    hv::sector_forget(h->uid);
     if (h->ev_ready)
         for (int j = 0; j < 4; ++j)
             (void)hipEventDestroy(h->ev[j]);

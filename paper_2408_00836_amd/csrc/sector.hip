@@ -1,0 +1,1120 @@
+// sector.hip -- the particle-number sector form of the HVA circuit on gfx950.
+//
+// H (Eq. (1)/(2)/(15)/(16)) and every gate of the Eq. (7) layer keep the
+// numbers of spin-up and spin-down electrons, so the circuit state prepared
+// from the checkerboard basis state |b0> (Sec. 2.1) has nonzero amplitudes
+// only on the basis states with b0's (N_up, N_dn).  This file stores only
+// those: the state is the matrix Psi[r_dn][r_up] of C(Ns, N_dn) x C(Ns, N_up)
+// complex128 amplitudes, r_s the rank of the spin-s site pattern among the
+// patterns with N_s electrons in increasing numeric order (at 4x4 half
+// filling 12870 x 12870 = 1.66e8 amplitudes, 2.6 GB, against 2^32 and
+// 64 GiB for the full vector).
+//
+// A hopping term of spin s changes only the spin-s pattern, so in the layout
+// whose rows are indexed by the other spin (layout A: rows r_dn, columns r_up;
+// layout B: the transpose) every spin-s gate acts inside rows, with the same
+// pairing of columns in every row.  A row pass holds one row per workgroup
+// in registers and applies a run of gates to it; a gate's partner amplitudes
+// come through LDS, each active element writing its value to its pair slot
+// and reading the partner's from the neighbouring slot (pair slots and the
+// Jordan-Wigner sign precomputed per gate and rank on the host).  Between
+// runs of the two spins the state is transposed (A <-> B).  The diagonal
+// phase acts element-wise in either layout.
+//
+// Schedule of L layers: [D_0, up_0] (A), [dn_0, D_1, dn_1] (B),
+// [up_1, D_2, up_2] (A), ...: within a layer the up and down hops commute,
+// so each row pass carries the second half of one layer and the first half
+// of the next, L + 1 row passes and L transposes per sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/hubbard.h"
+#include "hubvqe.hpp"
+#include "phase.hpp"
+
+namespace hv {
+
+// engine.hip: the handle's model, its unique id, the thread's last error
+const Model *handle_model(hubbard_t h);
+uint64_t handle_uid(hubbard_t h);
+hubbard_status set_error(hubbard_status s, const std::string &msg);
+
+namespace sec {
+
+constexpr int kT = 1024;                  // threads of a row workgroup
+constexpr int kWaves = kT / 64;
+constexpr int kMaxRed = 16;               // reduction slots of one row pass
+constexpr int kGrid = 1024;               // at most this many row workgroups
+constexpr uint32_t kNone = 0xFFFFu;       // code of an element a gate leaves alone
+constexpr int kMaxRows = 13 * kT;         // longest row: C(16, 8) = 12870
+
+enum { S_FWD = 0, S_REV = 1, S_HAM = 2 };
+enum { SOP_HOP = 0, SOP_DIAG = 1 };
+enum { SF_NO_STORE = 1 };
+
+// One operation of a row pass (32 bytes).  HOP: the gate exp(-i th t h) of
+// one bond and spin (h = a+_i a_j + h.c. on that spin's sites); DIAG: the
+// layer's diagonal exp(-i th D).
+struct SecOp {
+    int32_t kind;
+    int32_t param;   // theta index
+    int32_t tab;     // HOP: offset of its code table (entries of the row's columns)
+    int32_t red;     // REV: reduction slot of the parameter within the pass
+    double t;        // HOP: t_b
+    double pad;
+};
+
+// Device constants of a model's sector.
+struct SecModel {
+    int32_t ns, nvb;
+    int32_t n[2];              // patterns of each spin
+    double U;
+    const uint32_t *pat[2];    // site pattern of each rank
+    const double *base[2];     // sum_i eps_i p_i + sum_b V_b p_i p_j of each rank
+    const uint32_t *code;      // per gate and rank: pair slot | sign << 15, or kNone
+    int32_t vi[kMaxBonds], vj[kMaxBonds];
+    double vV[kMaxBonds];
+};
+
+// D of the basis state with row pattern rp and column pattern cp:
+// U #(doubly occupied) + base(rp) + base(cp) + sum_b V_b (rp_i cp_j + cp_i rp_j).
+__device__ __forceinline__ double diag_d(const SecModel *M, uint32_t rp, double rb, uint32_t cp,
+                                         double cb)
+{
+    double d = M->U * (double)__popc(rp & cp) + rb + cb;
+    for (int v = 0; v < M->nvb; ++v) {
+        const int i = M->vi[v], j = M->vj[v];
+        const uint32_t x = (((rp >> i) & (cp >> j)) | ((cp >> i) & (rp >> j))) & 1u;
+        const uint32_t y = ((rp >> i) & (cp >> j) & (cp >> i) & (rp >> j)) & 1u;
+        d += M->vV[v] * (double)(x + y);
+    }
+    return d;
+}
+
+// The value is final here: the work that produced it stays before the next
+// workgroup barrier instead of being sunk past it (which would keep the
+// inputs, a partner value each, live across the barrier).
+__device__ __forceinline__ void pin(double2 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        x += __shfl_xor(x, off);
+    return x;
+}
+
+// Row pass.  Each workgroup takes rows blockIdx.x, blockIdx.x + gridDim.x, ...
+// of the layout whose columns are indexed by spin `col`; thread t holds the
+// row's elements t + j kT, j < RPT.
+//   S_FWD: v0 <- ops applied in order.
+//   S_REV: (v0, v1) = (psi, lambda) <- ops un-applied in reverse order; the
+//          bracket Im <lambda| G |psi> of every op before its un-application
+//          goes to its reduction slot.
+//   S_HAM: v1 <- sum of the ops' generators applied to v0 (D if a DIAG op
+//          is present), slot 0 <- Re <v0|v1>.
+// Reductions: per-wave sums in LDS, then per workgroup one partial per slot
+// at partial[(row0 + slot) * pstride + blockIdx.x] (fixed order).
+// Two 16-bit gate codes per register (pair slot | sign << 15; 0xFFFF: the
+// element is left alone).
+template <int RPT>
+struct Codes {
+    uint32_t w[(RPT + 1) / 2];
+    __device__ __forceinline__ uint32_t get(int j) const { return (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu; }
+};
+
+typedef const __attribute__((address_space(1))) uint32_t gu32;
+typedef const __attribute__((address_space(1))) double gf64;
+typedef __attribute__((address_space(1))) double2 gc128;
+
+template <int RPT>
+__device__ __forceinline__ Codes<RPT> load_codes(const gu32 *__restrict__ ct, uint32_t tid,
+                                                 uint32_t n)
+{
+    // elements past the row end read the last entry and are marked inactive
+    // (selects, no branches)
+    Codes<RPT> c;
+#pragma unroll
+    for (int j = 0; j < RPT; j += 2) {
+        const uint32_t i0 = tid + j * kT, i1 = i0 + kT;
+        const uint32_t v0 = ct[min(i0, n - 1)];
+        const uint32_t lo = i0 < n ? v0 : kNone;
+        uint32_t hi = kNone;
+        if (j + 1 < RPT) {
+            const uint32_t v1 = ct[min(i1, n - 1)];
+            hi = i1 < n ? v1 : kNone;
+        }
+        c.w[j >> 1] = lo | (hi << 16);
+    }
+    return c;
+}
+
+// One gate's exchange of vector x through the pair slots: every active
+// element publishes its value, then every element calls use(j, partner,
+// w) with w = the Jordan-Wigner sign (+-1) if it is active and 0 if not (its
+// "partner" is then slot 0, any finite value): the updates are branch-free,
+// so the register tile is updated in place.
+template <int RPT, typename F>
+__device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
+                                         double2 *xch, F &&use)
+{
+    // decoded afresh in every exchange (not shared with an earlier one)
+#pragma unroll
+    for (int k = 0; k < (RPT + 1) / 2; ++k)
+        asm volatile("" : "+v"(cd.w[k]));
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const uint32_t c = cd.get(j);
+        if (c != kNone)
+            xch[c & 0x7FFFu] = x[j];
+    }
+    // the slot addresses are decoded again below rather than kept
+#pragma unroll
+    for (int k = 0; k < (RPT + 1) / 2; ++k)
+        asm volatile("" : "+v"(cd.w[k]));
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const uint32_t c = cd.get(j);
+        const bool act = c != kNone;
+        const double2 p = xch[act ? ((c & 0x7FFFu) ^ 1u) : 0u];
+        use(j, p, act ? ((c >> 15) ? -1.0 : 1.0) : 0.0);
+        // one partner value in flight per thread (the other waves hide the
+        // LDS latency): the register tile keeps its registers
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+}
+
+// Row pass.  Each workgroup takes rows blockIdx.x, blockIdx.x + gridDim.x, ...
+// of the layout whose columns are indexed by spin `col`; thread t holds the
+// row's elements t + j kT, j < RPT.
+//   S_FWD: v0 <- ops applied in order.
+//   S_REV: (v0, v1) = (psi, lambda) <- ops un-applied in reverse order; the
+//          bracket Im <lambda| G |psi> of every op before its un-application
+//          goes to its reduction slot.
+//   S_HAM: v1 <- sum of the ops' generators applied to v0 (D if a DIAG op
+//          is present), slot 0 <- Re <v0|v1>.
+// Reductions: per-wave sums in LDS, then per workgroup one partial per slot
+// at partial[(row0 + slot) * pstride + blockIdx.x] (fixed order).
+// GEN: the diagonal has eps or V terms (D from the pattern tables, its phase
+// by cis_neg); else D = U #(doubly occupied) and its phase comes from the
+// op's table dph[op.tab][k] = exp(-i th U k).
+template <int MODE, int RPT, bool GEN>
+__global__ void __launch_bounds__(kT)
+k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
+           const double2 *__restrict__ ang, const double2 *__restrict__ dph,
+           const SecModel *__restrict__ M, double2 *__restrict__ v0, double2 *__restrict__ v1,
+           double *__restrict__ partial, int row0, int pstride, int flags, int xch_elems)
+{
+    extern __shared__ __align__(16) char smem[];
+    double2 *xch = (double2 *)smem;                            // pair slots
+    double *acc = (double *)(smem + (size_t)xch_elems * 16);   // kMaxRed x kWaves
+    double2 *cis = (double2 *)(acc + kMaxRed * kWaves);         // unit phases
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t n = (uint32_t)M->n[col];
+    const int nr = M->n[1 - col];
+    // the tables' pointers come from memory: global address space, so that
+    // the loads take a scalar base and a 32-bit offset
+    const gu32 *__restrict__ cpat = (const gu32 *)M->pat[col];
+    const gf64 *__restrict__ cbase = (const gf64 *)M->base[col];
+    const gu32 *__restrict__ gcode = (const gu32 *)M->code;
+    const gu32 *__restrict__ rpat = (const gu32 *)M->pat[1 - col];
+    const gf64 *__restrict__ rbase = (const gf64 *)M->base[1 - col];
+    for (int i = tid; i < kMaxRed * kWaves; i += kT)
+        acc[i] = 0.0;
+    if constexpr (MODE != S_HAM && GEN)
+        build_cis(cis, tid, kT);
+    __syncthreads();
+    double eacc = 0.0;
+
+    for (int r = blockIdx.x; r < nr; r += gridDim.x) {
+        uint32_t tr = (uint32_t)tid;   // per-row indices are not kept across rows
+        asm volatile("" : "+v"(tr));
+        const uint32_t rp = rpat[r];
+        const double rb = rbase[r];
+        gc128 *__restrict__ x0 = (gc128 *)(v0 + (size_t)r * (size_t)n);
+        gc128 *__restrict__ x1 = (gc128 *)(v1 + (size_t)r * (size_t)n);
+        // elements past the row end (the last register of some threads) hold
+        // zero: every op leaves them zero and they add nothing to a sum
+        double2 a[RPT], b[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const uint32_t idx = tr + j * kT, ic = min(idx, n - 1);
+            const bool in = idx < n;
+            a[j] = make_double2(x0[ic].x, x0[ic].y);
+            a[j] = in ? a[j] : make_double2(0.0, 0.0);
+            if constexpr (MODE == S_REV) {
+                b[j] = make_double2(x1[ic].x, x1[ic].y);
+                b[j] = in ? b[j] : make_double2(0.0, 0.0);
+            } else {
+                b[j] = make_double2(0.0, 0.0);
+            }
+        }
+        for (int oi = 0; oi < n_ops; ++oi) {
+            const int io = MODE == S_REV ? n_ops - 1 - oi : oi;
+            const SecOp op = ops[io];
+            double racc = 0.0;
+            // the element indices recomputed per op, not kept live (with
+            // their 64-bit table addresses) across the op loop
+            uint32_t t = (uint32_t)tid;
+            asm volatile("" : "+v"(t));
+            if (op.kind == SOP_DIAG) {
+                double th = 0.0;
+                if constexpr (MODE != S_HAM)
+                    th = ang[io].x;
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) {
+                    const uint32_t ic = min(t + j * kT, n - 1);   // past the end: a zero element
+                    {
+                        const uint32_t cp = cpat[ic];
+                        const uint32_t k = __popc(rp & cp);
+                        const double d = GEN ? diag_d(M, rp, rb, cp, cbase[ic])
+                                             : M->U * (double)k;
+                        if constexpr (MODE == S_HAM) {
+                            b[j].x += d * a[j].x;
+                            b[j].y += d * a[j].y;
+                        } else {
+                            // exp(-i th D) forward, exp(+i th D) to un-apply
+                            double2 e;
+                            if constexpr (GEN) {
+                                e = cis_neg(MODE == S_REV ? -th * d : th * d, cis);
+                            } else {
+                                e = dph[(size_t)op.tab * kDiagTab + k];
+                                if constexpr (MODE == S_REV)
+                                    e.y = -e.y;
+                            }
+                            if constexpr (MODE == S_REV) {
+                                racc += d * (b[j].x * a[j].y - b[j].y * a[j].x);
+                                const double2 l = b[j];
+                                b[j] = make_double2(e.x * l.x - e.y * l.y, e.x * l.y + e.y * l.x);
+                            }
+                            const double2 p = a[j];
+                            a[j] = make_double2(e.x * p.x - e.y * p.y, e.x * p.y + e.y * p.x);
+                        }
+                    }
+                    // one element's phase at a time: fewer live temporaries
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+                double cs = 0.0, sn = 0.0;
+                if constexpr (MODE != S_HAM) {
+                    const double2 cssn = ang[io];   // (cos, sin)(th t)
+                    cs = cssn.x;
+                    sn = MODE == S_REV ? -cssn.y : cssn.y;   // un-apply: sin -> -sin
+                }
+                const double mt = -op.t;
+                const Codes<RPT> cd = load_codes<RPT>(gcode + op.tab, t, n);
+                // w = sign (active) or 0 (inactive: cos factor 1, no partner term)
+                exchange<RPT>(a, cd, xch, [&](int j, double2 p, double w) {
+                    if constexpr (MODE == S_HAM) {   // phi += (-t) s psi_x'
+                        b[j].x += mt * w * p.x;
+                        b[j].y += mt * w * p.y;
+                        pin(b[j]);
+                    } else {
+                        if constexpr (MODE == S_REV) {   // (-t) s Im(conj(lambda_x) psi_x')
+                            racc += mt * w * (b[j].x * p.y - b[j].y * p.x);
+                            pin(racc);
+                        }
+                        const double ss = w * sn;      // x <- cs x + i s sn x'
+                        const double c = w != 0.0 ? cs : 1.0;
+                        const double2 y = a[j];
+                        a[j] = make_double2(c * y.x - ss * p.y, c * y.y + ss * p.x);
+                        pin(a[j]);
+                    }
+                });
+                if constexpr (MODE == S_REV)
+                    exchange<RPT>(b, cd, xch, [&](int j, double2 p, double w) {
+                        const double ss = w * sn;
+                        const double c = w != 0.0 ? cs : 1.0;
+                        const double2 y = b[j];
+                        b[j] = make_double2(c * y.x - ss * p.y, c * y.y + ss * p.x);
+                        pin(b[j]);
+                    });
+            }
+            if constexpr (MODE == S_REV) {
+                const double w = wave_sum(racc);
+                if (lane == 0)
+                    acc[op.red * kWaves + wave] += w;
+            }
+        }
+        if constexpr (MODE == S_HAM) {
+#pragma unroll
+            for (int j = 0; j < RPT; ++j)
+                eacc += a[j].x * b[j].x + a[j].y * b[j].y;
+        }
+        if (!(flags & SF_NO_STORE)) {
+            // addresses recomputed here rather than kept from the loads
+            uint32_t t = (uint32_t)tid;
+            asm volatile("" : "+v"(t));
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const uint32_t idx = t + j * kT;
+                if (idx < n) {
+                    if constexpr (MODE != S_HAM) {
+                        x0[idx].x = a[j].x;
+                        x0[idx].y = a[j].y;
+                    }
+                    if constexpr (MODE != S_FWD) {
+                        x1[idx].x = b[j].x;
+                        x1[idx].y = b[j].y;
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (MODE == S_HAM) {
+        const double w = wave_sum(eacc);
+        if (lane == 0)
+            acc[wave] = w;
+    }
+    __syncthreads();
+    if constexpr (MODE != S_FWD) {
+        if (tid < n_red) {
+            double s = 0.0;
+            for (int w = 0; w < kWaves; ++w)
+                s += acc[tid * kWaves + w];
+            partial[(size_t)(row0 + tid) * pstride + blockIdx.x] = s;
+        }
+    }
+}
+
+// Per op of a sweep: HOP (cos, sin)(th_param t_b); DIAG (th_param, 0) and
+// its phase table dph[op.tab][k] = exp(-i th U k), k = 0 .. kDiagTab - 1.
+__global__ void __launch_bounds__(256)
+k_sec_angles(const SecOp *__restrict__ ops, int n, const double *__restrict__ theta, double U,
+             double2 *__restrict__ ang, double2 *__restrict__ dph)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const SecOp o = ops[i];
+        if (o.param < 0)   // a term of H: no angle
+            continue;
+        if (o.kind == SOP_HOP) {
+            double s, c;
+            sincos(theta[o.param] * o.t, &s, &c);
+            ang[i] = make_double2(c, s);
+        } else {
+            const double th = theta[o.param];
+            ang[i] = make_double2(th, 0.0);
+            for (int k = 0; k < kDiagTab; ++k) {
+                double s, c;
+                sincos(th * (U * (double)k), &s, &c);
+                dph[(size_t)o.tab * kDiagTab + k] = make_double2(c, -s);
+            }
+        }
+    }
+}
+
+// out[c nr + r] = in[r nc + c] (add: out += that), through 32 x 32 LDS tiles.
+__global__ void __launch_bounds__(256)
+k_sec_transpose(const double2 *__restrict__ in, double2 *__restrict__ out, int nr, int nc, int add)
+{
+    __shared__ double2 tile[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int r = r0 + k, c = c0 + tx;
+        if (r < nr && c < nc)
+            tile[k][tx] = in[(size_t)r * nc + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int c = c0 + k, r = r0 + tx;
+        if (r < nr && c < nc) {
+            double2 v = tile[tx][k];
+            double2 *o = out + (size_t)c * nr + r;
+            if (add) {
+                const double2 w = *o;
+                v.x += w.x;
+                v.y += w.y;
+            }
+            *o = v;
+        }
+    }
+}
+
+// psi <- the basis state at position `at` (zeros elsewhere).
+__global__ void __launch_bounds__(256) k_sec_basis(double2 *__restrict__ psi, size_t n, size_t at)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        psi[i] = make_double2(i == at ? 1.0 : 0.0, 0.0);
+}
+
+// out[o] = scale[o] * sum over partial rows rows[ptr[o] .. ptr[o+1]) of the
+// nblk[row] entries each (the workgroups of the pass that wrote it), in a
+// fixed order; o = 0 goes to E, o >= 1 to grad[o-1].
+__global__ void __launch_bounds__(256)
+k_sec_reduce(const double *__restrict__ partial, int pstride, const int32_t *__restrict__ nblk,
+             const int32_t *__restrict__ ptr, const int32_t *__restrict__ rows,
+             const double *__restrict__ scale, double *__restrict__ E, double *__restrict__ grad)
+{
+    __shared__ double sm[256];
+    const int o = blockIdx.x, tid = threadIdx.x;
+    double s = 0.0;
+    for (int k = ptr[o]; k < ptr[o + 1]; ++k) {
+        const double *p = partial + (size_t)rows[k] * pstride;
+        for (int b = tid; b < nblk[rows[k]]; b += 256)
+            s += p[b];
+    }
+    sm[tid] = s;
+    for (int st = 128; st > 0; st >>= 1) {
+        __syncthreads();
+        if (tid < st)
+            sm[tid] += sm[tid + st];
+    }
+    if (tid == 0) {
+        const double v = scale[o] * sm[0];
+        if (o == 0)
+            E[0] = v;
+        else
+            grad[o - 1] = v;
+    }
+}
+
+// ------------------------------------------------------------------ host --
+
+struct RowPass {
+    int col = 0;
+    std::vector<SecOp> ops;
+    std::vector<int> red_param;   // parameter of each reduction slot
+};
+
+// Sector tables of one model on one device.
+struct Tables {
+    int n[2] = {0, 0};
+    int xch = 0;                  // most active elements of any gate (LDS slots)
+    std::vector<int> tab[2];      // per bond: offset of its spin-s code table
+    size_t b0_pos = 0;            // position of |b0> in layout A
+    bool general = false;         // eps or V terms in the diagonal
+    double U = 0.0;
+    SecModel *d_model = nullptr;
+    uint32_t *d_pat[2] = {nullptr, nullptr};
+    double *d_base[2] = {nullptr, nullptr};
+    uint32_t *d_code = nullptr;
+    ~Tables()
+    {
+        (void)hipFree(d_model);
+        for (int s = 0; s < 2; ++s) {
+            (void)hipFree(d_pat[s]);
+            (void)hipFree(d_base[s]);
+        }
+        (void)hipFree(d_code);
+    }
+};
+
+struct Program {
+    std::vector<RowPass> fwd;
+    int final_col = 0;
+    SecOp *d_ops = nullptr;       // forward passes' ops, then H ops (X spin + D, Y spin)
+    int n_ops = 0;                // all of them (the angle table's entries)
+    int n_diag = 0;               // diagonal ops of the sweep (phase tables)
+    std::vector<int> op_off;      // per forward pass
+    int ham_x_off = 0, ham_x_n = 0, ham_y_off = 0, ham_y_n = 0;
+    // reduction: partial rows 0, 1 = the two energy parts, then each reverse
+    // pass's slots (forward order of passes)
+    std::vector<int> red_row0;    // per forward pass
+    int n_rows = 0;
+    int32_t *d_ptr = nullptr, *d_rows = nullptr, *d_nblk = nullptr;
+    double *d_scale = nullptr;
+    int n_out = 0;
+    ~Program()
+    {
+        (void)hipFree(d_ops);
+        (void)hipFree(d_nblk);
+        (void)hipFree(d_ptr);
+        (void)hipFree(d_rows);
+        (void)hipFree(d_scale);
+    }
+};
+
+struct Entry {
+    std::unique_ptr<Tables> tab;
+    std::map<int, std::unique_ptr<Program>> progs;   // by layer count
+};
+
+std::mutex g_mu;
+std::map<std::pair<uint64_t, int>, Entry> g_cache;   // (handle uid, device)
+
+hubbard_status fail(hubbard_status s, const std::string &m) { return set_error(s, m); }
+
+hipError_t upload(void **dst, const void *src, size_t bytes)
+{
+    hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+    if (e == hipSuccess && bytes)
+        e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    return e;
+}
+
+int popc(uint32_t x) { return __builtin_popcount(x); }
+
+// LDS of a row workgroup: the pair slots, the reduction slots, the unit phases.
+size_t lds_bytes(const Tables &T)
+{
+    return (size_t)T.xch * 16 + kMaxRed * kWaves * 8 + (1u << kCisBits) * 16;
+}
+
+hubbard_status build_tables(const Model &m, Tables &T)
+{
+    const int ns = m.ns;
+    const uint32_t smask = ns >= 32 ? 0xffffffffu : ((1u << ns) - 1u);
+    const int ne[2] = {popc((uint32_t)m.neel & smask), popc((uint32_t)(m.neel >> ns) & smask)};
+    std::vector<uint32_t> pat[2];
+    std::vector<double> base[2];
+    std::vector<int32_t> rank_of[2];
+    for (int s = 0; s < 2; ++s) {
+        rank_of[s].assign((size_t)1 << ns, -1);
+        for (uint32_t p = 0; p <= smask; ++p) {
+            if (popc(p) != ne[s])
+                continue;
+            rank_of[s][p] = (int32_t)pat[s].size();
+            pat[s].push_back(p);
+            double b = 0.0;
+            for (int i = 0; i < ns; ++i)
+                if ((p >> i) & 1u)
+                    b += m.eps[i];
+            for (int k = 0; k < m.nb; ++k)
+                if (((p >> m.bi[k]) & 1u) && ((p >> m.bj[k]) & 1u))
+                    b += m.V[k];
+            base[s].push_back(b);
+            if (p == smask)
+                break;
+        }
+        T.n[s] = (int)pat[s].size();
+    }
+    if (T.n[0] > kMaxRows || T.n[1] > kMaxRows)
+        return fail(HUBBARD_ERR_ARG, "sector rows longer than 13 x 1024");
+    const uint32_t up0 = (uint32_t)m.neel & smask, dn0 = (uint32_t)(m.neel >> ns) & smask;
+    T.b0_pos = (size_t)rank_of[1][dn0] * T.n[0] + rank_of[0][up0];
+    // per bond and spin: pair slots (pair p at slots 2p, 2p+1) and the
+    // Jordan-Wigner sign of the sites strictly between the bond's ends
+    std::vector<uint32_t> codes;
+    T.xch = 2;
+    for (int s = 0; s < 2; ++s) {
+        T.tab[s].assign(m.nb, 0);
+        for (int k = 0; k < m.nb; ++k) {
+            const int i = std::min(m.bi[k], m.bj[k]), j = std::max(m.bi[k], m.bj[k]);
+            const uint32_t mask = (1u << i) | (1u << j);
+            const uint32_t between = ((1u << j) - 1u) & ~((2u << i) - 1u);
+            T.tab[s][k] = (int)codes.size();
+            const size_t at = codes.size();
+            codes.resize(at + T.n[s], kNone);
+            uint32_t pairs = 0;
+            for (int r = 0; r < T.n[s]; ++r) {
+                const uint32_t p = pat[s][r];
+                if (((p >> i) ^ (p >> j)) & 1u) {
+                    const int r2 = rank_of[s][p ^ mask];
+                    if (r2 > r) {
+                        const uint32_t sg = (uint32_t)(popc(p & between) & 1) << 15;
+                        codes[at + r] = (2 * pairs) | sg;
+                        codes[at + r2] = (2 * pairs + 1) | sg;
+                        ++pairs;
+                    }
+                }
+            }
+            T.xch = std::max(T.xch, (int)(2 * pairs));
+        }
+    }
+    if (T.xch > 0x7FFF || lds_bytes(T) > 160 * 1024)
+        return fail(HUBBARD_ERR_ARG, "sector gate pairs do not fit the workgroup's LDS");
+    T.general = m.general;
+    T.U = m.U;
+    SecModel sm;
+    std::memset(&sm, 0, sizeof(sm));
+    sm.ns = ns;
+    sm.U = m.U;
+    sm.n[0] = T.n[0];
+    sm.n[1] = T.n[1];
+    for (int k = 0; k < m.nb; ++k)
+        if (m.V[k] != 0.0) {
+            sm.vi[sm.nvb] = m.bi[k];
+            sm.vj[sm.nvb] = m.bj[k];
+            sm.vV[sm.nvb] = m.V[k];
+            ++sm.nvb;
+        }
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < 2 && e == hipSuccess; ++s) {
+        e = upload((void **)&T.d_pat[s], pat[s].data(), pat[s].size() * 4);
+        if (e == hipSuccess)
+            e = upload((void **)&T.d_base[s], base[s].data(), base[s].size() * 8);
+        sm.pat[s] = T.d_pat[s];
+        sm.base[s] = T.d_base[s];
+    }
+    if (e == hipSuccess)
+        e = upload((void **)&T.d_code, codes.data(), codes.size() * 4);
+    sm.code = T.d_code;
+    if (e == hipSuccess)
+        e = upload((void **)&T.d_model, &sm, sizeof(sm));
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("uploading sector tables: ") +
+                                            hipGetErrorString(e));
+    return HUBBARD_OK;
+}
+
+void add_red(RowPass &p, SecOp &o)
+{
+    for (size_t s = 0; s < p.red_param.size(); ++s)
+        if (p.red_param[s] == o.param) {
+            o.red = (int)s;
+            return;
+        }
+    o.red = (int)p.red_param.size();
+    p.red_param.push_back(o.param);
+}
+
+hubbard_status build_program(const Model &m, const Tables &T, int layers, Program &P)
+{
+    const int per = m.params_per_layer();
+    auto hops = [&](int l, int spin, RowPass &p) {
+        for (int s = 1; s < per; ++s)
+            for (int k = 0; k < m.nb; ++k)
+                if (m.slot[k] == s) {
+                    SecOp o;
+                    std::memset(&o, 0, sizeof(o));
+                    o.kind = SOP_HOP;
+                    o.param = l * per + s;
+                    o.tab = T.tab[spin][k];
+                    o.t = m.t[k];
+                    add_red(p, o);
+                    p.ops.push_back(o);
+                }
+    };
+    int n_diag = 0;
+    auto diag = [&](int l, RowPass &p) {
+        SecOp o;
+        std::memset(&o, 0, sizeof(o));
+        o.kind = SOP_DIAG;
+        o.param = l * per;
+        o.tab = n_diag++;   // its phase table
+        add_red(p, o);
+        p.ops.push_back(o);
+    };
+    P.fwd.clear();
+    if (layers > 0) {
+        RowPass cur;
+        cur.col = 0;
+        for (int l = 0; l < layers; ++l) {
+            diag(l, cur);
+            hops(l, cur.col, cur);
+            RowPass nxt;
+            nxt.col = 1 - cur.col;
+            hops(l, nxt.col, nxt);
+            P.fwd.push_back(cur);
+            cur = nxt;
+        }
+        P.fwd.push_back(cur);
+    }
+    for (const RowPass &p : P.fwd)
+        if ((int)p.red_param.size() > kMaxRed)
+            return fail(HUBBARD_ERR_ARG, "sector row pass with more than 16 parameters");
+    P.final_col = P.fwd.empty() ? 0 : P.fwd.back().col;
+    P.n_diag = n_diag;
+    // H: the final layout's spin hops and D, then the other spin's hops
+    std::vector<SecOp> all;
+    for (const RowPass &p : P.fwd) {
+        P.op_off.push_back((int)all.size());
+        all.insert(all.end(), p.ops.begin(), p.ops.end());
+    }
+    auto ham_ops = [&](int spin, bool with_d) {
+        std::vector<SecOp> v;
+        if (with_d) {
+            SecOp o;
+            std::memset(&o, 0, sizeof(o));
+            o.kind = SOP_DIAG;
+            o.param = -1;
+            o.tab = -1;
+            v.push_back(o);
+        }
+        for (int k = 0; k < m.nb; ++k) {
+            SecOp o;
+            std::memset(&o, 0, sizeof(o));
+            o.kind = SOP_HOP;
+            o.param = -1;
+            o.tab = T.tab[spin][k];
+            o.t = m.t[k];
+            v.push_back(o);
+        }
+        return v;
+    };
+    std::vector<SecOp> hx = ham_ops(P.final_col, true), hy = ham_ops(1 - P.final_col, false);
+    P.ham_x_off = (int)all.size();
+    P.ham_x_n = (int)hx.size();
+    all.insert(all.end(), hx.begin(), hx.end());
+    P.ham_y_off = (int)all.size();
+    P.ham_y_n = (int)hy.size();
+    all.insert(all.end(), hy.begin(), hy.end());
+    // reduction rows, and the workgroups of the pass that writes each
+    auto grid_of = [&](int col) { return std::min(T.n[1 - col], kGrid); };
+    P.n_rows = 2;
+    std::vector<int32_t> nblk{grid_of(P.final_col), grid_of(1 - P.final_col)};
+    std::vector<std::vector<int>> rows_of(1 + layers * per);
+    rows_of[0] = {0, 1};
+    for (const RowPass &p : P.fwd) {
+        P.red_row0.push_back(P.n_rows);
+        for (size_t s = 0; s < p.red_param.size(); ++s) {
+            rows_of[1 + p.red_param[s]].push_back(P.n_rows + (int)s);
+            nblk.push_back(grid_of(p.col));
+        }
+        P.n_rows += (int)p.red_param.size();
+    }
+    std::vector<int32_t> ptr{0}, rows;
+    std::vector<double> scale;
+    for (size_t o = 0; o < rows_of.size(); ++o) {
+        rows.insert(rows.end(), rows_of[o].begin(), rows_of[o].end());
+        ptr.push_back((int32_t)rows.size());
+        scale.push_back(o == 0 ? 1.0 : 2.0);   // dE/dth_k = 2 Im <lambda_k|G_k|psi_k>
+    }
+    P.n_out = (int)rows_of.size();
+    P.n_ops = (int)all.size();
+    hipError_t e = upload((void **)&P.d_ops, all.data(), all.size() * sizeof(SecOp));
+    if (e == hipSuccess)
+        e = upload((void **)&P.d_ptr, ptr.data(), ptr.size() * 4);
+    if (e == hipSuccess)
+        e = upload((void **)&P.d_rows, rows.data(), rows.size() * 4);
+    if (e == hipSuccess)
+        e = upload((void **)&P.d_scale, scale.data(), scale.size() * 8);
+    if (e == hipSuccess)
+        e = upload((void **)&P.d_nblk, nblk.data(), nblk.size() * 4);
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string("uploading the sector program: ") +
+                                            hipGetErrorString(e));
+    return HUBBARD_OK;
+}
+
+// Tables and (layers >= 0) the program of a handle on the current device.
+hubbard_status get(hubbard_t h, int layers, Tables **T, Program **P)
+{
+    const Model *m = handle_model(h);
+    if (!m)
+        return fail(HUBBARD_ERR_ARG, "null handle");
+    if (m->ansatz != 0)
+        return fail(HUBBARD_ERR_STATE, "the sector form needs the HVA circuit (the NP "
+                                       "ansatz's on-site gates change N_up and N_dn)");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(g_mu);
+    Entry &en = g_cache[std::make_pair(handle_uid(h), dev)];
+    if (!en.tab) {
+        std::unique_ptr<Tables> t(new Tables());
+        hubbard_status st = build_tables(*m, *t);
+        if (st != HUBBARD_OK)
+            return st;
+        en.tab = std::move(t);
+    }
+    *T = en.tab.get();
+    if (P) {
+        auto it = en.progs.find(layers);
+        if (it == en.progs.end()) {
+            std::unique_ptr<Program> p(new Program());
+            hubbard_status st = build_program(*m, *en.tab, layers, *p);
+            if (st != HUBBARD_OK)
+                return st;
+            it = en.progs.emplace(layers, std::move(p)).first;
+        }
+        *P = it->second.get();
+    }
+    return HUBBARD_OK;
+}
+
+size_t vec_elems(const Tables &T) { return (size_t)T.n[0] * (size_t)T.n[1]; }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <int MODE, bool GEN>
+void launch_rows_g(const Tables &T, const SecOp *ops, int n_ops, int col, int n_red,
+                   const double2 *ang, const double2 *dph, double2 *v0, double2 *v1,
+                   double *partial, int row0, int flags, hipStream_t s)
+{
+    const int nr = T.n[1 - col], n = T.n[col];
+    const int grid = std::min(nr, kGrid);
+    const size_t lds = lds_bytes(T);
+#define HV_SEC(R)                                                                               \
+    hipLaunchKernelGGL((k_sec_rows<MODE, R, GEN>), dim3(grid), dim3(kT), lds, s, ops, n_ops,    \
+                       col, n_red, ang, dph, T.d_model, v0, v1, partial, row0, kGrid, flags,    \
+                       T.xch)
+    if (n <= kT)
+        HV_SEC(1);
+    else if (n <= 2 * kT)
+        HV_SEC(2);
+    else if (n <= 4 * kT)
+        HV_SEC(4);
+    else if (n <= 8 * kT)
+        HV_SEC(8);
+    else
+        HV_SEC(13);
+#undef HV_SEC
+}
+
+template <int MODE>
+void launch_rows(const Tables &T, const SecOp *ops, int n_ops, int col, int n_red,
+                 const double2 *ang, const double2 *dph, double2 *v0, double2 *v1,
+                 double *partial, int row0, int flags, hipStream_t s)
+{
+    if (T.general)
+        launch_rows_g<MODE, true>(T, ops, n_ops, col, n_red, ang, dph, v0, v1, partial, row0,
+                                  flags, s);
+    else
+        launch_rows_g<MODE, false>(T, ops, n_ops, col, n_red, ang, dph, v0, v1, partial, row0,
+                                   flags, s);
+}
+
+void transpose(const Tables &T, int from_col, const double2 *in, double2 *out, bool add,
+               hipStream_t s)
+{
+    const int nr = T.n[1 - from_col], nc = T.n[from_col];
+    hipLaunchKernelGGL(k_sec_transpose, dim3((nc + 31) / 32, (nr + 31) / 32), dim3(256), 0, s,
+                       in, out, nr, nc, add ? 1 : 0);
+}
+
+void set_attrs()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const void *fns[] = {
+#define HV_SEC_FNS(MODE, GEN)                                                                   \
+    (const void *)k_sec_rows<MODE, 1, GEN>, (const void *)k_sec_rows<MODE, 2, GEN>,             \
+        (const void *)k_sec_rows<MODE, 4, GEN>, (const void *)k_sec_rows<MODE, 8, GEN>,         \
+        (const void *)k_sec_rows<MODE, 13, GEN>
+            HV_SEC_FNS(S_FWD, false), HV_SEC_FNS(S_REV, false), HV_SEC_FNS(S_HAM, false),
+            HV_SEC_FNS(S_FWD, true), HV_SEC_FNS(S_REV, true), HV_SEC_FNS(S_HAM, true)};
+#undef HV_SEC_FNS
+        for (const void *f : fns)
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+}
+
+double2 *dph_of(const Program &P, double2 *ang)
+{
+    return (double2 *)((char *)ang + align256((size_t)P.n_ops * 16));
+}
+
+// Angles of every op, then the diagonal phase tables.
+size_t ang_bytes(const Program &P)
+{
+    return align256((size_t)P.n_ops * 16) + align256((size_t)P.n_diag * kDiagTab * 16);
+}
+
+// ang[i] for every op of the program and dph (see k_sec_angles); dph follows ang.
+void angles(const Tables &T, const Program &P, const double *theta, double2 *ang, hipStream_t s)
+{
+    const int blocks = std::max(1, std::min(64, (P.n_ops + 255) / 256));
+    hipLaunchKernelGGL(k_sec_angles, dim3(blocks), dim3(256), 0, s, P.d_ops, P.n_ops, theta, T.U,
+                       ang, dph_of(P, ang));
+}
+
+// Forward sweep: psi starts in layout A in `a`; `b` is the layout-B buffer.
+// Returns the buffer holding the result (in layout P.final_col).
+double2 *forward(const Tables &T, const Program &P, const double2 *ang, double2 *a, double2 *b,
+                 hipStream_t s)
+{
+    double2 *cur = a;
+    int col = 0;
+    for (size_t i = 0; i < P.fwd.size(); ++i) {
+        const RowPass &p = P.fwd[i];
+        if (p.col != col) {
+            double2 *dst = (cur == a) ? b : a;
+            transpose(T, col, cur, dst, false, s);
+            cur = dst;
+            col = p.col;
+        }
+        launch_rows<S_FWD>(T, P.d_ops + P.op_off[i], (int)p.ops.size(), p.col, 0,
+                           ang + P.op_off[i], dph_of(P, (double2 *)ang), cur, nullptr, nullptr,
+                           0, 0, s);
+    }
+    return cur;
+}
+
+// phi_x <- H psi_x for psi_x in layout `col` (x): the col-spin hops and D in
+// layout x, the other spin's hops in the transposed layout; psi_y, phi_y are
+// scratch of the other layout.  Energy parts to partial rows 0 and 1.
+void hamiltonian(const Tables &T, const Program &P, int col, const double2 *psi_x,
+                 double2 *phi_x, double2 *psi_y, double2 *phi_y, double *partial, hipStream_t s,
+                 const SecOp *ops_x, int n_x, const SecOp *ops_y, int n_y)
+{
+    launch_rows<S_HAM>(T, ops_x, n_x, col, 1, nullptr, nullptr, (double2 *)psi_x, phi_x,
+                       partial, 0, 0, s);
+    transpose(T, col, psi_x, psi_y, false, s);
+    launch_rows<S_HAM>(T, ops_y, n_y, 1 - col, 1, nullptr, nullptr, psi_y, phi_y, partial, 1, 0,
+                       s);
+    transpose(T, 1 - col, phi_y, phi_x, true, s);
+}
+
+hubbard_status check(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(HUBBARD_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return HUBBARD_OK;
+}
+
+}  // namespace sec
+
+// Drop the sector tables and programs of a destroyed handle.
+void sector_forget(uint64_t uid)
+{
+    std::lock_guard<std::mutex> lk(sec::g_mu);
+    for (auto it = sec::g_cache.begin(); it != sec::g_cache.end();)
+        it = it->first.first == uid ? sec::g_cache.erase(it) : std::next(it);
+}
+
+}  // namespace hv
+
+using namespace hv;
+using namespace hv::sec;
+
+hubbard_status hubbard_sector_dim(hubbard_t h, int64_t *n_up, int64_t *n_dn)
+{
+    Tables *T = nullptr;
+    hubbard_status st = get(h, -1, &T, nullptr);
+    if (st != HUBBARD_OK)
+        return st;
+    if (n_up)
+        *n_up = T->n[0];
+    if (n_dn)
+        *n_dn = T->n[1];
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_sector_workspace_size(hubbard_t h, int32_t n_layers, int32_t op,
+                                             size_t *bytes)
+{
+    if (!bytes || n_layers < 0 || op < HUBBARD_SECTOR_ANSATZ || op > HUBBARD_SECTOR_HAMILTONIAN)
+        return set_error(HUBBARD_ERR_ARG, "bad arguments to hubbard_sector_workspace_size");
+    Tables *T = nullptr;
+    Program *P = nullptr;
+    hubbard_status st = get(h, op == HUBBARD_SECTOR_HAMILTONIAN ? 0 : n_layers, &T, &P);
+    if (st != HUBBARD_OK)
+        return st;
+    const size_t v = align256(vec_elems(*T) * 16);
+    if (op == HUBBARD_SECTOR_ANSATZ)
+        *bytes = v + ang_bytes(*P);
+    else if (op == HUBBARD_SECTOR_HAMILTONIAN)
+        *bytes = 2 * v;
+    else
+        *bytes = 4 * v + align256((size_t)P->n_rows * kGrid * 8) + ang_bytes(*P);
+    return HUBBARD_OK;
+}
+
+hubbard_status hubbard_sector_init_neel(hubbard_t h, void *psi_dev, void *stream)
+{
+    Tables *T = nullptr;
+    hubbard_status st = get(h, -1, &T, nullptr);
+    if (st != HUBBARD_OK)
+        return st;
+    if (!psi_dev)
+        return set_error(HUBBARD_ERR_ARG, "null vector");
+    hipLaunchKernelGGL(k_sec_basis, dim3(2048), dim3(256), 0, (hipStream_t)stream,
+                       (double2 *)psi_dev, vec_elems(*T), T->b0_pos);
+    return check("sector init");
+}
+
+hubbard_status sector_ansatz_apply(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                                   void *psi_dev, void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (n_layers < 0 || !psi_dev || (n_layers > 0 && !theta_dev))
+        return set_error(HUBBARD_ERR_ARG, "bad arguments to sector_ansatz_apply");
+    Tables *T = nullptr;
+    Program *P = nullptr;
+    hubbard_status st = get(h, n_layers, &T, &P);
+    if (st != HUBBARD_OK)
+        return st;
+    const size_t v = align256(vec_elems(*T) * 16);
+    if (!ws_dev || ws_bytes < v + ang_bytes(*P))
+        return set_error(HUBBARD_ERR_SIZE, "workspace too small for sector_ansatz_apply");
+    set_attrs();
+    hipStream_t s = (hipStream_t)stream;
+    double2 *ang = (double2 *)((char *)ws_dev + v);
+    if (n_layers > 0)
+        angles(*T, *P, theta_dev, ang, s);
+    double2 *out = forward(*T, *P, ang, (double2 *)psi_dev, (double2 *)ws_dev, s);
+    if (out != (double2 *)psi_dev)   // ended in layout B
+        transpose(*T, 1, out, (double2 *)psi_dev, false, s);
+    return check("sector ansatz");
+}
+
+hubbard_status sector_hamiltonian_apply(hubbard_t h, const void *psi_dev, void *out_dev,
+                                        void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (!psi_dev || !out_dev || psi_dev == out_dev)
+        return set_error(HUBBARD_ERR_ARG, "sector_hamiltonian_apply needs distinct vectors");
+    Tables *T = nullptr;
+    Program *P = nullptr;
+    hubbard_status st = get(h, 0, &T, &P);
+    if (st != HUBBARD_OK)
+        return st;
+    const size_t v = align256(vec_elems(*T) * 16);
+    if (!ws_dev || ws_bytes < 2 * v)
+        return set_error(HUBBARD_ERR_SIZE, "workspace too small for sector_hamiltonian_apply");
+    set_attrs();
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws_dev;
+    // the 0-layer program's H ops: layout A (up hops and D), then B (down
+    // hops); no reduction rows (no energy)
+    double2 *psi_b = (double2 *)w, *phi_b = (double2 *)(w + v);
+    launch_rows<S_HAM>(*T, P->d_ops + P->ham_x_off, P->ham_x_n, 0, 0, nullptr, nullptr,
+                       (double2 *)psi_dev, (double2 *)out_dev, nullptr, 0, 0, s);
+    transpose(*T, 0, (const double2 *)psi_dev, psi_b, false, s);
+    launch_rows<S_HAM>(*T, P->d_ops + P->ham_y_off, P->ham_y_n, 1, 0, nullptr, nullptr, psi_b,
+                       phi_b, nullptr, 0, 0, s);
+    transpose(*T, 1, phi_b, (double2 *)out_dev, true, s);
+    return check("sector H");
+}
+
+hubbard_status sector_energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,
+                                  double *E_dev, double *grad_dev, void *ws_dev, size_t ws_bytes,
+                                  void *stream)
+{
+    if (n_layers < 0 || !E_dev || (n_layers > 0 && (!theta_dev || !grad_dev)))
+        return set_error(HUBBARD_ERR_ARG, "bad arguments to sector_energy_grad");
+    Tables *T = nullptr;
+    Program *P = nullptr;
+    hubbard_status st = get(h, n_layers, &T, &P);
+    if (st != HUBBARD_OK)
+        return st;
+    const size_t v = align256(vec_elems(*T) * 16);
+    const size_t pbytes = align256((size_t)P->n_rows * kGrid * 8);
+    if (!ws_dev || ws_bytes < 4 * v + pbytes + ang_bytes(*P))
+        return set_error(HUBBARD_ERR_SIZE, "workspace too small for sector_energy_grad");
+    set_attrs();
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws_dev;
+    double2 *psi[2] = {(double2 *)w, (double2 *)(w + v)};
+    double2 *lam[2] = {(double2 *)(w + 2 * v), (double2 *)(w + 3 * v)};
+    double *partial = (double *)(w + 4 * v);
+    double2 *ang = (double2 *)(w + 4 * v + pbytes);
+    if (n_layers > 0)
+        angles(*T, *P, theta_dev, ang, s);
+    hipLaunchKernelGGL(k_sec_basis, dim3(2048), dim3(256), 0, s, psi[0], vec_elems(*T),
+                       T->b0_pos);
+    double2 *end = forward(*T, *P, ang, psi[0], psi[1], s);
+    int col = P->final_col;
+    if (end != psi[col]) {   // cannot happen: layout A lives in psi[0], B in psi[1]
+        return set_error(HUBBARD_ERR_STATE, "sector forward ended in the wrong buffer");
+    }
+    // lambda = H psi in the final layout; the partial rows 0 and 1 get E
+    hamiltonian(*T, *P, col, psi[col], lam[col], psi[1 - col], lam[1 - col], partial, s,
+                P->d_ops + P->ham_x_off, P->ham_x_n, P->d_ops + P->ham_y_off, P->ham_y_n);
+    // reverse sweep
+    for (int i = (int)P->fwd.size() - 1; i >= 0; --i) {
+        const RowPass &p = P->fwd[i];
+        if (p.col != col) {
+            transpose(*T, col, psi[col], psi[p.col], false, s);
+            transpose(*T, col, lam[col], lam[p.col], false, s);
+            col = p.col;
+        }
+        launch_rows<S_REV>(*T, P->d_ops + P->op_off[i], (int)p.ops.size(), p.col,
+                           (int)p.red_param.size(), ang + P->op_off[i], dph_of(*P, ang), psi[col],
+                           lam[col], partial, P->red_row0[i], i == 0 ? SF_NO_STORE : 0, s);
+    }
+    hipLaunchKernelGGL(k_sec_reduce, dim3(P->n_out), dim3(256), 0, s, partial, kGrid,
+                       P->d_nblk, P->d_ptr, P->d_rows, P->d_scale, E_dev, grad_dev);
+    return check("sector energy_grad");
+}

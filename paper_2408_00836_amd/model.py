@@ -281,6 +281,58 @@ class Hubbard:
                               _stream(), opts)
         return th, res
 
+    # ---- particle-number sector form (HVA only; see hubbard_sector_dim) ----
+    def sector_dims(self):
+        """(C(Ns, N_up), C(Ns, N_dn)): a sector vector holds their product,
+        element r_dn * C(Ns, N_up) + r_up."""
+        return abi.hubbard_sector_dim(self.handle)
+
+    def _sector_ws(self, layers: int, op: int, device) -> torch.Tensor:
+        nb = abi.hubbard_sector_workspace_size(self.handle, layers, op)
+        cache = self.__dict__.setdefault("_sector_ws_cache", {})
+        key = (op, str(device))
+        ws = cache.get(key)
+        if ws is None or ws.numel() < nb:
+            cache.pop(key, None)
+            torch.cuda.empty_cache()
+            ws = cache[key] = torch.empty(nb, dtype=torch.uint8, device=device)
+        return ws
+
+    def sector_state(self, theta: torch.Tensor | None = None) -> torch.Tensor:
+        """psi(theta) as a sector vector (|b0> when theta is None)."""
+        nu, nd = self.sector_dims()
+        dev = theta.device if theta is not None else torch.device("cuda")
+        psi = torch.empty(nu * nd, dtype=torch.complex128, device=dev)
+        abi.hubbard_sector_init_neel(self.handle, psi.data_ptr(), _stream())
+        if theta is not None:
+            L = self._layers(theta)
+            ws = self._sector_ws(L, abi.HUBBARD_SECTOR_ANSATZ, dev)
+            abi.sector_ansatz_apply(self.handle, theta.data_ptr(), L, psi.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream())
+        return psi
+
+    def sector_apply_h(self, psi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _require_gpu(psi, "psi", torch.complex128)
+        if out is None:
+            out = torch.empty_like(psi)
+        ws = self._sector_ws(0, abi.HUBBARD_SECTOR_HAMILTONIAN, psi.device)
+        abi.sector_hamiltonian_apply(self.handle, psi.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                                     ws.numel(), _stream())
+        return out
+
+    def sector_energy_grad(self, theta: torch.Tensor, E: torch.Tensor | None = None,
+                           grad: torch.Tensor | None = None):
+        """energy_grad in the sector form (same results, 1/26 of the bytes at 4x4)."""
+        L = self._layers(theta)
+        ws = self._sector_ws(L, abi.HUBBARD_SECTOR_ENERGY_GRAD, theta.device)
+        if E is None:
+            E = torch.empty(1, dtype=torch.float64, device=theta.device)
+        if grad is None:
+            grad = torch.empty(theta.numel(), dtype=torch.float64, device=theta.device)
+        abi.sector_energy_grad(self.handle, theta.data_ptr(), L, E.data_ptr(), grad.data_ptr(),
+                               ws.data_ptr(), ws.numel(), _stream())
+        return E, grad
+
     def workspace_views(self, layers: int):
         """Two plain vector buffers carved out of the energy_grad workspace
         (scratch for ansatz/apply_h at the benchmark size; energy_grad stores
