@@ -108,6 +108,62 @@ def batch_bench(torch, dev, reps=3):
                        "source": b.config_source, "instance_tiles": tiles_src}}
 
 
+def sector_bench(torch, dev, w, reps=3):
+    """The particle-number sector form of the same workload: energy+gradient
+    evaluations on the C(Ns,N_dn) x C(Ns,N_up) sector amplitudes (the circuit
+    state's only nonzero ones), and H on a sector vector.  Algorithmic bytes
+    per evaluation: every row pass reads and writes its vectors once (the
+    forward one vector, the reverse two), every transpose reads and writes
+    them once, H reads psi and writes phi in both layouts."""
+    import numpy as np
+    from paper_2408_00836_amd.model import Hubbard
+    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    nu, nd = m.sector_dims()
+    dim = nu * nd
+    th = torch.tensor(w.theta, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(w.n_params, dtype=torch.float64, device=dev)
+    m.sector_energy_grad(th, E, g)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        m.sector_energy_grad(th, E, g)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - a)
+    t = min(ts)
+    psi = m.sector_state(th)
+    phi = torch.empty_like(psi)
+    m.sector_apply_h(psi, phi)
+    torch.cuda.synchronize()
+    hs = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        m.sector_apply_h(psi, phi)
+        torch.cuda.synchronize()
+        hs.append(time.perf_counter() - a)
+    th_ = min(hs)
+    L = w.layers
+    passes = L + 1 if L else 0
+    vec = 16.0 * dim
+    # forward: passes x 2 vec + L transposes x 2 vec; H: 2 row passes (psi
+    # read, phi written) + 2 transposes + the transpose-add (3 vec); reverse:
+    # passes x 4 vec (the last one reads only: 2) + L transposes of psi and
+    # lambda (4 vec each)
+    fwd = passes * 2 + L * 2
+    ham = 2 * 2 + 2 + 3
+    rev = (passes * 4 - 2) + L * 4
+    alg = (fwd + ham + rev) * vec
+    return {"workload": w.name + ", sector form", "sector_dims": [nu, nd],
+            "amplitudes": dim, "bytes_per_vector": vec,
+            "evals_per_s": 1.0 / t, "ms_per_eval": t * 1e3,
+            "E": float(E.item()), "row_passes_per_sweep": passes, "transposes_per_sweep": L,
+            "algorithmic_bytes_per_eval": alg, "algorithmic_GBs": alg / t / 1e9,
+            "frac_of_hbm_peak": alg / t / 1e9 / HBM_PEAK_GBS,
+            "hpsi_ms": th_ * 1e3, "hpsi_algorithmic_GBs": 2 * vec / th_ / 1e9,
+            "hpsi_bytes_moved_GBs": (2 * 2 + 2 + 3) * vec / th_ / 1e9}
+
+
 def copy_reference(torch, dev, gib=8, reps=3):
     """Bandwidth of a plain device copy (torch elementwise kernel, `gib` GiB
     read + `gib` GiB written): the practical HBM ceiling for an in-place
@@ -226,6 +282,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sector", action="store_true")
+    ap.add_argument("--sector-only", action="store_true",
+                    help="time only the sector form (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -239,6 +298,10 @@ def main():
 
     dev = torch.device("cuda:0")
     w = pick_workload(args.config)
+    if args.sector_only:
+        sec = sector_bench(torch, dev, w)
+        print(json.dumps({"sector": sec}), flush=True)
+        return
     m = Hubbard(w.nx, w.ny, **w.kwargs())
     th = torch.tensor(w.theta, dtype=torch.float64, device=dev)
     L, P, n = w.layers, w.n_params, w.n_qubits
@@ -340,6 +403,12 @@ def main():
     copy = copy_reference(torch, dev)
     log(f"[bench] plain copy: {copy['GBs']:.0f} GB/s")
 
+    sector = None
+    if not args.no_sector:
+        log("[bench] sector form")
+        sector = sector_bench(torch, dev, w)
+        log(f"[bench] sector: {sector['ms_per_eval']:.1f} ms per evaluation")
+
     batch = None
     if not args.no_batch:
         log("[bench] batch of 256 uneven instances")
@@ -380,6 +449,7 @@ def main():
                                                     "reverse": rev_ms / args.steps}),
         "copy_reference": copy,
         "batch": batch,
+        "sector": sector,
         "hpsi": {"ms": h_ms, "algorithmic_GBs": h_gbs, "frac": h_gbs / HBM_PEAK_GBS,
                  "passes": n_ham},
         "fd_plain": fd,

@@ -114,7 +114,7 @@ __device__ __forceinline__ double wave_sum(double x)
 
 // Row pass.  Each workgroup takes rows blockIdx.x, blockIdx.x + gridDim.x, ...
 // of the layout whose columns are indexed by spin `col`; thread t holds the
-// row's elements t + j kT, j < RPT.
+// row's elements t + j TT, j < RPT.
 //   S_FWD: v0 <- ops applied in order.
 //   S_REV: (v0, v1) = (psi, lambda) <- ops un-applied in reverse order; the
 //          bracket Im <lambda| G |psi> of every op before its un-application
@@ -135,7 +135,7 @@ typedef const __attribute__((address_space(1))) uint32_t gu32;
 typedef const __attribute__((address_space(1))) double gf64;
 typedef __attribute__((address_space(1))) double2 gc128;
 
-template <int RPT>
+template <int TT, int RPT>
 __device__ __forceinline__ Codes<RPT> load_codes(const gu32 *__restrict__ ct, uint32_t tid,
                                                  uint32_t n)
 {
@@ -144,7 +144,7 @@ __device__ __forceinline__ Codes<RPT> load_codes(const gu32 *__restrict__ ct, ui
     Codes<RPT> c;
 #pragma unroll
     for (int j = 0; j < RPT; j += 2) {
-        const uint32_t i0 = tid + j * kT, i1 = i0 + kT;
+        const uint32_t i0 = tid + j * TT, i1 = i0 + TT;
         const uint32_t v0 = ct[min(i0, n - 1)];
         const uint32_t lo = i0 < n ? v0 : kNone;
         uint32_t hi = kNone;
@@ -196,7 +196,7 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
 
 // Row pass.  Each workgroup takes rows blockIdx.x, blockIdx.x + gridDim.x, ...
 // of the layout whose columns are indexed by spin `col`; thread t holds the
-// row's elements t + j kT, j < RPT.
+// row's elements t + j TT, j < RPT.
 //   S_FWD: v0 <- ops applied in order.
 //   S_REV: (v0, v1) = (psi, lambda) <- ops un-applied in reverse order; the
 //          bracket Im <lambda| G |psi> of every op before its un-application
@@ -208,17 +208,18 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
 // GEN: the diagonal has eps or V terms (D from the pattern tables, its phase
 // by cis_neg); else D = U #(doubly occupied) and its phase comes from the
 // op's table dph[op.tab][k] = exp(-i th U k).
-template <int MODE, int RPT, bool GEN>
-__global__ void __launch_bounds__(kT)
+template <int MODE, int TT, int RPT, bool GEN>
+__global__ void __launch_bounds__(TT)
 k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
            const double2 *__restrict__ ang, const double2 *__restrict__ dph,
            const SecModel *__restrict__ M, double2 *__restrict__ v0, double2 *__restrict__ v1,
            double *__restrict__ partial, int row0, int pstride, int flags, int xch_elems)
 {
+    constexpr int kWv = TT / 64;   // waves of the workgroup
     extern __shared__ __align__(16) char smem[];
     double2 *xch = (double2 *)smem;                            // pair slots
     double *acc = (double *)(smem + (size_t)xch_elems * 16);   // kMaxRed x kWaves
-    double2 *cis = (double2 *)(acc + kMaxRed * kWaves);         // unit phases
+    double2 *cis = (double2 *)(acc + kMaxRed * kWv);         // unit phases
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t n = (uint32_t)M->n[col];
     const int nr = M->n[1 - col];
@@ -229,10 +230,10 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     const gu32 *__restrict__ gcode = (const gu32 *)M->code;
     const gu32 *__restrict__ rpat = (const gu32 *)M->pat[1 - col];
     const gf64 *__restrict__ rbase = (const gf64 *)M->base[1 - col];
-    for (int i = tid; i < kMaxRed * kWaves; i += kT)
+    for (int i = tid; i < kMaxRed * kWv; i += TT)
         acc[i] = 0.0;
     if constexpr (MODE != S_HAM && GEN)
-        build_cis(cis, tid, kT);
+        build_cis(cis, tid, TT);
     __syncthreads();
     double eacc = 0.0;
 
@@ -248,7 +249,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
         double2 a[RPT], b[RPT];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-            const uint32_t idx = tr + j * kT, ic = min(idx, n - 1);
+            const uint32_t idx = tr + j * TT, ic = min(idx, n - 1);
             const bool in = idx < n;
             a[j] = make_double2(x0[ic].x, x0[ic].y);
             a[j] = in ? a[j] : make_double2(0.0, 0.0);
@@ -273,7 +274,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     th = ang[io].x;
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) {
-                    const uint32_t ic = min(t + j * kT, n - 1);   // past the end: a zero element
+                    const uint32_t ic = min(t + j * TT, n - 1);   // past the end: a zero element
                     {
                         const uint32_t cp = cpat[ic];
                         const uint32_t k = __popc(rp & cp);
@@ -312,7 +313,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     sn = MODE == S_REV ? -cssn.y : cssn.y;   // un-apply: sin -> -sin
                 }
                 const double mt = -op.t;
-                const Codes<RPT> cd = load_codes<RPT>(gcode + op.tab, t, n);
+                const Codes<RPT> cd = load_codes<TT, RPT>(gcode + op.tab, t, n);
                 // w = sign (active) or 0 (inactive: cos factor 1, no partner term)
                 exchange<RPT>(a, cd, xch, [&](int j, double2 p, double w) {
                     if constexpr (MODE == S_HAM) {   // phi += (-t) s psi_x'
@@ -343,7 +344,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
             if constexpr (MODE == S_REV) {
                 const double w = wave_sum(racc);
                 if (lane == 0)
-                    acc[op.red * kWaves + wave] += w;
+                    acc[op.red * kWv + wave] += w;
             }
         }
         if constexpr (MODE == S_HAM) {
@@ -357,7 +358,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
             asm volatile("" : "+v"(t));
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
-                const uint32_t idx = t + j * kT;
+                const uint32_t idx = t + j * TT;
                 if (idx < n) {
                     if constexpr (MODE != S_HAM) {
                         x0[idx].x = a[j].x;
@@ -380,8 +381,8 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     if constexpr (MODE != S_FWD) {
         if (tid < n_red) {
             double s = 0.0;
-            for (int w = 0; w < kWaves; ++w)
-                s += acc[tid * kWaves + w];
+            for (int w = 0; w < kWv; ++w)
+                s += acc[tid * kWv + w];
             partial[(size_t)(row0 + tid) * pstride + blockIdx.x] = s;
         }
     }
@@ -559,7 +560,7 @@ int popc(uint32_t x) { return __builtin_popcount(x); }
 // LDS of a row workgroup: the pair slots, the reduction slots, the unit phases.
 size_t lds_bytes(const Tables &T)
 {
-    return (size_t)T.xch * 16 + kMaxRed * kWaves * 8 + (1u << kCisBits) * 16;
+    return (size_t)T.xch * 16 + kMaxRed * kWaves * 8 + (1u << kCisBits) * 16;   // kWaves: the widest
 }
 
 hubbard_status build_tables(const Model &m, Tables &T)
@@ -828,6 +829,9 @@ hubbard_status get(hubbard_t h, int layers, Tables **T, Program **P)
 size_t vec_elems(const Tables &T) { return (size_t)T.n[0] * (size_t)T.n[1]; }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Workgroup shape by row length: 1024 threads holding up to 13 elements of
+// each vector (two-vector passes of the longest rows spill part of their
+// tile to scratch memory; 256 threads holding 51 elements each spilled more).
 template <int MODE, bool GEN>
 void launch_rows_g(const Tables &T, const SecOp *ops, int n_ops, int col, int n_red,
                    const double2 *ang, const double2 *dph, double2 *v0, double2 *v1,
@@ -836,20 +840,20 @@ void launch_rows_g(const Tables &T, const SecOp *ops, int n_ops, int col, int n_
     const int nr = T.n[1 - col], n = T.n[col];
     const int grid = std::min(nr, kGrid);
     const size_t lds = lds_bytes(T);
-#define HV_SEC(R)                                                                               \
-    hipLaunchKernelGGL((k_sec_rows<MODE, R, GEN>), dim3(grid), dim3(kT), lds, s, ops, n_ops,    \
-                       col, n_red, ang, dph, T.d_model, v0, v1, partial, row0, kGrid, flags,    \
-                       T.xch)
+#define HV_SEC(TT, R)                                                                           \
+    hipLaunchKernelGGL((k_sec_rows<MODE, TT, R, GEN>), dim3(grid), dim3(TT), lds, s, ops,       \
+                       n_ops, col, n_red, ang, dph, T.d_model, v0, v1, partial, row0, kGrid,    \
+                       flags, T.xch)
     if (n <= kT)
-        HV_SEC(1);
+        HV_SEC(kT, 1);
     else if (n <= 2 * kT)
-        HV_SEC(2);
+        HV_SEC(kT, 2);
     else if (n <= 4 * kT)
-        HV_SEC(4);
+        HV_SEC(kT, 4);
     else if (n <= 8 * kT)
-        HV_SEC(8);
+        HV_SEC(kT, 8);
     else
-        HV_SEC(13);
+        HV_SEC(kT, 13);
 #undef HV_SEC
 }
 
@@ -880,9 +884,9 @@ void set_attrs()
     std::call_once(once, [] {
         const void *fns[] = {
 #define HV_SEC_FNS(MODE, GEN)                                                                   \
-    (const void *)k_sec_rows<MODE, 1, GEN>, (const void *)k_sec_rows<MODE, 2, GEN>,             \
-        (const void *)k_sec_rows<MODE, 4, GEN>, (const void *)k_sec_rows<MODE, 8, GEN>,         \
-        (const void *)k_sec_rows<MODE, 13, GEN>
+    (const void *)k_sec_rows<MODE, kT, 1, GEN>, (const void *)k_sec_rows<MODE, kT, 2, GEN>,     \
+        (const void *)k_sec_rows<MODE, kT, 4, GEN>, (const void *)k_sec_rows<MODE, kT, 8, GEN>, \
+        (const void *)k_sec_rows<MODE, kT, 13, GEN>
             HV_SEC_FNS(S_FWD, false), HV_SEC_FNS(S_REV, false), HV_SEC_FNS(S_HAM, false),
             HV_SEC_FNS(S_FWD, true), HV_SEC_FNS(S_REV, true), HV_SEC_FNS(S_HAM, true)};
 #undef HV_SEC_FNS
