@@ -58,7 +58,7 @@ constexpr int kMaxRows = 13 * kT;         // longest row: C(16, 8) = 12870
 
 enum { S_FWD = 0, S_REV = 1, S_HAM = 2 };
 enum { SOP_HOP = 0, SOP_DIAG = 1 };
-enum { SF_NO_STORE = 1 };
+enum { SF_NO_STORE = 1, SF_NEGATE = 2 };
 
 // One operation of a row pass (32 bytes).  HOP: the gate exp(-i th t h) of
 // one bond and spin (h = a+_i a_j + h.c. on that spin's sites); DIAG: the
@@ -112,17 +112,6 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-// Row pass.  Each workgroup takes rows blockIdx.x, blockIdx.x + gridDim.x, ...
-// of the layout whose columns are indexed by spin `col`; thread t holds the
-// row's elements t + j TT, j < RPT.
-//   S_FWD: v0 <- ops applied in order.
-//   S_REV: (v0, v1) = (psi, lambda) <- ops un-applied in reverse order; the
-//          bracket Im <lambda| G |psi> of every op before its un-application
-//          goes to its reduction slot.
-//   S_HAM: v1 <- sum of the ops' generators applied to v0 (D if a DIAG op
-//          is present), slot 0 <- Re <v0|v1>.
-// Reductions: per-wave sums in LDS, then per workgroup one partial per slot
-// at partial[(row0 + slot) * pstride + blockIdx.x] (fixed order).
 // Two 16-bit gate codes per register (pair slot | sign << 15; 0xFFFF: the
 // element is left alone).
 template <int RPT>
@@ -198,9 +187,13 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
 // of the layout whose columns are indexed by spin `col`; thread t holds the
 // row's elements t + j TT, j < RPT.
 //   S_FWD: v0 <- ops applied in order.
-//   S_REV: (v0, v1) = (psi, lambda) <- ops un-applied in reverse order; the
-//          bracket Im <lambda| G |psi> of every op before its un-application
-//          goes to its reduction slot.
+//   S_REV: v0 = chi <- ops un-applied in reverse order; the expectation
+//          <chi| G |chi> of every op before its un-application goes to its
+//          reduction slot (negated with SF_NEGATE).  The adjoint bracket
+//          Im <lambda|G|psi> is (<chi2|G|chi2> - <chi1|G|chi1>) / 4 with
+//          chi1, chi2 = lambda +- i psi, both of which evolve by the same
+//          un-applied gates: two one-vector sweeps instead of one sweep
+//          holding both psi and lambda.
 //   S_HAM: v1 <- sum of the ops' generators applied to v0 (D if a DIAG op
 //          is present), slot 0 <- Re <v0|v1>.
 // Reductions: per-wave sums in LDS, then per workgroup one partial per slot
@@ -216,10 +209,11 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
            double *__restrict__ partial, int row0, int pstride, int flags, int xch_elems)
 {
     constexpr int kWv = TT / 64;   // waves of the workgroup
+    constexpr bool REV = MODE == S_REV;
     extern __shared__ __align__(16) char smem[];
     double2 *xch = (double2 *)smem;                            // pair slots
     double *acc = (double *)(smem + (size_t)xch_elems * 16);   // kMaxRed x kWaves
-    double2 *cis = (double2 *)(acc + kMaxRed * kWv);         // unit phases
+    double2 *cis = (double2 *)(acc + kMaxRed * kWv);           // unit phases
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t n = (uint32_t)M->n[col];
     const int nr = M->n[1 - col];
@@ -250,18 +244,12 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
             const uint32_t idx = tr + j * TT, ic = min(idx, n - 1);
-            const bool in = idx < n;
             a[j] = make_double2(x0[ic].x, x0[ic].y);
-            a[j] = in ? a[j] : make_double2(0.0, 0.0);
-            if constexpr (MODE == S_REV) {
-                b[j] = make_double2(x1[ic].x, x1[ic].y);
-                b[j] = in ? b[j] : make_double2(0.0, 0.0);
-            } else {
-                b[j] = make_double2(0.0, 0.0);
-            }
+            a[j] = idx < n ? a[j] : make_double2(0.0, 0.0);
+            b[j] = make_double2(0.0, 0.0);
         }
         for (int oi = 0; oi < n_ops; ++oi) {
-            const int io = MODE == S_REV ? n_ops - 1 - oi : oi;
+            const int io = REV ? n_ops - 1 - oi : oi;
             const SecOp op = ops[io];
             double racc = 0.0;
             // the element indices recomputed per op, not kept live (with
@@ -287,18 +275,15 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                             // exp(-i th D) forward, exp(+i th D) to un-apply
                             double2 e;
                             if constexpr (GEN) {
-                                e = cis_neg(MODE == S_REV ? -th * d : th * d, cis);
+                                e = cis_neg(REV ? -th * d : th * d, cis);
                             } else {
                                 e = dph[(size_t)op.tab * kDiagTab + k];
-                                if constexpr (MODE == S_REV)
+                                if constexpr (REV)
                                     e.y = -e.y;
                             }
-                            if constexpr (MODE == S_REV) {
-                                racc += d * (b[j].x * a[j].y - b[j].y * a[j].x);
-                                const double2 l = b[j];
-                                b[j] = make_double2(e.x * l.x - e.y * l.y, e.x * l.y + e.y * l.x);
-                            }
                             const double2 p = a[j];
+                            if constexpr (REV)   // <chi|D|chi> term
+                                racc += d * (p.x * p.x + p.y * p.y);
                             a[j] = make_double2(e.x * p.x - e.y * p.y, e.x * p.y + e.y * p.x);
                         }
                     }
@@ -310,7 +295,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                 if constexpr (MODE != S_HAM) {
                     const double2 cssn = ang[io];   // (cos, sin)(th t)
                     cs = cssn.x;
-                    sn = MODE == S_REV ? -cssn.y : cssn.y;   // un-apply: sin -> -sin
+                    sn = REV ? -cssn.y : cssn.y;    // un-apply: sin -> -sin
                 }
                 const double mt = -op.t;
                 const Codes<RPT> cd = load_codes<TT, RPT>(gcode + op.tab, t, n);
@@ -321,27 +306,19 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                         b[j].y += mt * w * p.y;
                         pin(b[j]);
                     } else {
-                        if constexpr (MODE == S_REV) {   // (-t) s Im(conj(lambda_x) psi_x')
-                            racc += mt * w * (b[j].x * p.y - b[j].y * p.x);
+                        const double2 y = a[j];
+                        if constexpr (REV) {   // <chi|h|chi> term: (-t) s Re(conj(chi_x) chi_x')
+                            racc += mt * w * (y.x * p.x + y.y * p.y);
                             pin(racc);
                         }
                         const double ss = w * sn;      // x <- cs x + i s sn x'
                         const double c = w != 0.0 ? cs : 1.0;
-                        const double2 y = a[j];
                         a[j] = make_double2(c * y.x - ss * p.y, c * y.y + ss * p.x);
                         pin(a[j]);
                     }
                 });
-                if constexpr (MODE == S_REV)
-                    exchange<RPT>(b, cd, xch, [&](int j, double2 p, double w) {
-                        const double ss = w * sn;
-                        const double c = w != 0.0 ? cs : 1.0;
-                        const double2 y = b[j];
-                        b[j] = make_double2(c * y.x - ss * p.y, c * y.y + ss * p.x);
-                        pin(b[j]);
-                    });
             }
-            if constexpr (MODE == S_REV) {
+            if constexpr (REV) {
                 const double w = wave_sum(racc);
                 if (lane == 0)
                     acc[op.red * kWv + wave] += w;
@@ -363,8 +340,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     if constexpr (MODE != S_HAM) {
                         x0[idx].x = a[j].x;
                         x0[idx].y = a[j].y;
-                    }
-                    if constexpr (MODE != S_FWD) {
+                    } else {
                         x1[idx].x = b[j].x;
                         x1[idx].y = b[j].y;
                     }
@@ -383,8 +359,20 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
             double s = 0.0;
             for (int w = 0; w < kWv; ++w)
                 s += acc[tid * kWv + w];
-            partial[(size_t)(row0 + tid) * pstride + blockIdx.x] = s;
+            partial[(size_t)(row0 + tid) * pstride + blockIdx.x] = (flags & SF_NEGATE) ? -s : s;
         }
+    }
+}
+
+// chi1 <- lambda + i psi in psi's place, chi2 <- lambda - i psi in lambda's.
+__global__ void __launch_bounds__(256)
+k_sec_mix(double2 *__restrict__ psi, double2 *__restrict__ lam, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double2 p = psi[i], l = lam[i];
+        psi[i] = make_double2(l.x - p.y, l.y + p.x);
+        lam[i] = make_double2(l.x + p.y, l.y - p.x);
     }
 }
 
@@ -522,7 +510,7 @@ struct Program {
     int ham_x_off = 0, ham_x_n = 0, ham_y_off = 0, ham_y_n = 0;
     // reduction: partial rows 0, 1 = the two energy parts, then each reverse
     // pass's slots (forward order of passes)
-    std::vector<int> red_row0;    // per forward pass
+    std::vector<int> red_row0;    // per forward pass: its chi2 rows, then its chi1 rows
     int n_rows = 0;
     int32_t *d_ptr = nullptr, *d_rows = nullptr, *d_nblk = nullptr;
     double *d_scale = nullptr;
@@ -760,18 +748,21 @@ hubbard_status build_program(const Model &m, const Tables &T, int layers, Progra
     rows_of[0] = {0, 1};
     for (const RowPass &p : P.fwd) {
         P.red_row0.push_back(P.n_rows);
-        for (size_t s = 0; s < p.red_param.size(); ++s) {
-            rows_of[1 + p.red_param[s]].push_back(P.n_rows + (int)s);
-            nblk.push_back(grid_of(p.col));
+        for (int half = 0; half < 2; ++half) {   // chi2, then chi1 (stored negated)
+            for (size_t s = 0; s < p.red_param.size(); ++s) {
+                rows_of[1 + p.red_param[s]].push_back(P.n_rows + (int)s);
+                nblk.push_back(grid_of(p.col));
+            }
+            P.n_rows += (int)p.red_param.size();
         }
-        P.n_rows += (int)p.red_param.size();
     }
     std::vector<int32_t> ptr{0}, rows;
     std::vector<double> scale;
     for (size_t o = 0; o < rows_of.size(); ++o) {
         rows.insert(rows.end(), rows_of[o].begin(), rows_of[o].end());
         ptr.push_back((int32_t)rows.size());
-        scale.push_back(o == 0 ? 1.0 : 2.0);   // dE/dth_k = 2 Im <lambda_k|G_k|psi_k>
+        // dE/dth_k = 2 Im <lambda_k|G_k|psi_k> = (<chi2|G_k|chi2> - <chi1|G_k|chi1>) / 2
+        scale.push_back(o == 0 ? 1.0 : 0.5);
     }
     P.n_out = (int)rows_of.size();
     P.n_ops = (int)all.size();
@@ -1106,7 +1097,11 @@ hubbard_status sector_energy_grad(hubbard_t h, const double *theta_dev, int32_t 
     // lambda = H psi in the final layout; the partial rows 0 and 1 get E
     hamiltonian(*T, *P, col, psi[col], lam[col], psi[1 - col], lam[1 - col], partial, s,
                 P->d_ops + P->ham_x_off, P->ham_x_n, P->d_ops + P->ham_y_off, P->ham_y_n);
-    // reverse sweep
+    // reverse sweep on chi1 = lambda + i psi (psi's buffers) and chi2 =
+    // lambda - i psi (lambda's): brackets from their expectations
+    if (!P->fwd.empty())
+        hipLaunchKernelGGL(k_sec_mix, dim3(2048), dim3(256), 0, s, psi[col], lam[col],
+                           vec_elems(*T));
     for (int i = (int)P->fwd.size() - 1; i >= 0; --i) {
         const RowPass &p = P->fwd[i];
         if (p.col != col) {
@@ -1114,9 +1109,13 @@ hubbard_status sector_energy_grad(hubbard_t h, const double *theta_dev, int32_t 
             transpose(*T, col, lam[col], lam[p.col], false, s);
             col = p.col;
         }
-        launch_rows<S_REV>(*T, P->d_ops + P->op_off[i], (int)p.ops.size(), p.col,
-                           (int)p.red_param.size(), ang + P->op_off[i], dph_of(*P, ang), psi[col],
-                           lam[col], partial, P->red_row0[i], i == 0 ? SF_NO_STORE : 0, s);
+        const int nred = (int)p.red_param.size(), last = i == 0 ? SF_NO_STORE : 0;
+        launch_rows<S_REV>(*T, P->d_ops + P->op_off[i], (int)p.ops.size(), p.col, nred,
+                           ang + P->op_off[i], dph_of(*P, ang), lam[col], nullptr, partial,
+                           P->red_row0[i], last, s);
+        launch_rows<S_REV>(*T, P->d_ops + P->op_off[i], (int)p.ops.size(), p.col, nred,
+                           ang + P->op_off[i], dph_of(*P, ang), psi[col], nullptr, partial,
+                           P->red_row0[i] + nred, last | SF_NEGATE, s);
     }
     hipLaunchKernelGGL(k_sec_reduce, dim3(P->n_out), dim3(256), 0, s, partial, kGrid,
                        P->d_nblk, P->d_ptr, P->d_rows, P->d_scale, E_dev, grad_dev);
