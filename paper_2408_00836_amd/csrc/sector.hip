@@ -79,7 +79,8 @@ struct SecModel {
     double U;
     const uint32_t *pat[2];    // site pattern of each rank
     const double *base[2];     // sum_i eps_i p_i + sum_b V_b p_i p_j of each rank
-    const uint32_t *code;      // per gate and rank: pair slot | sign << 15, or kNone
+    const uint16_t *code;      // per gate and rank: pair slot | sign << 15, or kNone
+                               // (each gate's table padded to an even length)
     int32_t vi[kMaxBonds], vj[kMaxBonds];
     double vV[kMaxBonds];
 };
@@ -121,29 +122,44 @@ struct Codes {
 };
 
 typedef const __attribute__((address_space(1))) uint32_t gu32;
+typedef const __attribute__((address_space(1))) uint16_t gu16;
 typedef const __attribute__((address_space(1))) double gf64;
 typedef __attribute__((address_space(1))) double2 gc128;
 
+// The gate's codes of a thread's elements, from the LDS copy of its table
+// (elements past the row end: inactive).
 template <int TT, int RPT>
-__device__ __forceinline__ Codes<RPT> load_codes(const gu32 *__restrict__ ct, uint32_t tid,
-                                                 uint32_t n)
+__device__ __forceinline__ Codes<RPT> load_codes(const uint16_t *cb, uint32_t tid, uint32_t n)
 {
-    // elements past the row end read the last entry and are marked inactive
-    // (selects, no branches)
     Codes<RPT> c;
 #pragma unroll
     for (int j = 0; j < RPT; j += 2) {
         const uint32_t i0 = tid + j * TT, i1 = i0 + TT;
-        const uint32_t v0 = ct[min(i0, n - 1)];
-        const uint32_t lo = i0 < n ? v0 : kNone;
+        const uint32_t lo = i0 < n ? (uint32_t)cb[i0] : kNone;
         uint32_t hi = kNone;
-        if (j + 1 < RPT) {
-            const uint32_t v1 = ct[min(i1, n - 1)];
-            hi = i1 < n ? v1 : kNone;
-        }
+        if (j + 1 < RPT)
+            hi = i1 < n ? (uint32_t)cb[i1] : kNone;
         c.w[j >> 1] = lo | (hi << 16);
     }
     return c;
+}
+
+// Asynchronous copy of a gate's code table (n 16-bit entries, padded to an
+// even count) from global memory into LDS, a dword per lane, without
+// registers; complete for the issuing wave after its vmcnt wait.
+template <int TT>
+__device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16_t *cb,
+                                            uint32_t n, int tid)
+{
+    const uint32_t ndw = (n + 1) >> 1;
+    const uint32_t wbase = (uint32_t)(tid & ~63);
+    for (uint32_t d0 = 0; d0 < ndw; d0 += TT) {
+        const uint32_t d = d0 + (uint32_t)tid;
+        if (d < ndw)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void *)(src + 2 * d),
+                (__attribute__((address_space(3))) void *)(cb + 2 * (d0 + wbase)), 4, 0, 0);
+    }
 }
 
 // One gate's exchange of vector x through the pair slots: every active
@@ -151,9 +167,9 @@ __device__ __forceinline__ Codes<RPT> load_codes(const gu32 *__restrict__ ct, ui
 // w) with w = the Jordan-Wigner sign (+-1) if it is active and 0 if not (its
 // "partner" is then slot 0, any finite value): the updates are branch-free,
 // so the register tile is updated in place.
-template <int RPT, typename F>
+template <int RPT, typename G, typename F>
 __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
-                                         double2 *xch, F &&use)
+                                         double2 *xch, G &&mid, F &&use)
 {
     // decoded afresh in every exchange (not shared with an earlier one)
 #pragma unroll
@@ -170,6 +186,7 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
     for (int k = 0; k < (RPT + 1) / 2; ++k)
         asm volatile("" : "+v"(cd.w[k]));
     __syncthreads();
+    mid();
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const uint32_t c = cd.get(j);
@@ -180,6 +197,7 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
         // LDS latency): the register tile keeps its registers
         __builtin_amdgcn_sched_barrier(0);
     }
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's part of mid()'s copies has landed
     __syncthreads();
 }
 
@@ -213,7 +231,8 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     extern __shared__ __align__(16) char smem[];
     double2 *xch = (double2 *)smem;                            // pair slots
     double *acc = (double *)(smem + (size_t)xch_elems * 16);   // kMaxRed x kWaves
-    double2 *cis = (double2 *)(acc + kMaxRed * kWv);           // unit phases
+    double2 *cis = (double2 *)(acc + kMaxRed * kWaves);        // unit phases
+    uint16_t *cbuf = (uint16_t *)(cis + (1u << kCisBits));     // the next gate's codes
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t n = (uint32_t)M->n[col];
     const int nr = M->n[1 - col];
@@ -221,13 +240,30 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     // the loads take a scalar base and a 32-bit offset
     const gu32 *__restrict__ cpat = (const gu32 *)M->pat[col];
     const gf64 *__restrict__ cbase = (const gf64 *)M->base[col];
-    const gu32 *__restrict__ gcode = (const gu32 *)M->code;
+    const gu16 *__restrict__ gcode = (const gu16 *)M->code;
     const gu32 *__restrict__ rpat = (const gu32 *)M->pat[1 - col];
     const gf64 *__restrict__ rbase = (const gf64 *)M->base[1 - col];
     for (int i = tid; i < kMaxRed * kWv; i += TT)
         acc[i] = 0.0;
     if constexpr (MODE != S_HAM && GEN)
         build_cis(cis, tid, TT);
+    // the next hopping op (in execution order, wrapping to the first for the
+    // next row) after position oi; -1: none
+    auto next_hop = [&](int oi) -> int {
+        for (int k = 1; k <= n_ops; ++k) {
+            const int o2 = (oi + k) % n_ops;
+            const int io2 = REV ? n_ops - 1 - o2 : o2;
+            if (ops[io2].kind == SOP_HOP)
+                return io2;
+        }
+        return -1;
+    };
+    // cbuf holds the code table of op `ready` (-1: none); the first one now
+    int ready = next_hop(n_ops - 1);
+    if (ready >= 0) {
+        fetch_codes<TT>(gcode + ops[ready].tab, cbuf, n, tid);
+        __builtin_amdgcn_s_waitcnt(0);
+    }
     __syncthreads();
     double eacc = 0.0;
 
@@ -298,9 +334,22 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     sn = REV ? -cssn.y : cssn.y;    // un-apply: sin -> -sin
                 }
                 const double mt = -op.t;
-                const Codes<RPT> cd = load_codes<TT, RPT>(gcode + op.tab, t, n);
+                if (ready != io) {   // not prefetched (cannot happen with the schedule above)
+                    fetch_codes<TT>(gcode + op.tab, cbuf, n, tid);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                }
+                const Codes<RPT> cd = load_codes<TT, RPT>(cbuf, t, n);
+                // the next hop's codes arrive in cbuf while this one is applied
+                // (issued after the exchange's first barrier: by then every
+                // thread has read this op's codes)
+                ready = (r + (int)gridDim.x < nr || oi + 1 < n_ops) ? next_hop(oi) : -1;
+                const int nxt = ready;
                 // w = sign (active) or 0 (inactive: cos factor 1, no partner term)
-                exchange<RPT>(a, cd, xch, [&](int j, double2 p, double w) {
+                exchange<RPT>(a, cd, xch, [&]() {
+                    if (nxt >= 0)
+                        fetch_codes<TT>(gcode + ops[nxt].tab, cbuf, n, tid);
+                }, [&](int j, double2 p, double w) {
                     if constexpr (MODE == S_HAM) {   // phi += (-t) s psi_x'
                         b[j].x += mt * w * p.x;
                         b[j].y += mt * w * p.y;
@@ -488,7 +537,7 @@ struct Tables {
     SecModel *d_model = nullptr;
     uint32_t *d_pat[2] = {nullptr, nullptr};
     double *d_base[2] = {nullptr, nullptr};
-    uint32_t *d_code = nullptr;
+    uint16_t *d_code = nullptr;
     ~Tables()
     {
         (void)hipFree(d_model);
@@ -548,7 +597,10 @@ int popc(uint32_t x) { return __builtin_popcount(x); }
 // LDS of a row workgroup: the pair slots, the reduction slots, the unit phases.
 size_t lds_bytes(const Tables &T)
 {
-    return (size_t)T.xch * 16 + kMaxRed * kWaves * 8 + (1u << kCisBits) * 16;   // kWaves: the widest
+    // kWaves: the widest workgroup; the code buffer: the longest row, padded
+    const int nmax = std::max(T.n[0], T.n[1]);
+    return (size_t)T.xch * 16 + kMaxRed * kWaves * 8 + (1u << kCisBits) * 16 +
+           (size_t)(nmax + 1) / 2 * 4;
 }
 
 hubbard_status build_tables(const Model &m, Tables &T)
@@ -585,7 +637,7 @@ hubbard_status build_tables(const Model &m, Tables &T)
     T.b0_pos = (size_t)rank_of[1][dn0] * T.n[0] + rank_of[0][up0];
     // per bond and spin: pair slots (pair p at slots 2p, 2p+1) and the
     // Jordan-Wigner sign of the sites strictly between the bond's ends
-    std::vector<uint32_t> codes;
+    std::vector<uint16_t> codes;
     T.xch = 2;
     for (int s = 0; s < 2; ++s) {
         T.tab[s].assign(m.nb, 0);
@@ -595,7 +647,7 @@ hubbard_status build_tables(const Model &m, Tables &T)
             const uint32_t between = ((1u << j) - 1u) & ~((2u << i) - 1u);
             T.tab[s][k] = (int)codes.size();
             const size_t at = codes.size();
-            codes.resize(at + T.n[s], kNone);
+            codes.resize(at + T.n[s] + (T.n[s] & 1), (uint16_t)kNone);
             uint32_t pairs = 0;
             for (int r = 0; r < T.n[s]; ++r) {
                 const uint32_t p = pat[s][r];
@@ -603,8 +655,8 @@ hubbard_status build_tables(const Model &m, Tables &T)
                     const int r2 = rank_of[s][p ^ mask];
                     if (r2 > r) {
                         const uint32_t sg = (uint32_t)(popc(p & between) & 1) << 15;
-                        codes[at + r] = (2 * pairs) | sg;
-                        codes[at + r2] = (2 * pairs + 1) | sg;
+                        codes[at + r] = (uint16_t)((2 * pairs) | sg);
+                        codes[at + r2] = (uint16_t)((2 * pairs + 1) | sg);
                         ++pairs;
                     }
                 }
@@ -638,7 +690,7 @@ hubbard_status build_tables(const Model &m, Tables &T)
         sm.base[s] = T.d_base[s];
     }
     if (e == hipSuccess)
-        e = upload((void **)&T.d_code, codes.data(), codes.size() * 4);
+        e = upload((void **)&T.d_code, codes.data(), codes.size() * 2);
     sm.code = T.d_code;
     if (e == hipSuccess)
         e = upload((void **)&T.d_model, &sm, sizeof(sm));
