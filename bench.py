@@ -29,12 +29,13 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """sha256 over the HIP sources, plan and headers the pass kernels come from."""
+    """sha256 over the HIP sources, plan and headers the full-vector pass
+    kernels come from (every source but the sector form's own file)."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2408_00836_amd", "csrc")
     for name in sorted(os.listdir(src)):
-        if name.endswith((".hip", ".cpp", ".hpp")):
+        if name.endswith((".hip", ".cpp", ".hpp")) and name != "sector.hip":
             with open(os.path.join(src, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
@@ -361,10 +362,11 @@ def main():
             continue
         avg = tot / cnt
         # kernel template: <mode, general diagonal, full tiles, tiles per
-        # iteration, from the start state> (the first forward pass of a step
-        # is the one launch of the <..., true> variant)
+        # iteration, from the start state, op kinds> (the first forward pass
+        # of a step is the one launch of the <..., true, 0> variant; op kinds
+        # 0: hopping terms and diagonal sub-terms, the HVA circuit)
         nt = 2 if (mode == "forward" and not w.general) else 1
-        kernels[mode] = {"kernel": f"hv::k_pass<{abi.KERNEL_MODES[mode]}, {gen}, true, {nt}, false>",
+        kernels[mode] = {"kernel": f"hv::k_pass<{abi.KERNEL_MODES[mode]}, {gen}, true, {nt}, false, 0>",
                          "avg_ms": avg, "launches_per_step": cnt // args.steps,
                          "bytes_per_launch": nvec * vec,
                          "GBs": nvec * vec / (avg * 1e-3) / 1e9}

@@ -34,6 +34,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/hubbard.h"
@@ -55,6 +56,23 @@ constexpr int kMaxRed = 16;               // reduction slots of one row pass
 constexpr int kGrid = 1024;               // at most this many row workgroups
 constexpr uint32_t kNone = 0xFFFFu;       // code of an element a gate leaves alone
 constexpr int kMaxRows = 13 * kT;         // longest row: C(16, 8) = 12870
+constexpr int kTrash = 64;                // LDS slots (one per lane) that inactive elements write
+
+// Register tile of a row of n elements over kT threads: rpt_of(n) elements
+// per thread (element t + j kT in thread t).  A gate's code table holds
+// rp_of(rpt) >= rpt codes per thread in chunks of cw_of(rpt) consecutive
+// codes: element j of thread t is entry code_index(rpt, t, j), so that a
+// thread reads a chunk with one LDS load and a wave's loads are contiguous.
+__host__ __device__ constexpr int rpt_of(int n)
+{
+    return n <= kT ? 1 : n <= 2 * kT ? 2 : n <= 4 * kT ? 4 : n <= 8 * kT ? 8 : 13;
+}
+__host__ __device__ constexpr int rp_of(int rpt) { return rpt == 13 ? 16 : (rpt < 2 ? 2 : rpt); }
+__host__ __device__ constexpr int cw_of(int rpt) { return rp_of(rpt) < 8 ? rp_of(rpt) : 8; }
+__host__ __device__ constexpr int code_index(int rpt, int t, int j)
+{
+    return ((j / cw_of(rpt)) * kT + t) * cw_of(rpt) + j % cw_of(rpt);
+}
 
 enum { S_FWD = 0, S_REV = 1, S_HAM = 2 };
 enum { SOP_HOP = 0, SOP_DIAG = 1 };
@@ -65,11 +83,13 @@ enum { SF_NO_STORE = 1, SF_NEGATE = 2 };
 // layer's diagonal exp(-i th D).
 struct SecOp {
     int32_t kind;
-    int32_t param;   // theta index
-    int32_t tab;     // HOP: offset of its code table (entries of the row's columns)
-    int32_t red;     // REV: reduction slot of the parameter within the pass
-    double t;        // HOP: t_b
-    double pad;
+    int32_t param;    // theta index
+    int32_t tab;      // HOP: offset of its code table (kT rp_of(rpt) entries)
+    int32_t red;      // REV: reduction slot of the parameter within the pass
+    double t;         // HOP: t_b
+    int32_t nxt[2];   // the HOP op that follows this one in the pass's list in
+                      // forward [0] and reverse [1] execution order, wrapping
+                      // around (its code table is fetched while this op runs)
 };
 
 // Device constants of a model's sector.
@@ -106,6 +126,19 @@ __device__ __forceinline__ double diag_d(const SecModel *M, uint32_t rp, double 
 __device__ __forceinline__ void pin(double2 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 
+// x <- x m + q, and acc <- acc + m q, computed in the registers of x (acc):
+// the register tile is updated in place.  (Left to itself the allocator
+// writes an op's results to fresh registers and copies the whole tile back
+// at the end of the op: twice the tile's registers and a copy per element.)
+__device__ __forceinline__ void fma_ip(double &x, double m, double q)
+{
+    asm("v_fma_f64 %0, %0, %1, %2" : "+v"(x) : "v"(m), "v"(q));
+}
+__device__ __forceinline__ void fmac_ip(double &acc, double m, double q)
+{
+    asm("v_fma_f64 %0, %1, %2, %0" : "+v"(acc) : "v"(m), "v"(q));
+}
+
 __device__ __forceinline__ double wave_sum(double x)
 {
     for (int off = 32; off > 0; off >>= 1)
@@ -113,11 +146,11 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-// Two 16-bit gate codes per register (pair slot | sign << 15; 0xFFFF: the
-// element is left alone).
+// A thread's gate codes, two 16-bit codes per register (pair slot |
+// sign << 15; kNone: the element is left alone).
 template <int RPT>
 struct Codes {
-    uint32_t w[(RPT + 1) / 2];
+    uint32_t w[rp_of(RPT) / 2];
     __device__ __forceinline__ uint32_t get(int j) const { return (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu; }
 };
 
@@ -126,84 +159,99 @@ typedef const __attribute__((address_space(1))) uint16_t gu16;
 typedef const __attribute__((address_space(1))) double gf64;
 typedef __attribute__((address_space(1))) double2 gc128;
 
-// The gate's codes of a thread's elements, from the LDS copy of its table
-// (elements past the row end: inactive).
-template <int TT, int RPT>
-__device__ __forceinline__ Codes<RPT> load_codes(const uint16_t *cb, uint32_t tid, uint32_t n)
+// The gate's codes of thread t, from the LDS copy of its table: one load
+// per chunk (codes past the row end are kNone in the table).
+template <int RPT>
+__device__ __forceinline__ Codes<RPT> load_codes(const uint16_t *cb, uint32_t t)
 {
+    constexpr int CW = cw_of(RPT), NCH = rp_of(RPT) / CW;
     Codes<RPT> c;
 #pragma unroll
-    for (int j = 0; j < RPT; j += 2) {
-        const uint32_t i0 = tid + j * TT, i1 = i0 + TT;
-        const uint32_t lo = i0 < n ? (uint32_t)cb[i0] : kNone;
-        uint32_t hi = kNone;
-        if (j + 1 < RPT)
-            hi = i1 < n ? (uint32_t)cb[i1] : kNone;
-        c.w[j >> 1] = lo | (hi << 16);
+    for (int ch = 0; ch < NCH; ++ch) {
+        const uint16_t *q = cb + ((size_t)ch * kT + t) * CW;
+        if constexpr (CW == 8) {
+            const uint4 v = *(const uint4 *)q;
+            c.w[ch * 4 + 0] = v.x;
+            c.w[ch * 4 + 1] = v.y;
+            c.w[ch * 4 + 2] = v.z;
+            c.w[ch * 4 + 3] = v.w;
+        } else if constexpr (CW == 4) {
+            const uint2 v = *(const uint2 *)q;
+            c.w[ch * 2 + 0] = v.x;
+            c.w[ch * 2 + 1] = v.y;
+        } else {
+            c.w[ch] = *(const uint32_t *)q;
+        }
     }
     return c;
 }
 
-// Asynchronous copy of a gate's code table (n 16-bit entries, padded to an
-// even count) from global memory into LDS, a dword per lane, without
+// Asynchronous copy of a gate's code table (kT rp_of(RPT) 16-bit entries)
+// from global memory into LDS, a dword per lane and round, without
 // registers; complete for the issuing wave after its vmcnt wait.
-template <int TT>
-__device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16_t *cb,
-                                            uint32_t n, int tid)
+template <int TT, int RPT>
+__device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16_t *cb, int tid)
 {
-    const uint32_t ndw = (n + 1) >> 1;
+    constexpr int ROUNDS = kT * rp_of(RPT) / 2 / TT;
     const uint32_t wbase = (uint32_t)(tid & ~63);
-    for (uint32_t d0 = 0; d0 < ndw; d0 += TT) {
-        const uint32_t d = d0 + (uint32_t)tid;
-        if (d < ndw)
-            __builtin_amdgcn_global_load_lds(
-                (const __attribute__((address_space(1))) void *)(src + 2 * d),
-                (__attribute__((address_space(3))) void *)(cb + 2 * (d0 + wbase)), 4, 0, 0);
+#pragma unroll
+    for (int k = 0; k < ROUNDS; ++k) {
+        const uint32_t d0 = (uint32_t)k * TT;
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(src + 2 * (d0 + (uint32_t)tid)),
+            (__attribute__((address_space(3))) void *)(cb + 2 * (d0 + wbase)), 4, 0, 0);
     }
 }
 
 // One gate's exchange of vector x through the pair slots: every active
-// element publishes its value, then every element calls use(j, partner,
-// w) with w = the Jordan-Wigner sign (+-1) if it is active and 0 if not (its
-// "partner" is then slot 0, any finite value): the updates are branch-free,
-// so the register tile is updated in place.
-template <int RPT, typename G, typename F>
-__device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
-                                         double2 *xch, G &&mid, F &&use)
+// element publishes its value to its slot (an inactive one to its lane's
+// trash slot), then every element calls use(j, partner, w) with w = the
+// Jordan-Wigner sign (+-1) if it is active and 0 if not (its "partner" is
+// then its trash slot, a finite value): the whole exchange is branch-free.
+// code(j): element j's code; fresh() runs before each half (HOLD: it makes
+// the code registers opaque, so that the decoded slot addresses are not
+// kept across the barrier).  HOLD: the codes are in registers and mid()
+// (the next gate's table fetch) is issued right after the publishing
+// barrier; else code(j) reads the LDS table, which mid() overwrites: it is
+// issued after a barrier that follows every wave's last read.
+template <int N, bool HOLD, typename C, typename R, typename G, typename F>
+__device__ __forceinline__ void exchange(const double2 (&x)[N], C &&code, R &&fresh,
+                                         double2 *xch, uint32_t trash, G &&mid, F &&use)
 {
-    // decoded afresh in every exchange (not shared with an earlier one)
+    fresh();
 #pragma unroll
-    for (int k = 0; k < (RPT + 1) / 2; ++k)
-        asm volatile("" : "+v"(cd.w[k]));
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const uint32_t c = cd.get(j);
-        if (c != kNone)
-            xch[c & 0x7FFFu] = x[j];
+    for (int j = 0; j < N; ++j) {
+        const uint32_t c = code(j);
+        xch[c != kNone ? (c & 0x7FFFu) : trash] = x[j];
     }
-    // the slot addresses are decoded again below rather than kept
-#pragma unroll
-    for (int k = 0; k < (RPT + 1) / 2; ++k)
-        asm volatile("" : "+v"(cd.w[k]));
     __syncthreads();
-    mid();
+    if constexpr (HOLD)
+        mid();
+    fresh();
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const uint32_t c = cd.get(j);
+    for (int j = 0; j < N; ++j) {
+        const uint32_t c = code(j);
         const bool act = c != kNone;
-        const double2 p = xch[act ? ((c & 0x7FFFu) ^ 1u) : 0u];
+        const double2 p = xch[act ? ((c & 0x7FFFu) ^ 1u) : trash];
         use(j, p, act ? ((c >> 15) ? -1.0 : 1.0) : 0.0);
         // one partner value in flight per thread (the other waves hide the
         // LDS latency): the register tile keeps its registers
         __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (!HOLD) {
+        __syncthreads();
+        mid();
     }
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of mid()'s copies has landed
     __syncthreads();
 }
 
 // Row pass.  Each workgroup takes rows blockIdx.x, blockIdx.x + gridDim.x, ...
-// of the layout whose columns are indexed by spin `col`; thread t holds the
-// row's elements t + j TT, j < RPT.
+// of the layout whose columns are indexed by spin `col`.  The row's register
+// tile is that of kT threads holding RPT elements each (element u + j kT in
+// tile thread u, j < RPT); a workgroup of TT = kT / VT threads plays VT tile
+// threads per thread (thread t: tile threads t + v TT, v < VT), so that a
+// two-vector tile can have twice the registers per thread.
 //   S_FWD: v0 <- ops applied in order.
 //   S_REV: v0 = chi <- ops un-applied in reverse order; the expectation
 //          <chi| G |chi> of every op before its un-application goes to its
@@ -226,14 +274,25 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
            const SecModel *__restrict__ M, double2 *__restrict__ v0, double2 *__restrict__ v1,
            double *__restrict__ partial, int row0, int pstride, int flags, int xch_elems)
 {
+    static_assert(kT % TT == 0, "a thread plays a whole number of tile threads");
+    constexpr int VT = kT / TT;    // tile threads per thread
+    constexpr int N = VT * RPT;    // elements per thread
     constexpr int kWv = TT / 64;   // waves of the workgroup
     constexpr bool REV = MODE == S_REV;
+    // FWD and REV hold a gate's codes in registers; H, whose register tile
+    // holds two vectors, reads them from LDS where it uses them
+    constexpr bool HOLD = MODE != S_HAM;
+    // column of a thread's element e (tile thread u + v TT, register j)
+    auto elem = [](uint32_t u, int e) -> uint32_t {
+        return u + (uint32_t)((e / RPT) * TT + (e % RPT) * kT);
+    };
     extern __shared__ __align__(16) char smem[];
-    double2 *xch = (double2 *)smem;                            // pair slots
-    double *acc = (double *)(smem + (size_t)xch_elems * 16);   // kMaxRed x kWaves
-    double2 *cis = (double2 *)(acc + kMaxRed * kWaves);        // unit phases
-    uint16_t *cbuf = (uint16_t *)(cis + (1u << kCisBits));     // the next gate's codes
+    double2 *xch = (double2 *)smem;   // pair slots, then kTrash trash slots
+    double *acc = (double *)(smem + (size_t)(xch_elems + kTrash) * 16);   // kMaxRed x kWaves
+    double2 *cis = (double2 *)(acc + kMaxRed * kWaves);                   // unit phases
+    uint16_t *cbuf = (uint16_t *)(cis + (1u << kCisBits));                // the next gate's codes
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t trash = (uint32_t)(xch_elems + lane);
     const uint32_t n = (uint32_t)M->n[col];
     const int nr = M->n[1 - col];
     // the tables' pointers come from memory: global address space, so that
@@ -247,21 +306,21 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
         acc[i] = 0.0;
     if constexpr (MODE != S_HAM && GEN)
         build_cis(cis, tid, TT);
-    // the next hopping op (in execution order, wrapping to the first for the
-    // next row) after position oi; -1: none
-    auto next_hop = [&](int oi) -> int {
-        for (int k = 1; k <= n_ops; ++k) {
-            const int o2 = (oi + k) % n_ops;
-            const int io2 = REV ? n_ops - 1 - o2 : o2;
-            if (ops[io2].kind == SOP_HOP)
-                return io2;
-        }
-        return -1;
-    };
-    // cbuf holds the code table of op `ready` (-1: none); the first one now
-    int ready = next_hop(n_ops - 1);
+    // execution position of the pass's diagonal op (at most one; n_ops: none)
+    int dexec = n_ops;
+    for (int io = 0; io < n_ops; ++io)
+        if (ops[io].kind == SOP_DIAG)
+            dexec = REV ? n_ops - 1 - io : io;
+    // cbuf holds the code table of op `ready` (-1: none); the first hopping
+    // op in execution order now
+    int ready = -1;
+    for (int oi = 0; oi < n_ops && ready < 0; ++oi) {
+        const int io = REV ? n_ops - 1 - oi : oi;
+        if (ops[io].kind == SOP_HOP)
+            ready = io;
+    }
     if (ready >= 0) {
-        fetch_codes<TT>(gcode + ops[ready].tab, cbuf, n, tid);
+        fetch_codes<TT, RPT>(gcode + ops[ready].tab, cbuf, tid);
         __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
@@ -276,15 +335,17 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
         gc128 *__restrict__ x1 = (gc128 *)(v1 + (size_t)r * (size_t)n);
         // elements past the row end (the last register of some threads) hold
         // zero: every op leaves them zero and they add nothing to a sum
-        double2 a[RPT], b[RPT];
+        double2 a[N], b[N];
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const uint32_t idx = tr + j * TT, ic = min(idx, n - 1);
+        for (int j = 0; j < N; ++j) {
+            const uint32_t idx = elem(tr, j), ic = min(idx, n - 1);
             a[j] = make_double2(x0[ic].x, x0[ic].y);
             a[j] = idx < n ? a[j] : make_double2(0.0, 0.0);
             b[j] = make_double2(0.0, 0.0);
         }
-        for (int oi = 0; oi < n_ops; ++oi) {
+        // op at execution position oi; IS_DIAG: the diagonal op, else a hop
+        auto step = [&](int oi, auto diag_tag) __attribute__((always_inline)) {
+            constexpr bool IS_DIAG = decltype(diag_tag)::value;
             const int io = REV ? n_ops - 1 - oi : oi;
             const SecOp op = ops[io];
             double racc = 0.0;
@@ -292,21 +353,21 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
             // their 64-bit table addresses) across the op loop
             uint32_t t = (uint32_t)tid;
             asm volatile("" : "+v"(t));
-            if (op.kind == SOP_DIAG) {
+            if constexpr (IS_DIAG) {
                 double th = 0.0;
                 if constexpr (MODE != S_HAM)
                     th = ang[io].x;
 #pragma unroll
-                for (int j = 0; j < RPT; ++j) {
-                    const uint32_t ic = min(t + j * TT, n - 1);   // past the end: a zero element
+                for (int j = 0; j < N; ++j) {
+                    const uint32_t ic = min(elem(t, j), n - 1);   // past the end: a zero element
                     {
                         const uint32_t cp = cpat[ic];
                         const uint32_t k = __popc(rp & cp);
                         const double d = GEN ? diag_d(M, rp, rb, cp, cbase[ic])
                                              : M->U * (double)k;
                         if constexpr (MODE == S_HAM) {
-                            b[j].x += d * a[j].x;
-                            b[j].y += d * a[j].y;
+                            fmac_ip(b[j].x, d, a[j].x);
+                            fmac_ip(b[j].y, d, a[j].y);
                         } else {
                             // exp(-i th D) forward, exp(+i th D) to un-apply
                             double2 e;
@@ -317,10 +378,12 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                                 if constexpr (REV)
                                     e.y = -e.y;
                             }
-                            const double2 p = a[j];
                             if constexpr (REV)   // <chi|D|chi> term
-                                racc += d * (p.x * p.x + p.y * p.y);
-                            a[j] = make_double2(e.x * p.x - e.y * p.y, e.x * p.y + e.y * p.x);
+                                racc += d * (a[j].x * a[j].x + a[j].y * a[j].y);
+                            // a <- e a
+                            const double tx = e.y * a[j].y, ty = e.y * a[j].x;
+                            fma_ip(a[j].x, e.x, -tx);
+                            fma_ip(a[j].y, e.x, ty);
                         }
                     }
                     // one element's phase at a time: fewer live temporaries
@@ -334,25 +397,44 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     sn = REV ? -cssn.y : cssn.y;    // un-apply: sin -> -sin
                 }
                 const double mt = -op.t;
-                if (ready != io) {   // not prefetched (cannot happen with the schedule above)
-                    fetch_codes<TT>(gcode + op.tab, cbuf, n, tid);
+                if (ready != io) {   // not prefetched (the op list's nxt links are broken)
+                    fetch_codes<TT, RPT>(gcode + op.tab, cbuf, tid);
                     __builtin_amdgcn_s_waitcnt(0);
                     __syncthreads();
                 }
-                const Codes<RPT> cd = load_codes<TT, RPT>(cbuf, t, n);
+                Codes<RPT> cd[VT];
+                if constexpr (HOLD) {
+#pragma unroll
+                    for (int v = 0; v < VT; ++v)
+                        cd[v] = load_codes<RPT>(cbuf, t + (uint32_t)(v * TT));
+                }
                 // the next hop's codes arrive in cbuf while this one is applied
-                // (issued after the exchange's first barrier: by then every
-                // thread has read this op's codes)
-                ready = (r + (int)gridDim.x < nr || oi + 1 < n_ops) ? next_hop(oi) : -1;
+                // (HOLD: issued after the exchange's first barrier, by when every
+                // thread has its codes in registers; else after the last read)
+                ready = (r + (int)gridDim.x < nr || oi + 1 < n_ops) ? op.nxt[REV ? 1 : 0] : -1;
                 const int nxt = ready;
                 // w = sign (active) or 0 (inactive: cos factor 1, no partner term)
-                exchange<RPT>(a, cd, xch, [&]() {
+                exchange<N, HOLD>(a, [&](int e) -> uint32_t {
+                    if constexpr (HOLD)
+                        return cd[e / RPT].get(e % RPT);
+                    else
+                        return cbuf[code_index(RPT, (int)t + (e / RPT) * TT, e % RPT)];
+                }, [&]() {
+                    if constexpr (HOLD) {
+#pragma unroll
+                        for (int v = 0; v < VT; ++v)
+#pragma unroll
+                            for (int k = 0; k < rp_of(RPT) / 2; ++k)
+                                asm volatile("" : "+v"(cd[v].w[k]));
+                    }
+                }, xch, trash, [&]() {
                     if (nxt >= 0)
-                        fetch_codes<TT>(gcode + ops[nxt].tab, cbuf, n, tid);
+                        fetch_codes<TT, RPT>(gcode + ops[nxt].tab, cbuf, tid);
                 }, [&](int j, double2 p, double w) {
                     if constexpr (MODE == S_HAM) {   // phi += (-t) s psi_x'
-                        b[j].x += mt * w * p.x;
-                        b[j].y += mt * w * p.y;
+                        const double m = mt * w;
+                        fmac_ip(b[j].x, m, p.x);
+                        fmac_ip(b[j].y, m, p.y);
                         pin(b[j]);
                     } else {
                         const double2 y = a[j];
@@ -362,7 +444,8 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                         }
                         const double ss = w * sn;      // x <- cs x + i s sn x'
                         const double c = w != 0.0 ? cs : 1.0;
-                        a[j] = make_double2(c * y.x - ss * p.y, c * y.y + ss * p.x);
+                        fma_ip(a[j].x, c, -ss * p.y);
+                        fma_ip(a[j].y, c, ss * p.x);
                         pin(a[j]);
                     }
                 });
@@ -372,10 +455,20 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                 if (lane == 0)
                     acc[op.red * kWv + wave] += w;
             }
-        }
+        };
+        // the hops before the diagonal, the diagonal, the hops after it: each
+        // loop body is a single path, so the register tile keeps its
+        // registers across ops (a loop over both kinds merges two versions
+        // of the tile at the end of every op, and copies it)
+        for (int oi = 0; oi < dexec; ++oi)
+            step(oi, std::false_type());
+        if (dexec < n_ops)
+            step(dexec, std::true_type());
+        for (int oi = dexec + 1; oi < n_ops; ++oi)
+            step(oi, std::false_type());
         if constexpr (MODE == S_HAM) {
 #pragma unroll
-            for (int j = 0; j < RPT; ++j)
+            for (int j = 0; j < N; ++j)
                 eacc += a[j].x * b[j].x + a[j].y * b[j].y;
         }
         if (!(flags & SF_NO_STORE)) {
@@ -383,8 +476,8 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
             uint32_t t = (uint32_t)tid;
             asm volatile("" : "+v"(t));
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                const uint32_t idx = t + j * TT;
+            for (int j = 0; j < N; ++j) {
+                const uint32_t idx = elem(t, j);
                 if (idx < n) {
                     if constexpr (MODE != S_HAM) {
                         x0[idx].x = a[j].x;
@@ -594,13 +687,13 @@ hipError_t upload(void **dst, const void *src, size_t bytes)
 
 int popc(uint32_t x) { return __builtin_popcount(x); }
 
-// LDS of a row workgroup: the pair slots, the reduction slots, the unit phases.
+// LDS of a row workgroup: the pair and trash slots, the reduction slots, the
+// unit phases, one gate's code table (of the longer row).
 size_t lds_bytes(const Tables &T)
 {
-    // kWaves: the widest workgroup; the code buffer: the longest row, padded
-    const int nmax = std::max(T.n[0], T.n[1]);
-    return (size_t)T.xch * 16 + kMaxRed * kWaves * 8 + (1u << kCisBits) * 16 +
-           (size_t)(nmax + 1) / 2 * 4;
+    const int rp = std::max(rp_of(rpt_of(T.n[0])), rp_of(rpt_of(T.n[1])));
+    return (size_t)(T.xch + kTrash) * 16 + kMaxRed * kWaves * 8 + (1u << kCisBits) * 16 +
+           (size_t)kT * rp * 2;
 }
 
 hubbard_status build_tables(const Model &m, Tables &T)
@@ -636,18 +729,21 @@ hubbard_status build_tables(const Model &m, Tables &T)
     const uint32_t up0 = (uint32_t)m.neel & smask, dn0 = (uint32_t)(m.neel >> ns) & smask;
     T.b0_pos = (size_t)rank_of[1][dn0] * T.n[0] + rank_of[0][up0];
     // per bond and spin: pair slots (pair p at slots 2p, 2p+1) and the
-    // Jordan-Wigner sign of the sites strictly between the bond's ends
+    // Jordan-Wigner sign of the sites strictly between the bond's ends, at
+    // the rank's entry of the register-tile layout (kNone elsewhere)
     std::vector<uint16_t> codes;
     T.xch = 2;
     for (int s = 0; s < 2; ++s) {
         T.tab[s].assign(m.nb, 0);
+        const int R = rpt_of(T.n[s]);
+        auto entry = [&](int r) { return (size_t)code_index(R, r % kT, r / kT); };
         for (int k = 0; k < m.nb; ++k) {
             const int i = std::min(m.bi[k], m.bj[k]), j = std::max(m.bi[k], m.bj[k]);
             const uint32_t mask = (1u << i) | (1u << j);
             const uint32_t between = ((1u << j) - 1u) & ~((2u << i) - 1u);
             T.tab[s][k] = (int)codes.size();
             const size_t at = codes.size();
-            codes.resize(at + T.n[s] + (T.n[s] & 1), (uint16_t)kNone);
+            codes.resize(at + (size_t)kT * rp_of(R), (uint16_t)kNone);
             uint32_t pairs = 0;
             for (int r = 0; r < T.n[s]; ++r) {
                 const uint32_t p = pat[s][r];
@@ -655,8 +751,8 @@ hubbard_status build_tables(const Model &m, Tables &T)
                     const int r2 = rank_of[s][p ^ mask];
                     if (r2 > r) {
                         const uint32_t sg = (uint32_t)(popc(p & between) & 1) << 15;
-                        codes[at + r] = (uint16_t)((2 * pairs) | sg);
-                        codes[at + r2] = (uint16_t)((2 * pairs + 1) | sg);
+                        codes[at + entry(r)] = (uint16_t)((2 * pairs) | sg);
+                        codes[at + entry(r2)] = (uint16_t)((2 * pairs + 1) | sg);
                         ++pairs;
                     }
                 }
@@ -698,6 +794,22 @@ hubbard_status build_tables(const Model &m, Tables &T)
         return fail(HUBBARD_ERR_DEVICE, std::string("uploading sector tables: ") +
                                             hipGetErrorString(e));
     return HUBBARD_OK;
+}
+
+// Each op's nxt links: the next HOP op of the list in forward and in reverse
+// order, wrapping around (-1: the list has none).
+void link_hops(std::vector<SecOp> &v)
+{
+    const int n = (int)v.size();
+    for (int i = 0; i < n; ++i) {
+        v[i].nxt[0] = v[i].nxt[1] = -1;
+        for (int k = 1; k <= n && v[i].nxt[0] < 0; ++k)
+            if (v[(i + k) % n].kind == SOP_HOP)
+                v[i].nxt[0] = (i + k) % n;
+        for (int k = 1; k <= n && v[i].nxt[1] < 0; ++k)
+            if (v[(i - k + n) % n].kind == SOP_HOP)
+                v[i].nxt[1] = (i - k + n) % n;
+    }
 }
 
 void add_red(RowPass &p, SecOp &o)
@@ -753,9 +865,14 @@ hubbard_status build_program(const Model &m, const Tables &T, int layers, Progra
         }
         P.fwd.push_back(cur);
     }
-    for (const RowPass &p : P.fwd)
+    for (RowPass &p : P.fwd) {
         if ((int)p.red_param.size() > kMaxRed)
             return fail(HUBBARD_ERR_ARG, "sector row pass with more than 16 parameters");
+        if (std::count_if(p.ops.begin(), p.ops.end(),
+                          [](const SecOp &o) { return o.kind == SOP_DIAG; }) > 1)
+            return fail(HUBBARD_ERR_ARG, "sector row pass with two diagonal ops");
+        link_hops(p.ops);
+    }
     P.final_col = P.fwd.empty() ? 0 : P.fwd.back().col;
     P.n_diag = n_diag;
     // H: the final layout's spin hops and D, then the other spin's hops
@@ -786,6 +903,8 @@ hubbard_status build_program(const Model &m, const Tables &T, int layers, Progra
         return v;
     };
     std::vector<SecOp> hx = ham_ops(P.final_col, true), hy = ham_ops(1 - P.final_col, false);
+    link_hops(hx);
+    link_hops(hy);
     P.ham_x_off = (int)all.size();
     P.ham_x_n = (int)hx.size();
     all.insert(all.end(), hx.begin(), hx.end());
@@ -873,8 +992,10 @@ size_t vec_elems(const Tables &T) { return (size_t)T.n[0] * (size_t)T.n[1]; }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workgroup shape by row length: 1024 threads holding up to 13 elements of
-// each vector (two-vector passes of the longest rows spill part of their
-// tile to scratch memory; 256 threads holding 51 elements each spilled more).
+// each vector.  (At 13 elements, H -- two vectors -- and the general
+// diagonal's reverse pass keep part of their tile in scratch memory: 84 and
+// 104 bytes per thread; 512 threads playing two tile threads each spilled
+// more.)
 template <int MODE, bool GEN>
 void launch_rows_g(const Tables &T, const SecOp *ops, int n_ops, int col, int n_red,
                    const double2 *ang, const double2 *dph, double2 *v0, double2 *v1,
@@ -887,16 +1008,13 @@ void launch_rows_g(const Tables &T, const SecOp *ops, int n_ops, int col, int n_
     hipLaunchKernelGGL((k_sec_rows<MODE, TT, R, GEN>), dim3(grid), dim3(TT), lds, s, ops,       \
                        n_ops, col, n_red, ang, dph, T.d_model, v0, v1, partial, row0, kGrid,    \
                        flags, T.xch)
-    if (n <= kT)
-        HV_SEC(kT, 1);
-    else if (n <= 2 * kT)
-        HV_SEC(kT, 2);
-    else if (n <= 4 * kT)
-        HV_SEC(kT, 4);
-    else if (n <= 8 * kT)
-        HV_SEC(kT, 8);
-    else
-        HV_SEC(kT, 13);
+    switch (rpt_of(n)) {   // the register tile the code tables are laid out for
+    case 1: HV_SEC(kT, 1); break;
+    case 2: HV_SEC(kT, 2); break;
+    case 4: HV_SEC(kT, 4); break;
+    case 8: HV_SEC(kT, 8); break;
+    default: HV_SEC(kT, 13); break;
+    }
 #undef HV_SEC
 }
 

@@ -89,6 +89,46 @@ def test_sector_vs_oracle(gpu, key):
     assert float(np.max(np.abs(g.cpu().numpy() - g2.cpu().numpy()))) <= GRAD_TOL
 
 
+# Rows long enough for the wider register tiles (2, 4 and 8 elements per
+# thread of the 1024-thread row workgroup; the 32-qubit circuit below has 13):
+# checked against the sector oracle alone (pinned to the full-space oracle
+# in the CPU tests), since the full vectors of 26-30 qubits are beyond the
+# full-space oracle's test budget.
+TILE_CASES = {
+    "chain13 (2 per thread)": lambda: W.random_instance(1, 13, 2, 3, 4310, U=4.0, disorder=0.1,
+                                                        eps_width=0.2, V=0.3,
+                                                        name="1x13 chain eps V"),
+    "ladder2x7 (4 per thread)": lambda: W.random_instance(2, 7, 1, 5, 4311, U=6.0, disorder=0.1,
+                                                          name="2x7 ladder U=6"),
+    "lattice3x5 (8 per thread)": lambda: W.random_instance(3, 5, 1, 5, 4312, U=3.0,
+                                                           disorder=0.1, name="3x5 U=3"),
+}
+
+
+@pytest.mark.parametrize("key", list(TILE_CASES))
+def test_sector_register_tiles(gpu, key):
+    w = TILE_CASES[key]()
+    say(f"[sector tiles] {w.name}")
+    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    om = make_model(w.nx, w.ny, **w.kwargs())
+    th = torch.tensor(w.theta, dtype=torch.float64, device=gpu)
+    psi = m.sector_state(th)
+    ref = osec.ansatz(om, w.theta, w.layers)
+    amp = float(np.max(np.abs(psi.cpu().numpy() - ref)))
+    hx = m.sector_apply_h(psi)
+    href = osec.ham_apply(om, ref)
+    herr = float(np.max(np.abs(hx.cpu().numpy() - href)) / max(1.0, np.max(np.abs(href))))
+    E, g = m.sector_energy_grad(th)
+    E_ref, g_ref = osec.energy_grad(om, w.theta, w.layers)
+    dE = abs(E.item() - E_ref)
+    dg = float(np.max(np.abs(g.cpu().numpy() - g_ref)))
+    say(f"[sector tiles] {w.name}: amp {amp:.2e}, H {herr:.2e}, dE {dE:.2e}, dg {dg:.2e}")
+    assert amp <= AMP_TOL
+    assert herr <= AMP_TOL
+    assert dE <= e_tol(E_ref)
+    assert dg <= GRAD_TOL
+
+
 @pytest.mark.parametrize("layers", [0, 1, 2])
 def test_sector_short_circuits(gpu, layers):
     w = W.random_instance(2, 3, layers, 5, 4203 + layers, U=4.0, disorder=0.1, eps_width=0.2,
