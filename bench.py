@@ -155,6 +155,13 @@ def sector_bench(torch, dev, w, reps=3):
     ham = 2 * 2 + 2 + 3
     rev = (passes * 4 - 2) + L * 4
     alg = (fwd + ham + rev) * vec
+    # the reference ground state of the same model (sector Lanczos from the
+    # default start; one H application and a host synchronisation per step)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    lz = m.sector_lanczos(max_iter=600, tol=1e-9)
+    torch.cuda.synchronize()
+    t_lz = time.perf_counter() - a
     return {"workload": w.name + ", sector form", "sector_dims": [nu, nd],
             "amplitudes": dim, "bytes_per_vector": vec,
             "evals_per_s": 1.0 / t, "ms_per_eval": t * 1e3,
@@ -162,7 +169,9 @@ def sector_bench(torch, dev, w, reps=3):
             "algorithmic_bytes_per_eval": alg, "algorithmic_GBs": alg / t / 1e9,
             "frac_of_hbm_peak": alg / t / 1e9 / HBM_PEAK_GBS,
             "hpsi_ms": th_ * 1e3, "hpsi_algorithmic_GBs": 2 * vec / th_ / 1e9,
-            "hpsi_bytes_moved_GBs": (2 * 2 + 2 + 3) * vec / th_ / 1e9}
+            "hpsi_bytes_moved_GBs": (2 * 2 + 2 + 3) * vec / th_ / 1e9,
+            "lanczos": {"E0": lz["E0"], "E0_per_site": lz["E0"] / (w.nx * w.ny),
+                        "iters": lz["iters"], "ritz_residual": lz["residual"], "seconds": t_lz}}
 
 
 def copy_reference(torch, dev, gib=8, reps=3):

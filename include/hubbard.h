@@ -424,7 +424,8 @@ hubbard_status energy_grad_batch(const hubbard_t *hs, int32_t n, const double *t
 enum {
     HUBBARD_SECTOR_ANSATZ = 0,        /* sector_ansatz_apply: one sector vector */
     HUBBARD_SECTOR_ENERGY_GRAD = 1,   /* sector_energy_grad: four vectors + partial sums */
-    HUBBARD_SECTOR_HAMILTONIAN = 2    /* sector_hamiltonian_apply: two vectors */
+    HUBBARD_SECTOR_HAMILTONIAN = 2,   /* sector_hamiltonian_apply: two vectors */
+    HUBBARD_SECTOR_LANCZOS = 3        /* hubbard_sector_lanczos: five vectors + partial sums */
 };
 
 /* C(Ns, N_up) and C(Ns, N_dn) of the handle's start state (host outputs). */
@@ -458,6 +459,18 @@ hubbard_status sector_hamiltonian_apply(hubbard_t h, const void *psi_dev, void *
 hubbard_status sector_energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,
                                   double *E_dev, double *grad_dev, void *ws_dev, size_t ws_bytes,
                                   void *stream);
+
+/* hubbard_lanczos on sector vectors: the lowest eigenvalue of H (Eq.
+ * (1)/(2)/(15)/(16)) in the sector of the handle's start state, the
+ * reference ground state of Sec. 2.1/3.1/3.4, by the same Lanczos recurrence
+ * (same stopping rule, same arithmetic order) with sector_hamiltonian_apply
+ * as H.  start_dev and gs_dev (NULL or the unit Ritz vector) are sector
+ * vectors; ws_dev: HUBBARD_SECTOR_LANCZOS bytes (three Krylov vectors, H's
+ * two layout-B vectors, partial sums), overlapping neither.  Synchronises
+ * `stream` at every step. */
+hubbard_status hubbard_sector_lanczos(hubbard_t h, const void *start_dev, int32_t max_iter,
+                                      double tol, double *E0, int32_t *iters, double *residual,
+                                      void *gs_dev, void *ws_dev, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

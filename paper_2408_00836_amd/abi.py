@@ -32,6 +32,7 @@ HUBBARD_ANSATZ_NP = 1
 HUBBARD_SECTOR_ANSATZ = 0
 HUBBARD_SECTOR_ENERGY_GRAD = 1
 HUBBARD_SECTOR_HAMILTONIAN = 2
+HUBBARD_SECTOR_LANCZOS = 3
 
 # Every symbol the headers in include/ declare.
 EXPORTED = [
@@ -48,6 +49,7 @@ EXPORTED = [
     "hubbard_spin_correlation", "hubbard_set_ansatz", "hubbard_param_count",
     "hubbard_sector_dim", "hubbard_sector_workspace_size", "hubbard_sector_init_neel",
     "sector_ansatz_apply", "sector_hamiltonian_apply", "sector_energy_grad",
+    "hubbard_sector_lanczos",
 ]
 
 
@@ -164,6 +166,9 @@ def lib() -> ctypes.CDLL:
             "sector_ansatz_apply": ([vp, vp, i32, vp, vp, ctypes.c_size_t, vp], st),
             "sector_hamiltonian_apply": ([vp, vp, vp, vp, ctypes.c_size_t, vp], st),
             "sector_energy_grad": ([vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp], st),
+            "hubbard_sector_lanczos": ([vp, vp, i32, ctypes.c_double, P(ctypes.c_double),
+                                        P(i32), P(ctypes.c_double), vp, vp, ctypes.c_size_t,
+                                        vp], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -555,3 +560,14 @@ def sector_energy_grad(h: int, theta_dev: int, n_layers: int, E_dev: int, grad_d
                        ws_dev: int, ws_bytes: int, stream: int = 0) -> None:
     _check(lib().sector_energy_grad(h, theta_dev, int(n_layers), E_dev, grad_dev, ws_dev,
                                     int(ws_bytes), stream))
+
+
+def hubbard_sector_lanczos(h: int, start_dev: int, max_iter: int, tol: float, gs_dev,
+                           ws_dev: int, ws_bytes: int, stream: int = 0):
+    """(E0, iterations, Ritz residual) on sector vectors; the unit ground
+    state goes to gs_dev unless it is None."""
+    E0, it, res = ctypes.c_double(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib().hubbard_sector_lanczos(h, start_dev, int(max_iter), float(tol),
+                                        ctypes.byref(E0), ctypes.byref(it), ctypes.byref(res),
+                                        gs_dev, ws_dev, int(ws_bytes), stream))
+    return E0.value, it.value, res.value

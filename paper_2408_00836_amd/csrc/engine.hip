@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -42,6 +43,14 @@ __global__ void k_overlap_finish(const double2 *, double *, int, double *);
 __global__ void k_bit_moments(const double2 *, int, int, double *);
 __global__ void k_moments_final(const double *, int, int, int, double *);
 __global__ void k_spin_corr(const double *, int, double *, double *);
+
+// H applied to a device vector (in -> out) on the caller's stream.
+using ApplyH = std::function<hubbard_status(const double2 *, double2 *)>;
+hubbard_status lanczos_run(const ApplyH &apply, uint64_t n, const double2 *start_dev,
+                           int32_t max_iter, double tol, double *E0, int32_t *iters,
+                           double *residual, double2 *gs_dev, double2 *const buf[3],
+                           double2 *partial, hipStream_t s);
+size_t lanczos_partial_bytes();
 }  // namespace hv
 
 using namespace hv;
@@ -2056,12 +2065,11 @@ hubbard_status host_dot(const double2 *a, const double2 *b, uint64_t n, double2 
 
 // One step of the recurrence: w <- H v - alpha v - beta u with alpha =
 // <v|H v> (computed unless given), returns ||w||^2.  has_alpha: use *alpha.
-hubbard_status krylov_step(const Program &pr, const DeviceState &ds, const double2 *v,
-                           const double2 *u, double2 *w, double beta, bool has_alpha,
-                           double *alpha, double *wnorm2, double2 *partial, uint64_t n,
-                           hipStream_t s)
+hubbard_status krylov_step(const hv::ApplyH &apply, const double2 *v, const double2 *u,
+                           double2 *w, double beta, bool has_alpha, double *alpha,
+                           double *wnorm2, double2 *partial, uint64_t n, hipStream_t s)
 {
-    hubbard_status st = run_ham(pr, ds, v, w, nullptr, s);
+    hubbard_status st = apply(v, w);
     if (st != HUBBARD_OK)
         return st;
     if (!has_alpha) {
@@ -2088,6 +2096,91 @@ hubbard_status krylov_step(const Program &pr, const DeviceState &ds, const doubl
 }
 
 }  // namespace
+
+namespace hv {
+
+// The Lanczos recurrence on n amplitudes with the Hamiltonian given by
+// `apply` (see hubbard_lanczos): buf holds three vectors of n, partial the
+// vector kernels' block partials; gs (optional) receives the Ritz vector.
+hubbard_status lanczos_run(const ApplyH &apply, uint64_t n, const double2 *start_dev,
+                           int32_t max_iter, double tol, double *E0, int32_t *iters,
+                           double *residual, double2 *gs_dev, double2 *const buf[3],
+                           double2 *partial, hipStream_t s)
+{
+    hubbard_status st;
+    const unsigned g = vec_grid(n);
+    double nrm2 = 0.0, im = 0.0;
+    if ((st = host_dot(start_dev, start_dev, n, partial, s,
+                       &nrm2, &im)) != HUBBARD_OK)
+        return st;
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+        return fail(HUBBARD_ERR_ARG, "hubbard_lanczos: start vector has zero or non-finite norm");
+    const double inv0 = 1.0 / std::sqrt(nrm2);
+    // pass 1: the recurrence, alpha_j and beta_j, until the Ritz residual
+    // beta_j |s_j| of the lowest Ritz pair is below tol (or an invariant
+    // subspace: beta_j vanishes)
+    std::vector<double> alpha, beta, svec;
+    double lam = 0.0, res = 0.0;
+    {
+        double2 *v = buf[0], *u = buf[1], *w = buf[2];
+        hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, v,
+                           start_dev, inv0, n);
+        double bprev = 0.0;
+        for (int j = 0; j < max_iter; ++j) {
+            double a = 0.0, w2 = 0.0;
+            if ((st = krylov_step(apply, v, u, w, bprev, false, &a, &w2, partial, n, s)) !=
+                HUBBARD_OK)
+                return st;
+            alpha.push_back(a);
+            const double b = std::sqrt(w2);
+            svec.assign(alpha.size(), 0.0);
+            lam = tridiag_lowest(alpha.data(), beta.data(), (int)alpha.size(), svec.data());
+            res = b * std::fabs(svec.back());
+            const double scale = std::max(1.0, std::fabs(lam));
+            if (res <= tol * scale || b <= 1e-14 * scale)
+                break;
+            beta.push_back(b);
+            hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, u, w, 1.0 / b, n);
+            std::swap(u, v);   // u <- v_j, v <- v_{j+1}
+            bprev = b;
+        }
+    }
+    *E0 = lam;
+    if (iters)
+        *iters = (int32_t)alpha.size();
+    if (residual)
+        *residual = res;
+    if (!gs_dev)
+        return check_launch("lanczos");
+    // pass 2: the same recurrence with the stored coefficients (the same
+    // arithmetic, hence the same vectors) accumulating the Ritz vector
+    // x = sum_j s_j v_j, then normalised
+    double2 *x = gs_dev;
+    double2 *v = buf[0], *u = buf[1], *w = buf[2];
+    hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, v, start_dev,
+                       inv0, n);
+    hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, x, v, svec[0], n);
+    double bprev = 0.0;
+    for (size_t j = 0; j + 1 < alpha.size(); ++j) {
+        double a = alpha[j], w2 = 0.0;
+        if ((st = krylov_step(apply, v, u, w, bprev, true, &a, &w2, partial, n, s)) !=
+            HUBBARD_OK)
+            return st;
+        hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, u, w, 1.0 / beta[j], n);
+        std::swap(u, v);
+        hipLaunchKernelGGL(k_vaxpy, dim3(g), dim3(kVecThreads), 0, s, x, v, svec[j + 1], n);
+        bprev = beta[j];
+    }
+    double xn = 0.0;
+    if ((st = host_dot(x, x, n, partial, s, &xn, &im)) != HUBBARD_OK)
+        return st;
+    hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, x, x, 1.0 / std::sqrt(xn), n);
+    return check_launch("lanczos");
+}
+
+size_t lanczos_partial_bytes() { return vec_partial_bytes(); }
+
+}  // namespace hv
 
 extern "C" {
 
@@ -2136,7 +2229,6 @@ hubbard_status hubbard_lanczos(hubbard_t h, const void *start_dev, int32_t max_i
         return fail(HUBBARD_ERR_SIZE, "workspace too small for hubbard_lanczos");
     const size_t vb = align256(vec_bytes(h));
     const char *ws = (const char *)ws_dev;
-    const uint64_t n = (uint64_t)1 << h->m.nq;
     for (const void *p : {start_dev, (const void *)gs_dev}) {
         const char *q = (const char *)p;
         if (q && q < ws + need && ws < q + vec_bytes(h))
@@ -2149,75 +2241,12 @@ hubbard_status hubbard_lanczos(hubbard_t h, const void *start_dev, int32_t max_i
         return st;
     hipStream_t s = (hipStream_t)stream;
     double2 *buf[3] = {(double2 *)ws_dev, (double2 *)(ws + vb), (double2 *)(ws + 2 * vb)};
-    double2 *partial = (double2 *)(ws + 3 * vb);
-    const unsigned g = vec_grid(n);
-    double nrm2 = 0.0, im = 0.0;
-    if ((st = host_dot((const double2 *)start_dev, (const double2 *)start_dev, n, partial, s,
-                       &nrm2, &im)) != HUBBARD_OK)
-        return st;
-    if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
-        return fail(HUBBARD_ERR_ARG, "hubbard_lanczos: start vector has zero or non-finite norm");
-    const double inv0 = 1.0 / std::sqrt(nrm2);
-    // pass 1: the recurrence, alpha_j and beta_j, until the Ritz residual
-    // beta_j |s_j| of the lowest Ritz pair is below tol (or an invariant
-    // subspace: beta_j vanishes)
-    std::vector<double> alpha, beta, svec;
-    double lam = 0.0, res = 0.0;
-    {
-        double2 *v = buf[0], *u = buf[1], *w = buf[2];
-        hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, v,
-                           (const double2 *)start_dev, inv0, n);
-        double bprev = 0.0;
-        for (int j = 0; j < max_iter; ++j) {
-            double a = 0.0, w2 = 0.0;
-            if ((st = krylov_step(*pr, *ds, v, u, w, bprev, false, &a, &w2, partial, n, s)) !=
-                HUBBARD_OK)
-                return st;
-            alpha.push_back(a);
-            const double b = std::sqrt(w2);
-            svec.assign(alpha.size(), 0.0);
-            lam = tridiag_lowest(alpha.data(), beta.data(), (int)alpha.size(), svec.data());
-            res = b * std::fabs(svec.back());
-            const double scale = std::max(1.0, std::fabs(lam));
-            if (res <= tol * scale || b <= 1e-14 * scale)
-                break;
-            beta.push_back(b);
-            hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, u, w, 1.0 / b, n);
-            std::swap(u, v);   // u <- v_j, v <- v_{j+1}
-            bprev = b;
-        }
-    }
-    *E0 = lam;
-    if (iters)
-        *iters = (int32_t)alpha.size();
-    if (residual)
-        *residual = res;
-    if (!gs_dev)
-        return check_launch("lanczos");
-    // pass 2: the same recurrence with the stored coefficients (the same
-    // arithmetic, hence the same vectors) accumulating the Ritz vector
-    // x = sum_j s_j v_j, then normalised
-    double2 *x = (double2 *)gs_dev;
-    double2 *v = buf[0], *u = buf[1], *w = buf[2];
-    hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, v, (const double2 *)start_dev,
-                       inv0, n);
-    hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, x, v, svec[0], n);
-    double bprev = 0.0;
-    for (size_t j = 0; j + 1 < alpha.size(); ++j) {
-        double a = alpha[j], w2 = 0.0;
-        if ((st = krylov_step(*pr, *ds, v, u, w, bprev, true, &a, &w2, partial, n, s)) !=
-            HUBBARD_OK)
-            return st;
-        hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, u, w, 1.0 / beta[j], n);
-        std::swap(u, v);
-        hipLaunchKernelGGL(k_vaxpy, dim3(g), dim3(kVecThreads), 0, s, x, v, svec[j + 1], n);
-        bprev = beta[j];
-    }
-    double xn = 0.0;
-    if ((st = host_dot(x, x, n, partial, s, &xn, &im)) != HUBBARD_OK)
-        return st;
-    hipLaunchKernelGGL(k_vscale, dim3(g), dim3(kVecThreads), 0, s, x, x, 1.0 / std::sqrt(xn), n);
-    return check_launch("lanczos");
+    const hv::ApplyH apply = [&](const double2 *in, double2 *out) {
+        return run_ham(*pr, *ds, in, out, nullptr, s);
+    };
+    return hv::lanczos_run(apply, (uint64_t)1 << h->m.nq, (const double2 *)start_dev, max_iter,
+                           tol, E0, iters, residual, (double2 *)gs_dev, buf,
+                           (double2 *)(ws + 3 * vb), s);
 }
 
 hubbard_status hubbard_tridiag_lowest(const double *a, const double *b, int32_t m, double *lam,

@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -43,10 +44,17 @@
 
 namespace hv {
 
-// engine.hip: the handle's model, its unique id, the thread's last error
+// engine.hip: the handle's model, its unique id, the thread's last error,
+// the Lanczos recurrence on a Hamiltonian given as a callback
 const Model *handle_model(hubbard_t h);
 uint64_t handle_uid(hubbard_t h);
 hubbard_status set_error(hubbard_status s, const std::string &msg);
+using ApplyH = std::function<hubbard_status(const double2 *, double2 *)>;
+hubbard_status lanczos_run(const ApplyH &apply, uint64_t n, const double2 *start_dev,
+                           int32_t max_iter, double tol, double *E0, int32_t *iters,
+                           double *residual, double2 *gs_dev, double2 *const buf[3],
+                           double2 *partial, hipStream_t s);
+size_t lanczos_partial_bytes();
 
 namespace sec {
 
@@ -1112,6 +1120,19 @@ void hamiltonian(const Tables &T, const Program &P, int col, const double2 *psi_
     transpose(T, 1 - col, phi_y, phi_x, true, s);
 }
 
+// out <- H in for sector vectors in layout A (the 0-layer program's H ops:
+// up hops and D in layout A, down hops in layout B through in_b, out_b).
+void apply_h(const Tables &T, const Program &P, const double2 *in, double2 *out, double2 *in_b,
+             double2 *out_b, hipStream_t s)
+{
+    launch_rows<S_HAM>(T, P.d_ops + P.ham_x_off, P.ham_x_n, 0, 0, nullptr, nullptr,
+                       (double2 *)in, out, nullptr, 0, 0, s);
+    transpose(T, 0, in, in_b, false, s);
+    launch_rows<S_HAM>(T, P.d_ops + P.ham_y_off, P.ham_y_n, 1, 0, nullptr, nullptr, in_b, out_b,
+                       nullptr, 0, 0, s);
+    transpose(T, 1, out_b, out, true, s);
+}
+
 hubbard_status check(const char *what)
 {
     hipError_t e = hipGetLastError();
@@ -1151,11 +1172,12 @@ hubbard_status hubbard_sector_dim(hubbard_t h, int64_t *n_up, int64_t *n_dn)
 hubbard_status hubbard_sector_workspace_size(hubbard_t h, int32_t n_layers, int32_t op,
                                              size_t *bytes)
 {
-    if (!bytes || n_layers < 0 || op < HUBBARD_SECTOR_ANSATZ || op > HUBBARD_SECTOR_HAMILTONIAN)
+    if (!bytes || n_layers < 0 || op < HUBBARD_SECTOR_ANSATZ || op > HUBBARD_SECTOR_LANCZOS)
         return set_error(HUBBARD_ERR_ARG, "bad arguments to hubbard_sector_workspace_size");
     Tables *T = nullptr;
     Program *P = nullptr;
-    hubbard_status st = get(h, op == HUBBARD_SECTOR_HAMILTONIAN ? 0 : n_layers, &T, &P);
+    const bool h_only = op == HUBBARD_SECTOR_HAMILTONIAN || op == HUBBARD_SECTOR_LANCZOS;
+    hubbard_status st = get(h, h_only ? 0 : n_layers, &T, &P);
     if (st != HUBBARD_OK)
         return st;
     const size_t v = align256(vec_elems(*T) * 16);
@@ -1163,6 +1185,8 @@ hubbard_status hubbard_sector_workspace_size(hubbard_t h, int32_t n_layers, int3
         *bytes = v + ang_bytes(*P);
     else if (op == HUBBARD_SECTOR_HAMILTONIAN)
         *bytes = 2 * v;
+    else if (op == HUBBARD_SECTOR_LANCZOS)
+        *bytes = 5 * v + lanczos_partial_bytes();
     else
         *bytes = 4 * v + align256((size_t)P->n_rows * kGrid * 8) + ang_bytes(*P);
     return HUBBARD_OK;
@@ -1219,18 +1243,44 @@ hubbard_status sector_hamiltonian_apply(hubbard_t h, const void *psi_dev, void *
     if (!ws_dev || ws_bytes < 2 * v)
         return set_error(HUBBARD_ERR_SIZE, "workspace too small for sector_hamiltonian_apply");
     set_attrs();
+    char *w = (char *)ws_dev;
+    apply_h(*T, *P, (const double2 *)psi_dev, (double2 *)out_dev, (double2 *)w,
+            (double2 *)(w + v), (hipStream_t)stream);
+    return check("sector H");
+}
+
+hubbard_status hubbard_sector_lanczos(hubbard_t h, const void *start_dev, int32_t max_iter,
+                                      double tol, double *E0, int32_t *iters, double *residual,
+                                      void *gs_dev, void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (!start_dev || max_iter < 1 || !(tol > 0.0) || !E0 || !ws_dev)
+        return set_error(HUBBARD_ERR_ARG, "bad arguments to hubbard_sector_lanczos");
+    Tables *T = nullptr;
+    Program *P = nullptr;
+    hubbard_status st = get(h, 0, &T, &P);
+    if (st != HUBBARD_OK)
+        return st;
+    const size_t n = vec_elems(*T), v = align256(n * 16);
+    const size_t need = 5 * v + lanczos_partial_bytes();
+    if (ws_bytes < need)
+        return set_error(HUBBARD_ERR_SIZE, "workspace too small for hubbard_sector_lanczos");
+    const char *ws = (const char *)ws_dev;
+    for (const void *p : {start_dev, (const void *)gs_dev}) {
+        const char *q = (const char *)p;
+        if (q && q < ws + need && ws < q + n * 16)
+            return set_error(HUBBARD_ERR_ARG, "start or state vector overlaps the workspace");
+    }
+    set_attrs();
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws_dev;
-    // the 0-layer program's H ops: layout A (up hops and D), then B (down
-    // hops); no reduction rows (no energy)
-    double2 *psi_b = (double2 *)w, *phi_b = (double2 *)(w + v);
-    launch_rows<S_HAM>(*T, P->d_ops + P->ham_x_off, P->ham_x_n, 0, 0, nullptr, nullptr,
-                       (double2 *)psi_dev, (double2 *)out_dev, nullptr, 0, 0, s);
-    transpose(*T, 0, (const double2 *)psi_dev, psi_b, false, s);
-    launch_rows<S_HAM>(*T, P->d_ops + P->ham_y_off, P->ham_y_n, 1, 0, nullptr, nullptr, psi_b,
-                       phi_b, nullptr, 0, 0, s);
-    transpose(*T, 1, phi_b, (double2 *)out_dev, true, s);
-    return check("sector H");
+    double2 *buf[3] = {(double2 *)w, (double2 *)(w + v), (double2 *)(w + 2 * v)};
+    double2 *in_b = (double2 *)(w + 3 * v), *out_b = (double2 *)(w + 4 * v);
+    const ApplyH apply = [&](const double2 *in, double2 *out) {
+        apply_h(*T, *P, in, out, in_b, out_b, s);
+        return check("sector H");
+    };
+    return lanczos_run(apply, n, (const double2 *)start_dev, max_iter, tol, E0, iters, residual,
+                       (double2 *)gs_dev, buf, (double2 *)(w + 5 * v), s);
 }
 
 hubbard_status sector_energy_grad(hubbard_t h, const double *theta_dev, int32_t n_layers,

@@ -333,6 +333,26 @@ class Hubbard:
                                ws.data_ptr(), ws.numel(), _stream())
         return E, grad
 
+    def sector_lanczos(self, start: torch.Tensor | None = None, *, max_iter: int = 400,
+                       tol: float = 1e-10, want_state: bool = False, seed: int = 7):
+        """lanczos() on sector vectors: the ground state of H in the start
+        state's sector (default start: the checkerboard state after two
+        ansatz layers at angles drawn from `seed`).  Returns dict(E0, iters,
+        residual, state) with `state` a sector vector."""
+        if start is None:
+            th = np.random.default_rng(seed).uniform(-np.pi / 8, np.pi / 8, self.n_params(2))
+            start = self.sector_state(torch.tensor(th, dtype=torch.float64, device="cuda"))
+        _require_gpu(start, "start", torch.complex128)
+        nu, nd = self.sector_dims()
+        if start.numel() != nu * nd:
+            raise ValueError("start must hold C(Ns, N_up) * C(Ns, N_dn) amplitudes")
+        ws = self._sector_ws(0, abi.HUBBARD_SECTOR_LANCZOS, start.device)
+        gs = torch.empty_like(start) if want_state else None
+        E0, it, res = abi.hubbard_sector_lanczos(self.handle, start.data_ptr(), max_iter, tol,
+                                                 gs.data_ptr() if gs is not None else None,
+                                                 ws.data_ptr(), ws.numel(), _stream())
+        return dict(E0=E0, iters=it, residual=res, state=gs)
+
     def workspace_views(self, layers: int):
         """Two plain vector buffers carved out of the energy_grad workspace
         (scratch for ansatz/apply_h at the benchmark size; energy_grad stores
