@@ -174,6 +174,51 @@ def sector_bench(torch, dev, w, reps=3):
                         "iters": lz["iters"], "ritz_residual": lz["residual"], "seconds": t_lz}}
 
 
+def general_diagonal_leg(torch, dev, reps=5):
+    """The 24-qubit disordered ladder with on-site energies and V (the
+    general diagonal's kernels): energy+gradient evaluations/s and each
+    pass kind's launch-averaged HBM rate (algorithmic bytes as for the
+    benchmark workload) as a fraction of the peak."""
+    from paper_2408_00836_amd import abi, workloads as W
+    from paper_2408_00836_amd.model import Hubbard
+    w = W.config3()
+    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    th = torch.tensor(w.theta, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(w.n_params, dtype=torch.float64, device=dev)
+    n_fwd = len(abi.hubbard_plan_dump(m.handle, w.layers, 0))
+    n_rev = len(abi.hubbard_plan_dump(m.handle, w.layers, 2))
+    n_ham = len(abi.hubbard_plan_dump(m.handle, w.layers, 1))
+    abi.hubbard_set_timing(m.handle, True)
+    m.energy_grad(th, E, g)
+    torch.cuda.synchronize()
+    kt = {mode: [0.0, 0] for mode in ("forward", "reverse", "hamiltonian")}
+    ts = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        m.energy_grad(th, E, g)
+        abi.hubbard_phase_ms(m.handle)   # waits for the call's last event
+        ts.append(time.perf_counter() - a)
+        for mode in kt:
+            ms, cnt = abi.hubbard_kernel_ms(m.handle, abi.KERNEL_MODES[mode])
+            kt[mode][0] += ms
+            kt[mode][1] += cnt
+    abi.hubbard_set_timing(m.handle, False)
+    vec = 16.0 * (1 << w.n_qubits)
+    nvec = {"forward": (2.0 * n_fwd - 1.0) / n_fwd, "reverse": (4.0 * n_rev - 2.0) / n_rev,
+            "hamiltonian": (2.0 + 3.0 * (n_ham - 1)) / n_ham}
+    kinds = {}
+    for mode, (tot, cnt) in kt.items():
+        avg = tot / max(cnt, 1)
+        gbs = nvec[mode] * vec / (avg * 1e-3) / 1e9
+        kinds[mode] = {"kernel": f"hv::k_pass<{abi.KERNEL_MODES[mode]}, true, true, 1, false, 0>",
+                       "avg_ms": avg, "launches": cnt // reps, "GBs": gbs,
+                       "frac": gbs / HBM_PEAK_GBS}
+    t = min(ts)
+    return {"workload": w.name, "qubits": w.n_qubits, "evals_per_s": 1.0 / t,
+            "ms_per_eval": t * 1e3, "E": float(E.item()), "passes": kinds}
+
+
 def copy_reference(torch, dev, gib=8, reps=3):
     """Bandwidth of a plain device copy (torch elementwise kernel, `gib` GiB
     read + `gib` GiB written): the practical HBM ceiling for an in-place
@@ -293,6 +338,8 @@ def main():
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-sector", action="store_true")
+    ap.add_argument("--no-general", action="store_true",
+                    help="skip the 24-qubit general-diagonal leg")
     ap.add_argument("--sector-only", action="store_true",
                     help="time only the sector form (profiling runs)")
     args = ap.parse_args()
@@ -420,6 +467,12 @@ def main():
         sector = sector_bench(torch, dev, w)
         log(f"[bench] sector: {sector['ms_per_eval']:.1f} ms per evaluation")
 
+    general = None
+    if not args.no_general:
+        log("[bench] general diagonal: 24-qubit ladder with disorder, eps and V")
+        general = general_diagonal_leg(torch, dev)
+        log(f"[bench] general diagonal: {general['ms_per_eval']:.2f} ms per evaluation")
+
     batch = None
     if not args.no_batch:
         log("[bench] batch of 256 uneven instances")
@@ -461,6 +514,7 @@ def main():
         "copy_reference": copy,
         "batch": batch,
         "sector": sector,
+        "general_diagonal": general,
         "hpsi": {"ms": h_ms, "algorithmic_GBs": h_gbs, "frac": h_gbs / HBM_PEAK_GBS,
                  "passes": n_ham},
         "fd_plain": fd,
