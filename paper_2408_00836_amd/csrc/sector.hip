@@ -64,7 +64,7 @@ constexpr int kMaxRed = 16;               // reduction slots of one row pass
 constexpr int kGrid = 1024;               // at most this many row workgroups
 constexpr uint32_t kNone = 0xFFFFu;       // code of an element a gate leaves alone
 constexpr int kMaxRows = 13 * kT;         // longest row: C(16, 8) = 12870
-constexpr int kTrash = 64;                // LDS slots (one per lane) that inactive elements write
+constexpr int kTrash = 64;                // zeroed LDS slots (one per lane) that inactive elements read
 
 // Register tile of a row of n elements over kT threads: rpt_of(n) elements
 // per thread (element t + j kT in thread t).  A gate's code table holds
@@ -201,21 +201,27 @@ template <int TT, int RPT>
 __device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16_t *cb, int tid)
 {
     constexpr int ROUNDS = kT * rp_of(RPT) / 2 / TT;
-    const uint32_t wbase = (uint32_t)(tid & ~63);
+    // the wave's LDS base is uniform (a scalar register, no per-round
+    // readfirstlane); the lane's source offset is 32-bit (scalar base +
+    // vector offset addressing)
+    const uint32_t wbase = __builtin_amdgcn_readfirstlane((uint32_t)(tid & ~63));
+    const gu32 *__restrict__ s32 = (const gu32 *)src;
 #pragma unroll
     for (int k = 0; k < ROUNDS; ++k) {
         const uint32_t d0 = (uint32_t)k * TT;
         __builtin_amdgcn_global_load_lds(
-            (const __attribute__((address_space(1))) void *)(src + 2 * (d0 + (uint32_t)tid)),
+            (const __attribute__((address_space(1))) void *)(s32 + (d0 + (uint32_t)tid)),
             (__attribute__((address_space(3))) void *)(cb + 2 * (d0 + wbase)), 4, 0, 0);
     }
 }
 
 // One gate's exchange of vector x through the pair slots: every active
-// element publishes its value to its slot (an inactive one to its lane's
-// trash slot), then every element calls use(j, partner, w) with w = the
-// Jordan-Wigner sign (+-1) if it is active and 0 if not (its "partner" is
-// then its trash slot, a finite value): the whole exchange is branch-free.
+// element publishes its value to its slot, then every element calls use(j,
+// partner, w) with w = the Jordan-Wigner sign (+-1) if it is active and 0 if
+// not (its "partner" is then its lane's trash slot, which holds zero): the
+// reads and updates are branch-free.  (Inactive elements writing to their
+// trash slots too, to make the writes branch-free as well, cost 4 % of an
+// evaluation in LDS traffic.)
 // code(j): element j's code; fresh() runs before each half (HOLD: it makes
 // the code registers opaque, so that the decoded slot addresses are not
 // kept across the barrier).  HOLD: the codes are in registers and mid()
@@ -230,7 +236,8 @@ __device__ __forceinline__ void exchange(const double2 (&x)[N], C &&code, R &&fr
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         const uint32_t c = code(j);
-        xch[c != kNone ? (c & 0x7FFFu) : trash] = x[j];
+        if (c != kNone)
+            xch[c & 0x7FFFu] = x[j];
     }
     __syncthreads();
     if constexpr (HOLD)
@@ -312,6 +319,8 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     const gf64 *__restrict__ rbase = (const gf64 *)M->base[1 - col];
     for (int i = tid; i < kMaxRed * kWv; i += TT)
         acc[i] = 0.0;
+    for (int i = tid; i < kTrash; i += TT)   // read by inactive elements, never written
+        xch[xch_elems + i] = make_double2(0.0, 0.0);
     if constexpr (MODE != S_HAM && GEN)
         build_cis(cis, tid, TT);
     // execution position of the pass's diagonal op (at most one; n_ops: none)
@@ -351,12 +360,13 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
             a[j] = idx < n ? a[j] : make_double2(0.0, 0.0);
             b[j] = make_double2(0.0, 0.0);
         }
+        // this thread's part of the current reduction slot's sum (REV)
+        double racc = 0.0;
         // op at execution position oi; IS_DIAG: the diagonal op, else a hop
         auto step = [&](int oi, auto diag_tag) __attribute__((always_inline)) {
             constexpr bool IS_DIAG = decltype(diag_tag)::value;
             const int io = REV ? n_ops - 1 - oi : oi;
             const SecOp op = ops[io];
-            double racc = 0.0;
             // the element indices recomputed per op, not kept live (with
             // their 64-bit table addresses) across the op loop
             uint32_t t = (uint32_t)tid;
@@ -458,22 +468,38 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     }
                 });
             }
+        };
+        // REV: the thread's sum of a run of ops with one reduction slot into
+        // that slot (one wave reduction per run, not per op)
+        auto flush = [&](int red) __attribute__((always_inline)) {
             if constexpr (REV) {
                 const double w = wave_sum(racc);
                 if (lane == 0)
-                    acc[op.red * kWv + wave] += w;
+                    acc[red * kWv + wave] += w;
+                racc = 0.0;
+            }
+        };
+        // the hops at execution positions [o0, o1), in runs of equal slots
+        auto hops = [&](int o0, int o1) __attribute__((always_inline)) {
+            for (int oi = o0; oi < o1;) {
+                const int red = ops[REV ? n_ops - 1 - oi : oi].red;
+                do {
+                    step(oi, std::false_type());
+                    ++oi;
+                } while (oi < o1 && ops[REV ? n_ops - 1 - oi : oi].red == red);
+                flush(red);
             }
         };
         // the hops before the diagonal, the diagonal, the hops after it: each
         // loop body is a single path, so the register tile keeps its
         // registers across ops (a loop over both kinds merges two versions
         // of the tile at the end of every op, and copies it)
-        for (int oi = 0; oi < dexec; ++oi)
-            step(oi, std::false_type());
-        if (dexec < n_ops)
+        hops(0, dexec);
+        if (dexec < n_ops) {
             step(dexec, std::true_type());
-        for (int oi = dexec + 1; oi < n_ops; ++oi)
-            step(oi, std::false_type());
+            flush(ops[REV ? n_ops - 1 - dexec : dexec].red);
+        }
+        hops(dexec + 1, n_ops);
         if constexpr (MODE == S_HAM) {
 #pragma unroll
             for (int j = 0; j < N; ++j)
