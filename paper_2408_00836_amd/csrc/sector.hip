@@ -115,7 +115,8 @@ struct SecModel {
 
 // D of the basis state with row pattern rp and column pattern cp:
 // U #(doubly occupied) + base(rp) + base(cp) + sum_b V_b (rp_i cp_j + cp_i rp_j).
-__device__ __forceinline__ double diag_d(const SecModel *M, uint32_t rp, double rb, uint32_t cp,
+template <typename MT>
+__device__ __forceinline__ double diag_d(const MT *M, uint32_t rp, double rb, uint32_t cp,
                                          double cb)
 {
     double d = M->U * (double)__popc(rp & cp) + rb + cb;
@@ -166,6 +167,15 @@ typedef const __attribute__((address_space(1))) uint32_t gu32;
 typedef const __attribute__((address_space(1))) uint16_t gu16;
 typedef const __attribute__((address_space(1))) double gf64;
 typedef __attribute__((address_space(1))) double2 gc128;
+// The op list, its angles and the model constants are read-only for the
+// whole launch: constant address space, so that their wave-uniform loads are
+// scalar loads (as generic pointers they became vector loads with a wait in
+// front of every op).
+typedef const __attribute__((address_space(4))) SecOp kSecOp;
+typedef const __attribute__((address_space(4))) SecModel kSecModel;
+typedef const __attribute__((address_space(4))) double2 kc128;
+typedef const __attribute__((address_space(4))) uint32_t ku32;
+typedef const __attribute__((address_space(4))) double kf64;
 
 // The gate's codes of thread t, from the LDS copy of its table: one load
 // per chunk (codes past the row end are kNone in the table).
@@ -290,6 +300,9 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
            double *__restrict__ partial, int row0, int pstride, int flags, int xch_elems)
 {
     static_assert(kT % TT == 0, "a thread plays a whole number of tile threads");
+    const kSecOp *__restrict__ kops = (const kSecOp *)ops;
+    const kc128 *__restrict__ kang = (const kc128 *)ang;
+    const kSecModel *__restrict__ kM = (const kSecModel *)M;
     constexpr int VT = kT / TT;    // tile threads per thread
     constexpr int N = VT * RPT;    // elements per thread
     constexpr int kWv = TT / 64;   // waves of the workgroup
@@ -304,19 +317,21 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     extern __shared__ __align__(16) char smem[];
     double2 *xch = (double2 *)smem;   // pair slots, then kTrash trash slots
     double *acc = (double *)(smem + (size_t)(xch_elems + kTrash) * 16);   // kMaxRed x kWaves
-    double2 *cis = (double2 *)(acc + kMaxRed * kWaves);                   // unit phases
+    double2 *dloc = (double2 *)(acc + kMaxRed * kWaves);   // the pass's U-count phase table
+    double2 *cis = dloc + kDiagTab;                                       // unit phases
     uint16_t *cbuf = (uint16_t *)(cis + (1u << kCisBits));                // the next gate's codes
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t trash = (uint32_t)(xch_elems + lane);
-    const uint32_t n = (uint32_t)M->n[col];
-    const int nr = M->n[1 - col];
+    const uint32_t n = (uint32_t)kM->n[col];
+    const int nr = kM->n[1 - col];
     // the tables' pointers come from memory: global address space, so that
     // the loads take a scalar base and a 32-bit offset
-    const gu32 *__restrict__ cpat = (const gu32 *)M->pat[col];
-    const gf64 *__restrict__ cbase = (const gf64 *)M->base[col];
-    const gu16 *__restrict__ gcode = (const gu16 *)M->code;
-    const gu32 *__restrict__ rpat = (const gu32 *)M->pat[1 - col];
-    const gf64 *__restrict__ rbase = (const gf64 *)M->base[1 - col];
+    const gu32 *__restrict__ cpat = (const gu32 *)kM->pat[col];
+    const gf64 *__restrict__ cbase = (const gf64 *)kM->base[col];
+    const gu16 *__restrict__ gcode = (const gu16 *)kM->code;
+    // row-uniform: scalar loads
+    const ku32 *__restrict__ rpat = (const ku32 *)kM->pat[1 - col];
+    const kf64 *__restrict__ rbase = (const kf64 *)kM->base[1 - col];
     for (int i = tid; i < kMaxRed * kWv; i += TT)
         acc[i] = 0.0;
     for (int i = tid; i < kTrash; i += TT)   // read by inactive elements, never written
@@ -326,18 +341,28 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     // execution position of the pass's diagonal op (at most one; n_ops: none)
     int dexec = n_ops;
     for (int io = 0; io < n_ops; ++io)
-        if (ops[io].kind == SOP_DIAG)
+        if (kops[io].kind == SOP_DIAG)
             dexec = REV ? n_ops - 1 - io : io;
+    // U-only gate passes: the diagonal op's phase table in LDS (conjugated to
+    // un-apply), looked up per element by the number of doubly occupied sites
+    if constexpr (MODE != S_HAM && !GEN) {
+        if (dexec < n_ops && tid < kDiagTab) {
+            double2 e = dph[(size_t)kops[REV ? n_ops - 1 - dexec : dexec].tab * kDiagTab + tid];
+            if constexpr (REV)
+                e.y = -e.y;
+            dloc[tid] = e;
+        }
+    }
     // cbuf holds the code table of op `ready` (-1: none); the first hopping
     // op in execution order now
     int ready = -1;
     for (int oi = 0; oi < n_ops && ready < 0; ++oi) {
         const int io = REV ? n_ops - 1 - oi : oi;
-        if (ops[io].kind == SOP_HOP)
+        if (kops[io].kind == SOP_HOP)
             ready = io;
     }
     if (ready >= 0) {
-        fetch_codes<TT, RPT>(gcode + ops[ready].tab, cbuf, tid);
+        fetch_codes<TT, RPT>(gcode + kops[ready].tab, cbuf, tid);
         __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
@@ -366,7 +391,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
         auto step = [&](int oi, auto diag_tag) __attribute__((always_inline)) {
             constexpr bool IS_DIAG = decltype(diag_tag)::value;
             const int io = REV ? n_ops - 1 - oi : oi;
-            const SecOp op = ops[io];
+            const kSecOp &op = kops[io];
             // the element indices recomputed per op, not kept live (with
             // their 64-bit table addresses) across the op loop
             uint32_t t = (uint32_t)tid;
@@ -374,15 +399,21 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
             if constexpr (IS_DIAG) {
                 double th = 0.0;
                 if constexpr (MODE != S_HAM)
-                    th = ang[io].x;
+                    th = kang[io].x;
+                // every element's column pattern (U-only: its number of doubly
+                // occupied sites) first, the loads in flight together
+                uint32_t kc[N];
 #pragma unroll
                 for (int j = 0; j < N; ++j) {
-                    const uint32_t ic = min(elem(t, j), n - 1);   // past the end: a zero element
+                    const uint32_t cp = cpat[min(elem(t, j), n - 1)];   // past the end: a zero element
+                    kc[j] = GEN ? cp : __popc(rp & cp);
+                }
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
                     {
-                        const uint32_t cp = cpat[ic];
-                        const uint32_t k = __popc(rp & cp);
-                        const double d = GEN ? diag_d(M, rp, rb, cp, cbase[ic])
-                                             : M->U * (double)k;
+                        const uint32_t k = kc[j];
+                        const double d = GEN ? diag_d(kM, rp, rb, k, cbase[min(elem(t, j), n - 1)])
+                                             : kM->U * (double)k;
                         if constexpr (MODE == S_HAM) {
                             fmac_ip(b[j].x, d, a[j].x);
                             fmac_ip(b[j].y, d, a[j].y);
@@ -392,9 +423,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                             if constexpr (GEN) {
                                 e = cis_neg(REV ? -th * d : th * d, cis);
                             } else {
-                                e = dph[(size_t)op.tab * kDiagTab + k];
-                                if constexpr (REV)
-                                    e.y = -e.y;
+                                e = dloc[k];
                             }
                             if constexpr (REV)   // <chi|D|chi> term
                                 racc += d * (a[j].x * a[j].x + a[j].y * a[j].y);
@@ -410,9 +439,8 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
             } else {
                 double cs = 0.0, sn = 0.0;
                 if constexpr (MODE != S_HAM) {
-                    const double2 cssn = ang[io];   // (cos, sin)(th t)
-                    cs = cssn.x;
-                    sn = REV ? -cssn.y : cssn.y;    // un-apply: sin -> -sin
+                    cs = kang[io].x;                 // (cos, sin)(th t)
+                    sn = REV ? -kang[io].y : kang[io].y;   // un-apply: sin -> -sin
                 }
                 const double mt = -op.t;
                 if (ready != io) {   // not prefetched (the op list's nxt links are broken)
@@ -447,7 +475,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     }
                 }, xch, trash, [&]() {
                     if (nxt >= 0)
-                        fetch_codes<TT, RPT>(gcode + ops[nxt].tab, cbuf, tid);
+                        fetch_codes<TT, RPT>(gcode + kops[nxt].tab, cbuf, tid);
                 }, [&](int j, double2 p, double w) {
                     if constexpr (MODE == S_HAM) {   // phi += (-t) s psi_x'
                         const double m = mt * w;
@@ -479,15 +507,21 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                 racc = 0.0;
             }
         };
-        // the hops at execution positions [o0, o1), in runs of equal slots
+        // the hops at execution positions [o0, o1) (REV: in runs of equal
+        // reduction slots)
         auto hops = [&](int o0, int o1) __attribute__((always_inline)) {
-            for (int oi = o0; oi < o1;) {
-                const int red = ops[REV ? n_ops - 1 - oi : oi].red;
-                do {
+            if constexpr (REV) {
+                for (int oi = o0; oi < o1;) {
+                    const int red = kops[n_ops - 1 - oi].red;
+                    do {
+                        step(oi, std::false_type());
+                        ++oi;
+                    } while (oi < o1 && kops[n_ops - 1 - oi].red == red);
+                    flush(red);
+                }
+            } else {
+                for (int oi = o0; oi < o1; ++oi)
                     step(oi, std::false_type());
-                    ++oi;
-                } while (oi < o1 && ops[REV ? n_ops - 1 - oi : oi].red == red);
-                flush(red);
             }
         };
         // the hops before the diagonal, the diagonal, the hops after it: each
@@ -497,7 +531,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
         hops(0, dexec);
         if (dexec < n_ops) {
             step(dexec, std::true_type());
-            flush(ops[REV ? n_ops - 1 - dexec : dexec].red);
+            flush(kops[REV ? n_ops - 1 - dexec : dexec].red);
         }
         hops(dexec + 1, n_ops);
         if constexpr (MODE == S_HAM) {
@@ -722,12 +756,13 @@ hipError_t upload(void **dst, const void *src, size_t bytes)
 int popc(uint32_t x) { return __builtin_popcount(x); }
 
 // LDS of a row workgroup: the pair and trash slots, the reduction slots, the
-// unit phases, one gate's code table (of the longer row).
+// U-count phase table, the unit phases, one gate's code table (of the longer
+// row).
 size_t lds_bytes(const Tables &T)
 {
     const int rp = std::max(rp_of(rpt_of(T.n[0])), rp_of(rpt_of(T.n[1])));
-    return (size_t)(T.xch + kTrash) * 16 + kMaxRed * kWaves * 8 + (1u << kCisBits) * 16 +
-           (size_t)kT * rp * 2;
+    return (size_t)(T.xch + kTrash) * 16 + kMaxRed * kWaves * 8 + kDiagTab * 16 +
+           (1u << kCisBits) * 16 + (size_t)kT * rp * 2;
 }
 
 hubbard_status build_tables(const Model &m, Tables &T)
