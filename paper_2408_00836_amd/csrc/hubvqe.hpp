@@ -339,6 +339,8 @@ struct TileConfig {
 // Forward circuit (layers of Eq. (7)) as elementary ops, then fused passes.
 std::vector<HostOp> circuit_ops(const Model &m, int layers);
 std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig &tc);
+// Fused passes of an op list on n qubits (the forward planner's search).
+std::vector<HostPass> plan_ops(const std::vector<HostOp> &ops, int n, const TileConfig &tc);
 // Passes that together apply H (terms split over tiles, D in the first).
 std::vector<HostPass> plan_hamiltonian(const Model &m, const TileConfig &tc);
 // Split a pass's ops into register phases (reorders ops within the pass only

@@ -253,11 +253,14 @@ std::vector<HostOp> circuit_ops(const Model &m, int layers)
 
 std::vector<HostPass> plan_forward(const Model &m, int layers, const TileConfig &tc)
 {
-    std::vector<HostOp> ops = circuit_ops(m, layers);
+    return plan_ops(circuit_ops(m, layers), m.nq, tc);
+}
+
+std::vector<HostPass> plan_ops(const std::vector<HostOp> &ops, int n, const TileConfig &tc)
+{
     std::vector<HostPass> passes;
     if (ops.empty())
         return passes;
-    const int n = m.nq;
     const int k = std::min(tc.k, n);
     const int c = std::min(tc.c, k);
     if (n <= k) {
