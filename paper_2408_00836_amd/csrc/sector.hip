@@ -232,30 +232,31 @@ __device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16
 // reads and updates are branch-free.  (Inactive elements writing to their
 // trash slots too, to make the writes branch-free as well, cost 4 % of an
 // evaluation in LDS traffic.)
-// code(j): element j's code; fresh() runs before each half (HOLD: it makes
-// the code registers opaque, so that the decoded slot addresses are not
-// kept across the barrier).  HOLD: the codes are in registers and mid()
-// (the next gate's table fetch) is issued right after the publishing
-// barrier; else code(j) reads the LDS table, which mid() overwrites: it is
-// issued after a barrier that follows every wave's last read.
-template <int N, bool HOLD, typename C, typename R, typename G, typename F>
-__device__ __forceinline__ void exchange(const double2 (&x)[N], C &&code, R &&fresh,
-                                         double2 *xch, uint32_t trash, G &&mid, F &&use)
+// The codes are in registers: they are made opaque before each half, so that
+// the decoded slot addresses are not kept across the barrier; mid() (the
+// next gate's table fetch into the LDS the codes came from) is issued right
+// after the publishing barrier, by when every thread holds its codes.
+template <int RPT, typename G, typename F>
+__device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd, double2 *xch,
+                                         uint32_t trash, G &&mid, F &&use)
 {
-    fresh();
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-        const uint32_t c = code(j);
+    for (int k = 0; k < rp_of(RPT) / 2; ++k)
+        asm volatile("" : "+v"(cd.w[k]));
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const uint32_t c = cd.get(j);
         if (c != kNone)
             xch[c & 0x7FFFu] = x[j];
     }
     __syncthreads();
-    if constexpr (HOLD)
-        mid();
-    fresh();
+    mid();
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-        const uint32_t c = code(j);
+    for (int k = 0; k < rp_of(RPT) / 2; ++k)
+        asm volatile("" : "+v"(cd.w[k]));
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const uint32_t c = cd.get(j);
         const bool act = c != kNone;
         const double2 p = xch[act ? ((c & 0x7FFFu) ^ 1u) : trash];
         use(j, p, act ? ((c >> 15) ? -1.0 : 1.0) : 0.0);
@@ -263,20 +264,13 @@ __device__ __forceinline__ void exchange(const double2 (&x)[N], C &&code, R &&fr
         // LDS latency): the register tile keeps its registers
         __builtin_amdgcn_sched_barrier(0);
     }
-    if constexpr (!HOLD) {
-        __syncthreads();
-        mid();
-    }
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of mid()'s copies has landed
     __syncthreads();
 }
 
 // Row pass.  Each workgroup takes rows blockIdx.x, blockIdx.x + gridDim.x, ...
-// of the layout whose columns are indexed by spin `col`.  The row's register
-// tile is that of kT threads holding RPT elements each (element u + j kT in
-// tile thread u, j < RPT); a workgroup of TT = kT / VT threads plays VT tile
-// threads per thread (thread t: tile threads t + v TT, v < VT), so that a
-// two-vector tile can have twice the registers per thread.
+// of the layout whose columns are indexed by spin `col`; thread t holds the
+// row's elements t + j TT, j < RPT (TT = kT, the layout of the code tables).
 //   S_FWD: v0 <- ops applied in order.
 //   S_REV: v0 = chi <- ops un-applied in reverse order; the expectation
 //          <chi| G |chi> of every op before its un-application goes to its
@@ -299,21 +293,15 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
            const SecModel *__restrict__ M, double2 *__restrict__ v0, double2 *__restrict__ v1,
            double *__restrict__ partial, int row0, int pstride, int flags, int xch_elems)
 {
-    static_assert(kT % TT == 0, "a thread plays a whole number of tile threads");
+    static_assert(TT == kT, "the code tables are laid out for kT threads");
     const kSecOp *__restrict__ kops = (const kSecOp *)ops;
     const kc128 *__restrict__ kang = (const kc128 *)ang;
     const kSecModel *__restrict__ kM = (const kSecModel *)M;
-    constexpr int VT = kT / TT;    // tile threads per thread
-    constexpr int N = VT * RPT;    // elements per thread
+    constexpr int N = RPT;         // elements per thread
     constexpr int kWv = TT / 64;   // waves of the workgroup
     constexpr bool REV = MODE == S_REV;
-    // FWD and REV hold a gate's codes in registers; H, whose register tile
-    // holds two vectors, reads them from LDS where it uses them
-    constexpr bool HOLD = MODE != S_HAM;
-    // column of a thread's element e (tile thread u + v TT, register j)
-    auto elem = [](uint32_t u, int e) -> uint32_t {
-        return u + (uint32_t)((e / RPT) * TT + (e % RPT) * kT);
-    };
+    // column of thread u's element e
+    auto elem = [](uint32_t u, int e) -> uint32_t { return u + (uint32_t)(e * TT); };
     extern __shared__ __align__(16) char smem[];
     double2 *xch = (double2 *)smem;   // pair slots, then kTrash trash slots
     double *acc = (double *)(smem + (size_t)(xch_elems + kTrash) * 16);   // kMaxRed x kWaves
@@ -448,32 +436,14 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     __builtin_amdgcn_s_waitcnt(0);
                     __syncthreads();
                 }
-                Codes<RPT> cd[VT];
-                if constexpr (HOLD) {
-#pragma unroll
-                    for (int v = 0; v < VT; ++v)
-                        cd[v] = load_codes<RPT>(cbuf, t + (uint32_t)(v * TT));
-                }
+                const Codes<RPT> cd = load_codes<RPT>(cbuf, t);
                 // the next hop's codes arrive in cbuf while this one is applied
-                // (HOLD: issued after the exchange's first barrier, by when every
-                // thread has its codes in registers; else after the last read)
+                // (issued after the exchange's first barrier, by when every
+                // thread has its codes in registers)
                 ready = (r + (int)gridDim.x < nr || oi + 1 < n_ops) ? op.nxt[REV ? 1 : 0] : -1;
                 const int nxt = ready;
                 // w = sign (active) or 0 (inactive: cos factor 1, no partner term)
-                exchange<N, HOLD>(a, [&](int e) -> uint32_t {
-                    if constexpr (HOLD)
-                        return cd[e / RPT].get(e % RPT);
-                    else
-                        return cbuf[code_index(RPT, (int)t + (e / RPT) * TT, e % RPT)];
-                }, [&]() {
-                    if constexpr (HOLD) {
-#pragma unroll
-                        for (int v = 0; v < VT; ++v)
-#pragma unroll
-                            for (int k = 0; k < rp_of(RPT) / 2; ++k)
-                                asm volatile("" : "+v"(cd[v].w[k]));
-                    }
-                }, xch, trash, [&]() {
+                exchange<RPT>(a, cd, xch, trash, [&]() {
                     if (nxt >= 0)
                         fetch_codes<TT, RPT>(gcode + kops[nxt].tab, cbuf, tid);
                 }, [&](int j, double2 p, double w) {
@@ -1066,8 +1036,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workgroup shape by row length: 1024 threads holding up to 13 elements of
 // each vector.  (At 13 elements, H -- two vectors -- and the general
-// diagonal's reverse pass keep part of their tile in scratch memory: 84 and
-// 104 bytes per thread; 512 threads playing two tile threads each spilled
+// diagonal's gate passes keep part of their tiles in scratch memory, about
+// 100 bytes per thread; 512 threads playing two tile threads each spilled
 // more.)
 template <int MODE, bool GEN>
 void launch_rows_g(const Tables &T, const SecOp *ops, int n_ops, int col, int n_red,
