@@ -148,6 +148,12 @@ __device__ __forceinline__ void fmac_ip(double &acc, double m, double q)
     asm("v_fma_f64 %0, %1, %2, %0" : "+v"(acc) : "v"(m), "v"(q));
 }
 
+// x with its sign bit flipped when bit (0 or 1) is set.
+__device__ __forceinline__ double flip_sign(double x, uint32_t bit)
+{
+    return __longlong_as_double(__double_as_longlong(x) ^ ((long long)bit << 63));
+}
+
 __device__ __forceinline__ double wave_sum(double x)
 {
     for (int off = 32; off > 0; off >>= 1)
@@ -227,8 +233,9 @@ __device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16
 
 // One gate's exchange of vector x through the pair slots: every active
 // element publishes its value to its slot, then every element calls use(j,
-// partner, w) with w = the Jordan-Wigner sign (+-1) if it is active and 0 if
-// not (its "partner" is then its lane's trash slot, which holds zero): the
+// partner, active, sign bit) (the Jordan-Wigner sign (-1)^bit; an inactive
+// element's "partner" is its lane's trash slot, which holds zero, so that
+// every term with the partner vanishes for it whatever the sign): the
 // reads and updates are branch-free.  (Inactive elements writing to their
 // trash slots too, to make the writes branch-free as well, cost 4 % of an
 // evaluation in LDS traffic.)
@@ -259,7 +266,7 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
         const uint32_t c = cd.get(j);
         const bool act = c != kNone;
         const double2 p = xch[act ? ((c & 0x7FFFu) ^ 1u) : trash];
-        use(j, p, act ? ((c >> 15) ? -1.0 : 1.0) : 0.0);
+        use(j, p, act, (c >> 15) & 1u);
         // one partner value in flight per thread (the other waves hide the
         // LDS latency): the register tile keeps its registers
         __builtin_amdgcn_sched_barrier(0);
@@ -446,20 +453,22 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                 exchange<RPT>(a, cd, xch, trash, [&]() {
                     if (nxt >= 0)
                         fetch_codes<TT, RPT>(gcode + kops[nxt].tab, cbuf, tid);
-                }, [&](int j, double2 p, double w) {
+                }, [&](int j, double2 p, bool act, uint32_t sgn) {
+                    // s (-t) and s sn by a flip of the sign bit (p = 0 when
+                    // inactive: those terms then vanish without a select)
                     if constexpr (MODE == S_HAM) {   // phi += (-t) s psi_x'
-                        const double m = mt * w;
+                        const double m = flip_sign(mt, sgn);
                         fmac_ip(b[j].x, m, p.x);
                         fmac_ip(b[j].y, m, p.y);
                         pin(b[j]);
                     } else {
                         const double2 y = a[j];
                         if constexpr (REV) {   // <chi|h|chi> term: (-t) s Re(conj(chi_x) chi_x')
-                            racc += mt * w * (y.x * p.x + y.y * p.y);
+                            racc += flip_sign(mt, sgn) * (y.x * p.x + y.y * p.y);
                             pin(racc);
                         }
-                        const double ss = w * sn;      // x <- cs x + i s sn x'
-                        const double c = w != 0.0 ? cs : 1.0;
+                        const double ss = flip_sign(sn, sgn);   // x <- cs x + i s sn x'
+                        const double c = act ? cs : 1.0;
                         fma_ip(a[j].x, c, -ss * p.y);
                         fma_ip(a[j].y, c, ss * p.x);
                         pin(a[j]);
