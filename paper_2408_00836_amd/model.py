@@ -298,6 +298,10 @@ class Hubbard:
             ws = cache[key] = torch.empty(nb, dtype=torch.uint8, device=device)
         return ws
 
+    def release_sector_workspaces(self) -> None:
+        """Drop the cached sector workspaces (device memory back to torch)."""
+        self.__dict__.pop("_sector_ws_cache", None)
+
     def sector_state(self, theta: torch.Tensor | None = None) -> torch.Tensor:
         """psi(theta) as a sector vector (|b0> when theta is None)."""
         nu, nd = self.sector_dims()

@@ -101,7 +101,8 @@ TILE_CASES = {
     "ladder2x7 (4 per thread)": lambda: W.random_instance(2, 7, 1, 5, 4311, U=6.0, disorder=0.1,
                                                           name="2x7 ladder U=6"),
     "lattice3x5 (8 per thread)": lambda: W.random_instance(3, 5, 1, 5, 4312, U=3.0,
-                                                           disorder=0.1, name="3x5 U=3"),
+                                                           disorder=0.1, eps_width=0.3, V=0.4,
+                                                           name="3x5 U=3 eps V"),
 }
 
 
@@ -127,6 +128,39 @@ def test_sector_register_tiles(gpu, key):
     assert herr <= AMP_TOL
     assert dE <= e_tol(E_ref)
     assert dg <= GRAD_TOL
+
+
+def test_sector_general_diagonal_32q(gpu):
+    """Rows of 12870 (13 elements per thread) with the general diagonal
+    (on-site energies and V): the sector form against the full-vector path
+    (itself pinned to the oracle up to 24 qubits with the same diagonal) on a
+    4x4 open lattice, two layers: E, every gradient entry, and amplitudes at
+    sampled positions."""
+    w = W.random_instance(4, 4, 2, 5, 4320, U=6.0, disorder=0.1, eps_width=0.4, V=0.5,
+                          name="4x4 open eps V")
+    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    th = torch.tensor(w.theta, dtype=torch.float64, device=gpu)
+    Es, gs = m.sector_energy_grad(th)
+    psi_s = m.sector_state(th)
+    om = make_model(w.nx, w.ny, **w.kwargs())
+    rng = np.random.default_rng(4321)
+    pos = np.sort(rng.choice(psi_s.numel(), 256, replace=False))
+    idx = osec.indices(om)[pos].astype(np.int64)
+    amp_s = psi_s[torch.tensor(pos, device=gpu)].cpu().numpy()
+    del psi_s
+    m.release_sector_workspaces()
+    torch.cuda.empty_cache()
+    Ef, gf = m.energy_grad(th)
+    psi_f = m.ansatz(th)
+    amp_f = psi_f[torch.tensor(idx, device=gpu)].cpu().numpy()
+    del psi_f
+    dE = abs(Es.item() - Ef.item())
+    dg = float(np.max(np.abs(gs.cpu().numpy() - gf.cpu().numpy())))
+    amp = float(np.max(np.abs(amp_s - amp_f)))
+    say(f"[sector 32q general] dE {dE:.2e} dg {dg:.2e} amp {amp:.2e}")
+    assert dE <= e_tol(Ef.item())
+    assert dg <= GRAD_TOL
+    assert amp <= AMP_TOL
 
 
 @pytest.mark.parametrize("layers", [0, 1, 2])
