@@ -107,8 +107,8 @@ struct SecModel {
     double U;
     const uint32_t *pat[2];    // site pattern of each rank
     const double *base[2];     // sum_i eps_i p_i + sum_b V_b p_i p_j of each rank
-    const uint16_t *code;      // per gate and rank: pair slot | sign << 15, or kNone
-                               // (each gate's table padded to an even length)
+    const uint16_t *code;      // per gate: pair slot | sign << 15 (kNone: not active)
+                               // of every column, at code_index (kT rp_of(rpt) entries)
     int32_t vi[kMaxBonds], vj[kMaxBonds];
     double vV[kMaxBonds];
 };
@@ -292,7 +292,7 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
 // at partial[(row0 + slot) * pstride + blockIdx.x] (fixed order).
 // GEN: the diagonal has eps or V terms (D from the pattern tables, its phase
 // by cis_neg); else D = U #(doubly occupied) and its phase comes from the
-// op's table dph[op.tab][k] = exp(-i th U k).
+// op's table dph[op.tab][k] = exp(-i th U k), copied into LDS at the start.
 template <int MODE, int TT, int RPT, bool GEN>
 __global__ void __launch_bounds__(TT)
 k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
