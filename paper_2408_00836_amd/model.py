@@ -281,6 +281,28 @@ class Hubbard:
                               _stream(), opts)
         return th, res
 
+    def sector_vqe(self, theta0, layers: int, opts: dict | None = None):
+        """vqe() with every energy+gradient evaluation in the sector form (the
+        same optimiser and stopping rules, driven from here; the starts run
+        one after another).  Returns (final thetas on the device, results)."""
+        th0 = np.asarray(theta0, dtype=np.float64).reshape(-1, self.n_params(layers))
+        out = torch.empty(th0.shape, dtype=torch.float64, device="cuda")
+        E = torch.empty(1, dtype=torch.float64, device="cuda")
+        g = torch.empty(th0.shape[1], dtype=torch.float64, device="cuda")
+        results = []
+        for i, x0 in enumerate(th0):
+            opt = abi.Lbfgs(x0, opts)
+            x = opt.start
+            while True:
+                th = torch.as_tensor(x, device="cuda")
+                self.sector_energy_grad(th, E, g)
+                state, x = opt.tell(E.item(), g.cpu().numpy())
+                if state != 0:
+                    break
+            out[i] = torch.as_tensor(x, device="cuda")
+            results.append(opt.result())
+        return out, results
+
     # ---- particle-number sector form (HVA only; see hubbard_sector_dim) ----
     def sector_dims(self):
         """(C(Ns, N_up), C(Ns, N_dn)): a sector vector holds their product,

@@ -18,21 +18,22 @@ from . import workloads as W
 
 
 def run(model, layers: int, *, n_starts: int = 10, seed: int = 0, warm_start: bool = True,
-        opts: dict | None = None, E_ref: float | None = None) -> dict:
+        opts: dict | None = None, E_ref: float | None = None, sector: bool = False) -> dict:
     """Returns dict(E, theta, best, results, warm_results, delta_per_site):
     the lowest final energy, its parameters (host array), the index of that
     start, every start's result (energy, gradient norm, iterations,
     evaluations, stopping reason) and, with E_ref, (E - E_ref) / N_sites,
-    the error per site of Sec. 3.1."""
+    the error per site of Sec. 3.1.  sector: evaluate in the particle-number
+    sector form (HVA circuit; the starts run one after another)."""
     P = model.n_params(layers)
     theta0 = W.vqe_starts(P, n_starts, seed)
     warm = None
     if warm_start:
         free = model.noninteracting()
-        th, warm = free.vqe(theta0, layers, opts)
+        th, warm = (free.sector_vqe if sector else free.vqe)(theta0, layers, opts)
         theta0 = th.cpu().numpy()
         del free
-    th, res = model.vqe(theta0, layers, opts)
+    th, res = (model.sector_vqe if sector else model.vqe)(theta0, layers, opts)
     th = th.cpu().numpy()
     best = int(np.argmin([r["E"] for r in res]))
     out = dict(E=res[best]["E"], theta=th[best], best=best, results=res, warm_results=warm,

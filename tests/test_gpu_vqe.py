@@ -73,3 +73,61 @@ def test_vqe_ten_starts_lockstep_config2(gpu):
     th_w, _ = free.vqe(W.vqe_starts(w.n_params, 10, 0)[:1], w.layers)
     _, res1 = m.vqe(th_w.cpu().numpy(), w.layers)
     assert abs(res1[0]["E"] - res[0]["E"]) <= 1e-6
+
+
+def test_sector_vqe_matches_oracle_driven_run(gpu):
+    """The driver with sector-form evaluations reaches the oracle-driven run's
+    minimum (config 1)."""
+    w = W.config1()
+    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    om = make_model(w.nx, w.ny, **w.kwargs())
+    x0 = W.vqe_starts(w.n_params, 1, seed=3)
+    th, res = m.sector_vqe(x0, w.layers)
+    ref, _ = host_run(om, w.layers, x0[0])
+    say(f"[sector vqe] GPU {res[0]}, oracle-driven {ref}")
+    assert abs(res[0]["E"] - ref["E"]) <= 1e-9
+    E_chk = oc.energy(om, th.cpu().numpy()[0], w.layers)
+    assert abs(E_chk - res[0]["E"]) <= 1e-12 * max(1.0, abs(E_chk))
+
+
+def test_sector_vqe_workflow_config2(gpu):
+    """Three starts with the U = 0 warm start in the sector form: every start
+    converges by the paper's stopping rules, its final point's energy checks
+    out on the full-vector path, it lies above the Lanczos ground energy, and
+    it is the minimum the full-vector driver reaches from the same start.
+    (The two runs' energies and gradients differ by rounding, ~1e-15, enough
+    for hundreds of L-BFGS steps on a flat landscape to end their
+    energy-change stopping rule a few 1e-6 apart: same minimum to 1e-4.)"""
+    w = W.config2(4.0)
+    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    E0 = m.sector_lanczos()["E0"]
+    out_s = vqe.run(m, w.layers, n_starts=3, seed=1, E_ref=E0, sector=True)
+    out_f = vqe.run(m, w.layers, n_starts=3, seed=1, E_ref=E0)
+    say(f"[sector vqe] config 2: sector {[r['E'] for r in out_s['results']]}, "
+        f"full {[r['E'] for r in out_f['results']]}, E0 {E0!r}")
+    for i, (rs, rf) in enumerate(zip(out_s["results"], out_f["results"])):
+        assert rs["why"] in ("energy tolerance", "gradient tolerance")
+        assert abs(rs["E"] - rf["E"]) <= 1e-4
+        E_chk = m.energy(torch.tensor(out_s["thetas"][i], device=gpu)).item()
+        assert abs(E_chk - rs["E"]) <= 1e-12 * max(1.0, abs(E_chk))
+        assert rs["E"] >= E0 - 1e-12
+
+
+def test_sector_vqe_32q_steps(gpu):
+    """The optimiser on the 4x4 periodic U = 8 torus (32 qubits) for a bounded
+    number of iterations: the energy decreases from the start and stays above
+    the sector Lanczos ground energy; the final point checks out."""
+    w = W.config5()
+    m = Hubbard(w.nx, w.ny, **w.kwargs())
+    E0 = m.sector_lanczos(max_iter=600, tol=1e-9)["E0"]
+    x0 = W.vqe_starts(w.n_params, 1, seed=0)
+    th0 = torch.tensor(x0[0], device=gpu)
+    E_start = m.sector_energy_grad(th0)[0].item()
+    th, res = m.sector_vqe(x0, w.layers, {"max_steps": 25})
+    E_end = m.sector_energy_grad(th[0])[0].item()
+    say(f"[sector vqe 32q] E {E_start:.8f} -> {res[0]['E']:.8f} in {res[0]['steps']} steps "
+        f"({res[0]['evals']} evaluations), E0 {E0:.8f}")
+    assert res[0]["steps"] <= 25
+    assert res[0]["E"] < E_start - 1.0
+    assert res[0]["E"] >= E0
+    assert abs(E_end - res[0]["E"]) <= 1e-12 * abs(E_end)
