@@ -1,6 +1,7 @@
 """Graph-form models (hubbard_create_graph) against the oracle: random graphs
 with long-range and non-bipartite bonds, default and custom groups, custom
-start spins, general diagonals, single- and multi-tile schedules."""
+start spins, general diagonals, single- and multi-tile schedules, and the
+sector form's energy and gradient on the same graphs."""
 import sys
 
 import numpy as np
@@ -74,3 +75,7 @@ def test_graph_parity(gpu, case):
     assert abs(E.item() - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
     assert np.max(np.abs(g.cpu().numpy() - g_ref)) <= GRAD_TOL
     assert abs(m.energy(tdev).item() - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    # the sector form on the same graph (the start spins fix N_up, N_dn)
+    Es, gs = m.sector_energy_grad(tdev)
+    assert abs(Es.item() - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert np.max(np.abs(gs.cpu().numpy() - g_ref)) <= GRAD_TOL
