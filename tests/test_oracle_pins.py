@@ -446,3 +446,24 @@ def test_graph_form_of_a_chain_is_the_chain(oracle_lib):
     E1, g1 = oc.energy_grad(m, th, 2)
     E2, g2 = oc.energy_grad(gm, th, 2)
     assert E1 == E2 and np.array_equal(g1, g2)
+
+
+@pytest.mark.parametrize("nx,ny", [(2, 2), (1, 6), (2, 3), (1, 5)])
+def test_noninteracting_bipartite_energy_vanishes(oracle_lib, nx, ny):
+    """Bipartite lattice, checkerboard start, U = V = eps = 0: the sublattice
+    sign change a_i -> (-1)^i a_i negates every hopping term and leaves the
+    start state alone, so it maps the circuit at theta to the circuit at
+    -theta and E(theta) = -E(-theta); E is also even in theta (real start
+    state and H).  Hence E(theta) = 0 and grad = 0 for every theta, whatever
+    the bond disorder (the VQE's U = V = 0 warm start leaves such a start
+    where it is)."""
+    rng = np.random.default_rng(10 * nx + ny)
+    nb = len(make_model(nx, ny, U=0.0).bonds)
+    m = make_model(nx, ny, U=0.0, t=1 + 0.1 * rng.standard_normal(nb))
+    th = rng.uniform(-1.0, 1.0, 3 * m.params_per_layer)
+    E, g = oc.energy_grad(m, th, 3)
+    assert abs(E) <= 1e-13 and np.max(np.abs(g)) <= 1e-13
+    # with U the same angles give a nonzero energy and gradient
+    mu = make_model(nx, ny, U=2.0, t=m.t)
+    Eu, gu = oc.energy_grad(mu, th, 3)
+    assert abs(Eu) > 1e-3 and np.max(np.abs(gu)) > 1e-3
