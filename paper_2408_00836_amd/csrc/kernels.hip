@@ -160,11 +160,6 @@ struct PairCtx {
     double acc[NT];        // reduction of the op (register part of the sign applied)
 };
 
-__device__ __forceinline__ double flip_sign(double x, uint32_t bit)
-{
-    return __longlong_as_double(__double_as_longlong(x) ^ ((long long)bit << 63));
-}
-
 // One register pair (J, JJ) of a hopping term.  Register sets: forward and
 // expectation passes hold NT tiles of one vector (set t = tile t); reverse
 // and H passes hold one tile of two vectors (set 0 = psi, set 1 = lambda or

@@ -1,5 +1,5 @@
-// phase.hpp -- unit phases exp(-i x) for arbitrary real x in fp64 on gfx950,
-// shared by the pass kernels (general diagonal) and the sector kernels.
+// phase.hpp -- unit phases exp(-i x) for arbitrary real x in fp64 on gfx950
+// and sign flips, shared by the pass kernels and the sector kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,6 +7,13 @@
 #include "hubvqe.hpp"
 
 namespace hv {
+
+// x with its sign bit flipped when bit (0 or 1) is set: a Jordan-Wigner sign
+// applied without a select.
+__device__ __forceinline__ double flip_sign(double x, uint32_t bit)
+{
+    return __longlong_as_double(__double_as_longlong(x) ^ ((long long)bit << 63));
+}
 
 // exp(-i x) for the general diagonal: x = k h + r with h = 2 pi / 2^kCisBits
 // (Cody-Waite reduction with a two-part h whose leading part has 36

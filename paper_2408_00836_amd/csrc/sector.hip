@@ -148,12 +148,6 @@ __device__ __forceinline__ void fmac_ip(double &acc, double m, double q)
     asm("v_fma_f64 %0, %1, %2, %0" : "+v"(acc) : "v"(m), "v"(q));
 }
 
-// x with its sign bit flipped when bit (0 or 1) is set.
-__device__ __forceinline__ double flip_sign(double x, uint32_t bit)
-{
-    return __longlong_as_double(__double_as_longlong(x) ^ ((long long)bit << 63));
-}
-
 __device__ __forceinline__ double wave_sum(double x)
 {
     for (int off = 32; off > 0; off >>= 1)
@@ -243,7 +237,7 @@ __device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16
 // the decoded slot addresses are not kept across the barrier; mid() (the
 // next gate's table fetch into the LDS the codes came from) is issued right
 // after the publishing barrier, by when every thread holds its codes.
-template <int RPT, typename G, typename F>
+template <int RPT, int INF, typename G, typename F>
 __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd, double2 *xch,
                                          uint32_t trash, G &&mid, F &&use)
 {
@@ -261,14 +255,25 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
 #pragma unroll
     for (int k = 0; k < rp_of(RPT) / 2; ++k)
         asm volatile("" : "+v"(cd.w[k]));
+    // INF partner values in flight per thread: element j + INF - 1's read is
+    // issued before element j is updated (the other waves hide the rest of
+    // the LDS latency; the register tile keeps its registers)
+    auto partner = [&](int j) __attribute__((always_inline)) {
+        const uint32_t c = cd.get(j);
+        return xch[c != kNone ? ((c & 0x7FFFu) ^ 1u) : trash];
+    };
+    double2 pq[INF];
+#pragma unroll
+    for (int k = 0; k + 1 < INF && k < RPT; ++k)
+        pq[k] = partner(k);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const uint32_t c = cd.get(j);
-        const bool act = c != kNone;
-        const double2 p = xch[act ? ((c & 0x7FFFu) ^ 1u) : trash];
-        use(j, p, act, (c >> 15) & 1u);
-        // one partner value in flight per thread (the other waves hide the
-        // LDS latency): the register tile keeps its registers
+        if (j + INF - 1 < RPT)
+            pq[(j + INF - 1) % INF] = partner(j + INF - 1);
+        if constexpr (INF > 1)
+            __builtin_amdgcn_sched_barrier(0);
+        use(j, pq[j % INF], c != kNone, (c >> 15) & 1u);
         __builtin_amdgcn_sched_barrier(0);
     }
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of mid()'s copies has landed
@@ -307,6 +312,9 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     constexpr int N = RPT;         // elements per thread
     constexpr int kWv = TT / 64;   // waves of the workgroup
     constexpr bool REV = MODE == S_REV;
+    // partner reads in flight per thread in a gate's exchange (H: one, its
+    // two register tiles leave no registers for more)
+    constexpr int kInFlight = MODE == S_HAM ? 1 : 3;
     // column of thread u's element e
     auto elem = [](uint32_t u, int e) -> uint32_t { return u + (uint32_t)(e * TT); };
     extern __shared__ __align__(16) char smem[];
@@ -450,7 +458,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                 ready = (r + (int)gridDim.x < nr || oi + 1 < n_ops) ? op.nxt[REV ? 1 : 0] : -1;
                 const int nxt = ready;
                 // w = sign (active) or 0 (inactive: cos factor 1, no partner term)
-                exchange<RPT>(a, cd, xch, trash, [&]() {
+                exchange<RPT, kInFlight>(a, cd, xch, trash, [&]() {
                     if (nxt >= 0)
                         fetch_codes<TT, RPT>(gcode + kops[nxt].tab, cbuf, tid);
                 }, [&](int j, double2 p, bool act, uint32_t sgn) {
