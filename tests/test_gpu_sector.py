@@ -229,3 +229,67 @@ def test_sector_32q_benchmark_circuit(gpu):
     assert dg <= GRAD_TOL
     assert amp <= AMP_TOL
     assert abs(norm - 1.0) <= 1e-12
+
+
+# Degenerate sectors: a single amplitude (one site; every spin up, where
+# every hop is Pauli-blocked and the energy is the diagonal alone) and
+# one-row / one-column sector matrices (a single electron of one spin),
+# where one layout's rows hold one element and its gates no pair at all.
+# Graph models with explicit start spins, against the sector and full-space
+# oracles; the sector Lanczos against the lowest eigenvalue of the oracle's
+# sector H assembled column by column.
+DEGENERATE = {
+    "one site": (1, [], [0]),
+    "ring4 all up": (4, [(0, 1), (1, 2), (2, 3), (0, 3)], [0, 0, 0, 0]),
+    "5 sites, one down": (5, [(0, 1), (1, 2), (2, 3), (3, 4), (0, 3)], [0, 0, 0, 1, 0]),
+    "6 sites, one up": (6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (0, 5), (1, 4)],
+                        [1, 1, 1, 1, 1, 0]),
+}
+
+
+@pytest.mark.parametrize("key", list(DEGENERATE))
+def test_sector_degenerate_sectors(gpu, key):
+    from oracle.model import make_graph_model
+    n, bonds, spins = DEGENERATE[key]
+    rng = np.random.default_rng(77 + n)
+    nb = len(bonds)
+    kw = dict(t=(1 + 0.2 * rng.standard_normal(nb)) if nb else None, U=3.0,
+              V=rng.uniform(-0.5, 0.5, nb) if nb else None, eps=rng.uniform(-0.5, 0.5, n))
+    om = make_graph_model(n, bonds, site_spin=spins, **kw)
+    m = Hubbard.graph(n, np.asarray(bonds, dtype=np.int32).reshape(-1, 2), site_spin=spins,
+                      **kw)
+    L = 2
+    th_h = rng.uniform(-np.pi / 8, np.pi / 8, L * om.params_per_layer)
+    th = torch.tensor(th_h, dtype=torch.float64, device=gpu)
+    nu, nd = m.sector_dims()
+    dim = osec.dim(om)
+    say(f"[sector degenerate] {key}: dims {nu}x{nd}")
+    assert nu * nd == dim
+    psi = m.sector_state(th)
+    ref = osec.ansatz(om, th_h, L)
+    amp = float(np.max(np.abs(psi.cpu().numpy() - ref)))
+    x = rng.standard_normal(dim) + 1j * rng.standard_normal(dim)
+    hx = m.sector_apply_h(torch.tensor(x, device=gpu)).cpu().numpy()
+    href = osec.ham_apply(om, x)
+    herr = float(np.max(np.abs(hx - href)) / max(1.0, np.max(np.abs(href))))
+    E, g = m.sector_energy_grad(th)
+    E_ref, g_ref = oc.energy_grad(om, th_h, L)
+    dE = abs(E.item() - E_ref)
+    dg = float(np.max(np.abs(g.cpu().numpy() - g_ref)))
+    Hs = np.stack([osec.ham_apply(om, np.eye(dim, dtype=np.complex128)[:, c])
+                   for c in range(dim)], axis=1)
+    e0 = float(np.linalg.eigvalsh(0.5 * (Hs + Hs.conj().T))[0])
+    lz = m.sector_lanczos()
+    say(f"[sector degenerate] {key}: amp {amp:.2e}, H {herr:.2e}, dE {dE:.2e}, dg {dg:.2e}, "
+        f"E0 {lz['E0']:.12f} (ED {e0:.12f}, {lz['iters']} steps)")
+    assert amp <= AMP_TOL
+    assert herr <= AMP_TOL
+    assert dE <= e_tol(E_ref)
+    assert dg <= GRAD_TOL
+    assert abs(lz["E0"] - e0) <= 1e-9 * max(1.0, abs(e0))
+    if dim == 1:   # a single amplitude: a phase only, the energy is the diagonal
+        assert abs(abs(ref[0]) - 1.0) <= 1e-12
+        assert float(np.max(np.abs(g_ref))) <= 1e-12
+    E2, g2 = m.energy_grad(th)
+    assert abs(E.item() - E2.item()) <= e_tol(E_ref)
+    assert float(np.max(np.abs(g.cpu().numpy() - g2.cpu().numpy()))) <= GRAD_TOL
