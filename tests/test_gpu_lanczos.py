@@ -84,6 +84,9 @@ def test_vqe_state_fidelity_and_bound(gpu):
     F_ref = abs(np.vdot(x, vref[:, 0])) ** 2
     assert abs(F - F_ref) <= 1e-10
     assert m.energy(th).item() >= r["E0"] - 1e-12
+    # the circuit keeps the checkerboard start's total-spin weights and the
+    # ground state is a singlet: F <= the start's singlet weight 1 / (N/2 + 1)
+    assert F <= 1.0 / (w.nx * w.ny // 2 + 1) + 1e-12
 
 
 def test_overlap_matches_oracle(gpu):

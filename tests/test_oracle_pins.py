@@ -467,3 +467,49 @@ def test_noninteracting_bipartite_energy_vanishes(oracle_lib, nx, ny):
     mu = make_model(nx, ny, U=2.0, t=m.t)
     Eu, gu = oc.energy_grad(mu, th, 3)
     assert abs(Eu) > 1e-3 and np.max(np.abs(gu)) > 1e-3
+
+
+@pytest.mark.parametrize("nx,ny,px", [(2, 2, 0), (1, 4, 0), (2, 3, 0), (1, 6, 1)])
+def test_circuit_keeps_the_start_states_total_spin_content(oracle_lib, nx, ny, px):
+    """Every generator of the circuit (hopping of both spins with one t per
+    bond, U n_up n_dn, V n_i n_j, eps n_i) commutes with the total spin S^2,
+    so the circuit state keeps the checkerboard start's weights in each
+    total-spin sector.  For N singly occupied sites with alternating spins
+    the singlet weight is 1 / (N/2 + 1) (the S = 0 component of a Neel
+    product state), so it bounds the fidelity of the circuit state with a
+    singlet ground state.  S^2 = S^- S^+ + S_z^2 + S_z is built here from the
+    Kronecker-product operators, independently of the C loops that produce
+    the state; a hopping or Jordan-Wigner sign that differs between the
+    spins breaks the invariance."""
+    rng = np.random.default_rng(100 * nx + ny)
+    nb = len(make_model(nx, ny, periodic_y=bool(px)).bonds)
+    m = make_model(nx, ny, periodic_y=bool(px), U=3.0, t=1 + 0.2 * rng.standard_normal(nb),
+                   V=rng.uniform(-0.5, 0.5, nb), eps=rng.uniform(-0.5, 0.5, nx * ny))
+    a, ad, num = od.operators(m)
+    up = [m.qubit(i, 0) for i in range(m.nsites)]
+    dn = [m.qubit(i, 1) for i in range(m.nsites)]
+    Sp = sum(ad[u] @ a[d] for u, d in zip(up, dn))
+    Sz = 0.5 * sum(num[u] - num[d] for u, d in zip(up, dn))
+    S2 = (Sp.conj().T @ Sp + Sz @ Sz + Sz).toarray()
+    b0 = m.neel_index()
+    nu, nd = sector_of(m, b0)
+    idx = [b for b in range(1 << m.nqubits) if sector_of(m, b) == (nu, nd)]
+    w, v = np.linalg.eigh(S2[np.ix_(idx, idx)])
+    S = np.rint((-1.0 + np.sqrt(1.0 + 4.0 * np.clip(w, 0.0, None))) / 2.0)
+    assert np.allclose(S * (S + 1.0), w, atol=1e-9)
+
+    def weights(x):
+        c = np.abs(v.conj().T @ x[idx]) ** 2
+        return np.array([c[S == s].sum() for s in range(m.nsites // 2 + 1)])
+
+    x0 = np.zeros(1 << m.nqubits, dtype=np.complex128)
+    x0[b0] = 1.0
+    w0 = weights(x0)
+    assert abs(w0[0] - 1.0 / (m.nsites // 2 + 1)) <= 1e-12
+    th = rng.uniform(-1.0, 1.0, 3 * m.params_per_layer)
+    x = oc.ansatz(m, th, 3)
+    assert np.max(np.abs(weights(x) - w0)) <= 1e-12
+    # the ground state is a singlet: the circuit's fidelity with it is bounded
+    E0, g0 = np.linalg.eigh(oc.ham_matrix(m, idx))
+    assert abs(np.vdot(g0[:, 0], v[:, S == 0] @ (v[:, S == 0].conj().T @ g0[:, 0]))) >= 1 - 1e-9
+    assert abs(np.vdot(g0[:, 0], x[idx])) ** 2 <= w0[0] + 1e-12
