@@ -64,7 +64,7 @@ constexpr int kMaxRed = 16;               // reduction slots of one row pass
 constexpr int kGrid = 1024;               // at most this many row workgroups
 constexpr uint32_t kNone = 0xFFFFu;       // code of an element a gate leaves alone
 constexpr int kMaxRows = 13 * kT;         // longest row: C(16, 8) = 12870
-constexpr int kTrash = 64;                // zeroed LDS slots (one per lane) that inactive elements read
+constexpr int kTrash = 1;                 // the zeroed LDS slot that inactive elements read
 
 // Register tile of a row of n elements over kT threads: rpt_of(n) elements
 // per thread (element t + j kT in thread t).  A gate's code table holds
@@ -228,9 +228,11 @@ __device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16
 // One gate's exchange of vector x through the pair slots: every active
 // element publishes its value to its slot, then every element calls use(j,
 // partner, active, sign bit) (the Jordan-Wigner sign (-1)^bit; an inactive
-// element's "partner" is its lane's trash slot, which holds zero, so that
-// every term with the partner vanishes for it whatever the sign): the
-// reads and updates are branch-free.  (Inactive elements writing to their
+// element's "partner" is the trash slot, which holds zero, so that every
+// term with the partner vanishes for it whatever the sign): the reads and
+// updates are branch-free.  All inactive lanes read the one trash slot, a
+// broadcast that takes no LDS banks from the active lanes' reads (a slot
+// per lane cost 4 % of sector H|psi>).  (Inactive elements writing to
 // trash slots too, to make the writes branch-free as well, cost 4 % of an
 // evaluation in LDS traffic.)
 // The codes are in registers: they are made opaque before each half, so that
@@ -318,13 +320,13 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     // column of thread u's element e
     auto elem = [](uint32_t u, int e) -> uint32_t { return u + (uint32_t)(e * TT); };
     extern __shared__ __align__(16) char smem[];
-    double2 *xch = (double2 *)smem;   // pair slots, then kTrash trash slots
+    double2 *xch = (double2 *)smem;   // pair slots, then the trash slot
     double *acc = (double *)(smem + (size_t)(xch_elems + kTrash) * 16);   // kMaxRed x kWaves
     double2 *dloc = (double2 *)(acc + kMaxRed * kWaves);   // the pass's U-count phase table
     double2 *cis = dloc + kDiagTab;                                       // unit phases
     uint16_t *cbuf = (uint16_t *)(cis + (1u << kCisBits));                // the next gate's codes
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t trash = (uint32_t)(xch_elems + lane);
+    const uint32_t trash = (uint32_t)xch_elems;
     const uint32_t n = (uint32_t)kM->n[col];
     const int nr = kM->n[1 - col];
     // the tables' pointers come from memory: global address space, so that
