@@ -62,9 +62,8 @@ constexpr int kT = 1024;                  // threads of a row workgroup
 constexpr int kWaves = kT / 64;
 constexpr int kMaxRed = 16;               // reduction slots of one row pass
 constexpr int kGrid = 1024;               // at most this many row workgroups
-constexpr uint32_t kNone = 0xFFFFu;       // code of an element a gate leaves alone
 constexpr int kMaxRows = 13 * kT;         // longest row: C(16, 8) = 12870
-constexpr int kTrash = 1;                 // the zeroed LDS slot that inactive elements read
+constexpr int kZero = 16;                 // zeroed LDS slots (one per bank group) read by inactive elements
 
 // Register tile of a row of n elements over kT threads: rpt_of(n) elements
 // per thread (element t + j kT in thread t).  A gate's code table holds
@@ -107,7 +106,7 @@ struct SecModel {
     double U;
     const uint32_t *pat[2];    // site pattern of each rank
     const double *base[2];     // sum_i eps_i p_i + sum_b V_b p_i p_j of each rank
-    const uint16_t *code;      // per gate: pair slot | sign << 15 (kNone: not active)
+    const uint16_t *code;      // per gate: LDS slot | sign << 15 (a zero slot: not active)
                                // of every column, at code_index (kT rp_of(rpt) entries)
     int32_t vi[kMaxBonds], vj[kMaxBonds];
     double vV[kMaxBonds];
@@ -155,8 +154,9 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-// A thread's gate codes, two 16-bit codes per register (pair slot |
-// sign << 15; kNone: the element is left alone).
+// A thread's gate codes, two 16-bit codes per register (LDS slot | sign <<
+// 15; an element the gate leaves alone has a zero slot, at or above the
+// first zero slot nz, with sign 0).
 template <int RPT>
 struct Codes {
     uint32_t w[rp_of(RPT) / 2];
@@ -178,7 +178,7 @@ typedef const __attribute__((address_space(4))) uint32_t ku32;
 typedef const __attribute__((address_space(4))) double kf64;
 
 // The gate's codes of thread t, from the LDS copy of its table: one load
-// per chunk (codes past the row end are kNone in the table).
+// per chunk (codes past the row end name zero slots in the table).
 template <int RPT>
 __device__ __forceinline__ Codes<RPT> load_codes(const uint16_t *cb, uint32_t t)
 {
@@ -227,30 +227,32 @@ __device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16
 
 // One gate's exchange of vector x through the pair slots: every active
 // element publishes its value to its slot, then every element calls use(j,
-// partner, active, sign bit) (the Jordan-Wigner sign (-1)^bit; an inactive
-// element's "partner" is the trash slot, which holds zero, so that every
-// term with the partner vanishes for it whatever the sign): the reads and
-// updates are branch-free.  All inactive lanes read the one trash slot, a
-// broadcast that takes no LDS banks from the active lanes' reads (a slot
-// per lane cost 4 % of sector H|psi>).  (Inactive elements writing to
-// trash slots too, to make the writes branch-free as well, cost 4 % of an
-// evaluation in LDS traffic.)
+// partner, active, sign bit) with the partner read from its slot XOR 1 (the
+// Jordan-Wigner sign (-1)^bit).  An inactive element's code names one of
+// the kZero zero slots, so its "partner" is zero and every term with it
+// vanishes whatever the sign: the reads and updates are branch-free and
+// take no select.  The zero slot of the inactive lanes of a group of 16
+// lanes is chosen by the host in a bank group that none of the group's
+// active reads uses (the lanes of a 16-byte LDS access are served in such
+// groups; all of the group's inactive lanes read the same slot, a
+// broadcast).  (Inactive elements writing to zero slots too, to make the
+// writes branch-free as well, cost 4 % of an evaluation in LDS traffic.)
 // The codes are in registers: they are made opaque before each half, so that
 // the decoded slot addresses are not kept across the barrier; mid() (the
 // next gate's table fetch into the LDS the codes came from) is issued right
 // after the publishing barrier, by when every thread holds its codes.
 template <int RPT, int INF, typename G, typename F>
 __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd, double2 *xch,
-                                         uint32_t trash, G &&mid, F &&use)
+                                         uint32_t nz, G &&mid, F &&use)
 {
 #pragma unroll
     for (int k = 0; k < rp_of(RPT) / 2; ++k)
         asm volatile("" : "+v"(cd.w[k]));
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-        const uint32_t c = cd.get(j);
-        if (c != kNone)
-            xch[c & 0x7FFFu] = x[j];
+        const uint32_t sl = cd.get(j) & 0x7FFFu;
+        if (sl < nz)
+            xch[sl] = x[j];
     }
     __syncthreads();
     mid();
@@ -261,8 +263,7 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
     // issued before element j is updated (the other waves hide the rest of
     // the LDS latency; the register tile keeps its registers)
     auto partner = [&](int j) __attribute__((always_inline)) {
-        const uint32_t c = cd.get(j);
-        return xch[c != kNone ? ((c & 0x7FFFu) ^ 1u) : trash];
+        return xch[(cd.get(j) & 0x7FFFu) ^ 1u];
     };
     double2 pq[INF];
 #pragma unroll
@@ -275,7 +276,7 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
             pq[(j + INF - 1) % INF] = partner(j + INF - 1);
         if constexpr (INF > 1)
             __builtin_amdgcn_sched_barrier(0);
-        use(j, pq[j % INF], c != kNone, (c >> 15) & 1u);
+        use(j, pq[j % INF], ((c & 0x7FFFu) ^ 1u) < nz, (c >> 15) & 1u);
         __builtin_amdgcn_sched_barrier(0);
     }
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of mid()'s copies has landed
@@ -320,13 +321,12 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     // column of thread u's element e
     auto elem = [](uint32_t u, int e) -> uint32_t { return u + (uint32_t)(e * TT); };
     extern __shared__ __align__(16) char smem[];
-    double2 *xch = (double2 *)smem;   // pair slots, then the trash slot
-    double *acc = (double *)(smem + (size_t)(xch_elems + kTrash) * 16);   // kMaxRed x kWaves
+    double2 *xch = (double2 *)smem;   // pair slots below xch_elems, then kZero zero slots
+    double *acc = (double *)(smem + (size_t)(xch_elems + kZero) * 16);   // kMaxRed x kWaves
     double2 *dloc = (double2 *)(acc + kMaxRed * kWaves);   // the pass's U-count phase table
     double2 *cis = dloc + kDiagTab;                                       // unit phases
     uint16_t *cbuf = (uint16_t *)(cis + (1u << kCisBits));                // the next gate's codes
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t trash = (uint32_t)xch_elems;
     const uint32_t n = (uint32_t)kM->n[col];
     const int nr = kM->n[1 - col];
     // the tables' pointers come from memory: global address space, so that
@@ -339,7 +339,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     const kf64 *__restrict__ rbase = (const kf64 *)kM->base[1 - col];
     for (int i = tid; i < kMaxRed * kWv; i += TT)
         acc[i] = 0.0;
-    for (int i = tid; i < kTrash; i += TT)   // read by inactive elements, never written
+    for (int i = tid; i < kZero; i += TT)   // read by inactive elements, never written
         xch[xch_elems + i] = make_double2(0.0, 0.0);
     if constexpr (MODE != S_HAM && GEN)
         build_cis(cis, tid, TT);
@@ -460,7 +460,7 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                 ready = (r + (int)gridDim.x < nr || oi + 1 < n_ops) ? op.nxt[REV ? 1 : 0] : -1;
                 const int nxt = ready;
                 // w = sign (active) or 0 (inactive: cos factor 1, no partner term)
-                exchange<RPT, kInFlight>(a, cd, xch, trash, [&]() {
+                exchange<RPT, kInFlight>(a, cd, xch, (uint32_t)xch_elems, [&]() {
                     if (nxt >= 0)
                         fetch_codes<TT, RPT>(gcode + kops[nxt].tab, cbuf, tid);
                 }, [&](int j, double2 p, bool act, uint32_t sgn) {
@@ -683,7 +683,7 @@ struct RowPass {
 // Sector tables of one model on one device.
 struct Tables {
     int n[2] = {0, 0};
-    int xch = 0;                  // most active elements of any gate (LDS slots)
+    int xch = 0;                  // first zero slot: above every gate's pair slots, a multiple of 16
     std::vector<int> tab[2];      // per bond: offset of its spin-s code table
     size_t b0_pos = 0;            // position of |b0> in layout A
     bool general = false;         // eps or V terms in the diagonal
@@ -748,13 +748,13 @@ hipError_t upload(void **dst, const void *src, size_t bytes)
 
 int popc(uint32_t x) { return __builtin_popcount(x); }
 
-// LDS of a row workgroup: the pair and trash slots, the reduction slots, the
+// LDS of a row workgroup: the pair and zero slots, the reduction slots, the
 // U-count phase table, the unit phases, one gate's code table (of the longer
 // row).
 size_t lds_bytes(const Tables &T)
 {
     const int rp = std::max(rp_of(rpt_of(T.n[0])), rp_of(rpt_of(T.n[1])));
-    return (size_t)(T.xch + kTrash) * 16 + kMaxRed * kWaves * 8 + kDiagTab * 16 +
+    return (size_t)(T.xch + kZero) * 16 + kMaxRed * kWaves * 8 + kDiagTab * 16 +
            (1u << kCisBits) * 16 + (size_t)kT * rp * 2;
 }
 
@@ -792,38 +792,82 @@ hubbard_status build_tables(const Model &m, Tables &T)
     T.b0_pos = (size_t)rank_of[1][dn0] * T.n[0] + rank_of[0][up0];
     // per bond and spin: pair slots (pair p at slots 2p, 2p+1) and the
     // Jordan-Wigner sign of the sites strictly between the bond's ends, at
-    // the rank's entry of the register-tile layout (kNone elsewhere)
+    // the rank's entry of the register-tile layout; every other entry (the
+    // bond's inactive elements and the tile's padding) names a zero slot
+    auto active = [&](int s, int k, int r, int *r2) {
+        const int i = std::min(m.bi[k], m.bj[k]), j = std::max(m.bi[k], m.bj[k]);
+        const uint32_t p = pat[s][r];
+        if (!(((p >> i) ^ (p >> j)) & 1u))
+            return false;
+        *r2 = rank_of[s][p ^ ((1u << i) | (1u << j))];
+        return true;
+    };
+    int most = 1;   // most pairs of any gate
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < m.nb; ++k) {
+            int pairs = 0, r2 = 0;
+            for (int r = 0; r < T.n[s]; ++r)
+                pairs += active(s, k, r, &r2) && r2 > r;
+            most = std::max(most, pairs);
+        }
+    T.xch = (2 * most + 15) & ~15;
+    if (T.xch + kZero > 0x7FFF || lds_bytes(T) > 160 * 1024)
+        return fail(HUBBARD_ERR_ARG, "sector gate pairs do not fit the workgroup's LDS");
     std::vector<uint16_t> codes;
-    T.xch = 2;
     for (int s = 0; s < 2; ++s) {
         T.tab[s].assign(m.nb, 0);
         const int R = rpt_of(T.n[s]);
         auto entry = [&](int r) { return (size_t)code_index(R, r % kT, r / kT); };
         for (int k = 0; k < m.nb; ++k) {
             const int i = std::min(m.bi[k], m.bj[k]), j = std::max(m.bi[k], m.bj[k]);
-            const uint32_t mask = (1u << i) | (1u << j);
             const uint32_t between = ((1u << j) - 1u) & ~((2u << i) - 1u);
             T.tab[s][k] = (int)codes.size();
             const size_t at = codes.size();
-            codes.resize(at + (size_t)kT * rp_of(R), (uint16_t)kNone);
+            codes.resize(at + (size_t)kT * rp_of(R), (uint16_t)T.xch);
+            std::vector<int> slot((size_t)R * kT, -1);   // per element (rank): pair slot
             uint32_t pairs = 0;
             for (int r = 0; r < T.n[s]; ++r) {
-                const uint32_t p = pat[s][r];
-                if (((p >> i) ^ (p >> j)) & 1u) {
-                    const int r2 = rank_of[s][p ^ mask];
-                    if (r2 > r) {
-                        const uint32_t sg = (uint32_t)(popc(p & between) & 1) << 15;
-                        codes[at + entry(r)] = (uint16_t)((2 * pairs) | sg);
-                        codes[at + entry(r2)] = (uint16_t)((2 * pairs + 1) | sg);
-                        ++pairs;
-                    }
+                int r2 = 0;
+                if (active(s, k, r, &r2) && r2 > r) {
+                    const uint32_t sg = (uint32_t)(popc(pat[s][r] & between) & 1) << 15;
+                    slot[r] = (int)(2 * pairs);
+                    slot[r2] = (int)(2 * pairs + 1);
+                    codes[at + entry(r)] = (uint16_t)(slot[r] | sg);
+                    codes[at + entry(r2)] = (uint16_t)(slot[r2] | sg);
+                    ++pairs;
                 }
             }
-            T.xch = std::max(T.xch, (int)(2 * pairs));
+            // per group of 16 threads and register (the lanes of one 16-byte
+            // LDS access that share the banks): the zero slot its inactive
+            // elements read, one per half of the group, in a bank group that
+            // the group's active reads leave free (slot mod 16, and slot mod 8
+            // within the half: 64 banks serve 16 lanes at a time, 32 banks 8)
+            for (int e0 = 0; e0 < R * kT; e0 += 16) {
+                uint32_t taken = 0, u8[2] = {0, 0};
+                for (int e = e0; e < e0 + 16; ++e)
+                    if (slot[e] >= 0) {
+                        const int q = (slot[e] ^ 1) & 15;
+                        taken |= 1u << q;
+                        u8[(e - e0) / 8] |= 1u << (q & 7);
+                    }
+                for (int h = 0; h < 2; ++h) {
+                    int best = 0, best_miss = 1 << 30;
+                    for (int q = 0; q < 16; ++q) {
+                        const int miss = 4 * ((taken >> q) & 1) + ((u8[h] >> (q & 7)) & 1);
+                        if (miss < best_miss) {
+                            best_miss = miss;
+                            best = q;
+                        }
+                    }
+                    taken |= 1u << best;
+                    // read slot T.xch + best (T.xch is a multiple of 16)
+                    for (int e = e0 + 8 * h; e < e0 + 8 * h + 8; ++e)
+                        if (slot[e] < 0)
+                            codes[at + entry(e)] = (uint16_t)((T.xch + best) ^ 1);
+                }
+            }
         }
     }
-    if (T.xch > 0x7FFF || lds_bytes(T) > 160 * 1024)
-        return fail(HUBBARD_ERR_ARG, "sector gate pairs do not fit the workgroup's LDS");
     T.general = m.general;
     T.U = m.U;
     SecModel sm;
