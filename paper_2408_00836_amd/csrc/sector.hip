@@ -239,8 +239,10 @@ __device__ __forceinline__ void fetch_codes(const gu16 *__restrict__ src, uint16
 // writes branch-free as well, cost 4 % of an evaluation in LDS traffic.)
 // The codes are in registers: they are made opaque before each half, so that
 // the decoded slot addresses are not kept across the barrier; mid() (the
-// next gate's table fetch into the LDS the codes came from) is issued right
-// after the publishing barrier, by when every thread holds its codes.
+// next gate's table fetch into the LDS the codes came from) is issued after
+// the reads, before the closing barrier (every thread holds its codes since
+// the publishing barrier; issued right after that barrier, the copies
+// overlapped the reads and the gate took longer).
 template <int RPT, int INF, typename G, typename F>
 __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd, double2 *xch,
                                          uint32_t nz, G &&mid, F &&use)
@@ -255,7 +257,6 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
             xch[sl] = x[j];
     }
     __syncthreads();
-    mid();
 #pragma unroll
     for (int k = 0; k < rp_of(RPT) / 2; ++k)
         asm volatile("" : "+v"(cd.w[k]));
@@ -279,6 +280,7 @@ __device__ __forceinline__ void exchange(const double2 (&x)[RPT], Codes<RPT> cd,
         use(j, pq[j % INF], ((c & 0x7FFFu) ^ 1u) < nz, (c >> 15) & 1u);
         __builtin_amdgcn_sched_barrier(0);
     }
+    mid();
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of mid()'s copies has landed
     __syncthreads();
 }
@@ -454,9 +456,8 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     __syncthreads();
                 }
                 const Codes<RPT> cd = load_codes<RPT>(cbuf, t);
-                // the next hop's codes arrive in cbuf while this one is applied
-                // (issued after the exchange's first barrier, by when every
-                // thread has its codes in registers)
+                // the next hop's codes are copied into cbuf at the end of this
+                // one's exchange (every thread has its codes in registers)
                 ready = (r + (int)gridDim.x < nr || oi + 1 < n_ops) ? op.nxt[REV ? 1 : 0] : -1;
                 const int nxt = ready;
                 // w = sign (active) or 0 (inactive: cos factor 1, no partner term)
