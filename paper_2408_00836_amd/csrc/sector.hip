@@ -204,6 +204,24 @@ __device__ __forceinline__ Codes<RPT> load_codes(const uint16_t *cb, uint32_t t)
     return c;
 }
 
+// The gate's codes of thread t straight from its table in global memory
+// (the same chunks as load_codes: a wave's loads are contiguous).
+template <int RPT>
+__device__ __forceinline__ Codes<RPT> load_codes_g(const gu16 *__restrict__ src, uint32_t t)
+{
+    constexpr int CW = cw_of(RPT), NCH = rp_of(RPT) / CW;
+    Codes<RPT> c;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        // CW / 2 adjacent dwords: one vector load
+        const gu32 *q = (const gu32 *)(src + ((size_t)ch * kT + t) * CW);
+#pragma unroll
+        for (int k = 0; k < (CW + 1) / 2; ++k)
+            c.w[ch * ((CW + 1) / 2) + k] = q[k];
+    }
+    return c;
+}
+
 // Asynchronous copy of a gate's code table (kT rp_of(RPT) 16-bit entries)
 // from global memory into LDS, a dword per lane and round, without
 // registers; complete for the issuing wave after its vmcnt wait.
@@ -320,6 +338,10 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
     // partner reads in flight per thread in a gate's exchange (H: one, its
     // two register tiles leave no registers for more)
     constexpr int kInFlight = MODE == S_HAM ? 1 : 3;
+    // gate codes: forward and reverse passes load the next gate's codes from
+    // global memory into registers while a gate is applied; H (no registers
+    // to spare) copies them into LDS (cbuf)
+    constexpr bool RC = MODE != S_HAM;
     // column of thread u's element e
     auto elem = [](uint32_t u, int e) -> uint32_t { return u + (uint32_t)(e * TT); };
     extern __shared__ __align__(16) char smem[];
@@ -368,9 +390,14 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
         if (kops[io].kind == SOP_HOP)
             ready = io;
     }
+    Codes<RPT> pre;   // RC: the codes of op `ready`
     if (ready >= 0) {
-        fetch_codes<TT, RPT>(gcode + kops[ready].tab, cbuf, tid);
-        __builtin_amdgcn_s_waitcnt(0);
+        if constexpr (RC) {
+            pre = load_codes_g<RPT>(gcode + kops[ready].tab, (uint32_t)tid);
+        } else {
+            fetch_codes<TT, RPT>(gcode + kops[ready].tab, cbuf, tid);
+            __builtin_amdgcn_s_waitcnt(0);
+        }
     }
     __syncthreads();
     double eacc = 0.0;
@@ -450,19 +477,31 @@ k_sec_rows(const SecOp *__restrict__ ops, int n_ops, int col, int n_red,
                     sn = REV ? -kang[io].y : kang[io].y;   // un-apply: sin -> -sin
                 }
                 const double mt = -op.t;
-                if (ready != io) {   // not prefetched (the op list's nxt links are broken)
-                    fetch_codes<TT, RPT>(gcode + op.tab, cbuf, tid);
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __syncthreads();
+                Codes<RPT> cd;
+                if constexpr (RC) {
+                    if (ready != io)   // not prefetched (the op list's nxt links are broken)
+                        pre = load_codes_g<RPT>(gcode + op.tab, t);
+                    cd = pre;
+                } else {
+                    if (ready != io) {
+                        fetch_codes<TT, RPT>(gcode + op.tab, cbuf, tid);
+                        __builtin_amdgcn_s_waitcnt(0);
+                        __syncthreads();
+                    }
+                    cd = load_codes<RPT>(cbuf, t);
                 }
-                const Codes<RPT> cd = load_codes<RPT>(cbuf, t);
-                // the next hop's codes are copied into cbuf at the end of this
-                // one's exchange (every thread has its codes in registers)
+                // the next hop's codes: loaded into registers now (RC), or
+                // copied into cbuf at the end of this one's exchange (every
+                // thread has its codes in registers by then)
                 ready = (r + (int)gridDim.x < nr || oi + 1 < n_ops) ? op.nxt[REV ? 1 : 0] : -1;
                 const int nxt = ready;
+                if constexpr (RC) {
+                    if (nxt >= 0)
+                        pre = load_codes_g<RPT>(gcode + kops[nxt].tab, t);
+                }
                 // w = sign (active) or 0 (inactive: cos factor 1, no partner term)
                 exchange<RPT, kInFlight>(a, cd, xch, (uint32_t)xch_elems, [&]() {
-                    if (nxt >= 0)
+                    if (!RC && nxt >= 0)
                         fetch_codes<TT, RPT>(gcode + kops[nxt].tab, cbuf, tid);
                 }, [&](int j, double2 p, bool act, uint32_t sgn) {
                     // s (-t) and s sn by a flip of the sign bit (p = 0 when
