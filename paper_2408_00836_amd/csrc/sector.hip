@@ -147,11 +147,34 @@ __device__ __forceinline__ void fmac_ip(double &acc, double m, double q)
     asm("v_fma_f64 %0, %1, %2, %0" : "+v"(acc) : "v"(m), "v"(q));
 }
 
+// x from another lane of the same 16-lane row (DPP control CTRL), both
+// 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double row_dpp(double y)
+{
+    const long long b = __double_as_longlong(y);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane_value(double y, int l)
+{
+    const long long b = __double_as_longlong(y);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of x over the wave, the same value in every lane: each 16-lane row
+// summed by lane permutations (no LDS traffic), then the four rows' sums.
 __device__ __forceinline__ double wave_sum(double x)
 {
-    for (int off = 32; off > 0; off >>= 1)
-        x += __shfl_xor(x, off);
-    return x;
+    x += row_dpp<0xB1>(x);    // quad_perm [1,0,3,2]: pairs
+    x += row_dpp<0x4E>(x);    // quad_perm [2,3,0,1]: quads
+    x += row_dpp<0x141>(x);   // row_half_mirror: the other quad of the half row
+    x += row_dpp<0x140>(x);   // row_mirror: the other half of the row
+    return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
 }
 
 // A thread's gate codes, two 16-bit codes per register (LDS slot | sign <<
