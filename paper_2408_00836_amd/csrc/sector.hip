@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -811,6 +812,52 @@ hipError_t upload(void **dst, const void *src, size_t bytes)
 
 int popc(uint32_t x) { return __builtin_popcount(x); }
 
+// LDS slots of a gate's pairs, chosen so that the exchange's LDS accesses
+// are free of bank conflicts.  Pair q takes the slots 2p and 2p + 1 for some
+// p, in either order (an element reads its partner at its own slot XOR 1),
+// and p and the order are free.  On this GPU a wave's 16-byte LDS write is
+// served 8 lanes per cycle (32 banks of 4 bytes: slots equal modulo 8
+// conflict) and a 16-byte read 16 lanes per cycle (64 banks: modulo 16).
+// An element e (thread e mod kT, register e / kT) writes its slot s and reads
+// s XOR 1, so a pair with lower slot residue r (mod 16) puts r (mod 8) into
+// e1's write group, r ^ 1 (mod 8) into e2's, r ^ 1 into e1's read group and r
+// into e2's.  Greedy over the pairs in rank order: the residue that adds no
+// conflict (else the fewest), then the least used class p mod 8 (the slots
+// stay dense).  Returns the slots used (2 + 2 max p).
+int pair_slots(const std::vector<std::array<int, 2>> &prs, int rpt, std::vector<int> &slot)
+{
+    const int groups = rpt * kT / 8;
+    std::vector<uint8_t> w8((size_t)groups, 0);        // write residues (mod 8) per 8 lanes
+    std::vector<uint16_t> r16((size_t)groups / 2, 0);  // read residues (mod 16) per 16 lanes
+    auto g8 = [](int e) { return (e / kT) * (kT / 8) + (e % kT) / 8; };
+    int count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int top = -1;
+    slot.assign(2 * prs.size(), 0);
+    for (size_t q = 0; q < prs.size(); ++q) {
+        const int a8 = g8(prs[q][0]), b8 = g8(prs[q][1]), a16 = a8 / 2, b16 = b8 / 2;
+        int best = 0, best_score = 1 << 30;
+        for (int r = 0; r < 16; ++r) {
+            const int r2 = r ^ 1;
+            const int miss = ((w8[a8] >> (r & 7)) & 1) + ((w8[b8] >> (r2 & 7)) & 1) +
+                             ((r16[a16] >> r2) & 1) + ((r16[b16] >> r) & 1);
+            const int score = miss * (1 << 20) + count[r >> 1];
+            if (score < best_score) {
+                best_score = score;
+                best = r;
+            }
+        }
+        const int cls = best >> 1, p = cls + 8 * count[cls]++;
+        top = std::max(top, p);
+        slot[2 * q] = 2 * p + (best & 1);
+        slot[2 * q + 1] = 2 * p + 1 - (best & 1);
+        w8[a8] |= (uint8_t)(1u << (best & 7));
+        w8[b8] |= (uint8_t)(1u << ((best ^ 1) & 7));
+        r16[a16] |= (uint16_t)(1u << (best ^ 1));
+        r16[b16] |= (uint16_t)(1u << best);
+    }
+    return 2 * top + 2;
+}
+
 // LDS of a row workgroup: the pair and zero slots, the reduction slots, the
 // U-count phase table, the unit phases, one gate's code table (of the longer
 // row).
@@ -853,27 +900,39 @@ hubbard_status build_tables(const Model &m, Tables &T)
         return fail(HUBBARD_ERR_ARG, "sector rows longer than 13 x 1024");
     const uint32_t up0 = (uint32_t)m.neel & smask, dn0 = (uint32_t)(m.neel >> ns) & smask;
     T.b0_pos = (size_t)rank_of[1][dn0] * T.n[0] + rank_of[0][up0];
-    // per bond and spin: pair slots (pair p at slots 2p, 2p+1) and the
-    // Jordan-Wigner sign of the sites strictly between the bond's ends, at
-    // the rank's entry of the register-tile layout; every other entry (the
-    // bond's inactive elements and the tile's padding) names a zero slot
-    auto active = [&](int s, int k, int r, int *r2) {
-        const int i = std::min(m.bi[k], m.bj[k]), j = std::max(m.bi[k], m.bj[k]);
-        const uint32_t p = pat[s][r];
-        if (!(((p >> i) ^ (p >> j)) & 1u))
-            return false;
-        *r2 = rank_of[s][p ^ ((1u << i) | (1u << j))];
-        return true;
+    // per bond and spin: pair slots and the Jordan-Wigner sign of the sites
+    // strictly between the bond's ends, at the rank's entry of the
+    // register-tile layout; every other entry (the bond's inactive elements
+    // and the tile's padding) names a zero slot
+    struct Gate {
+        std::vector<std::array<int, 2>> prs;   // (lower, upper) rank, in rank order
+        std::vector<uint32_t> sgn;
+        std::vector<int> slot;                 // per pair: lower's, upper's slot
     };
-    int most = 1;   // most pairs of any gate
-    for (int s = 0; s < 2; ++s)
+    std::vector<Gate> gates[2];
+    int used = 2;
+    for (int s = 0; s < 2; ++s) {
+        const int R = rpt_of(T.n[s]);
+        gates[s].resize(m.nb);
         for (int k = 0; k < m.nb; ++k) {
-            int pairs = 0, r2 = 0;
-            for (int r = 0; r < T.n[s]; ++r)
-                pairs += active(s, k, r, &r2) && r2 > r;
-            most = std::max(most, pairs);
+            const int i = std::min(m.bi[k], m.bj[k]), j = std::max(m.bi[k], m.bj[k]);
+            const uint32_t mask = (1u << i) | (1u << j);
+            const uint32_t between = ((1u << j) - 1u) & ~((2u << i) - 1u);
+            Gate &G = gates[s][k];
+            for (int r = 0; r < T.n[s]; ++r) {
+                const uint32_t p = pat[s][r];
+                if (((p >> i) ^ (p >> j)) & 1u) {
+                    const int r2 = rank_of[s][p ^ mask];
+                    if (r2 > r) {
+                        G.prs.push_back({r, r2});
+                        G.sgn.push_back((uint32_t)(popc(p & between) & 1) << 15);
+                    }
+                }
+            }
+            used = std::max(used, pair_slots(G.prs, R, G.slot));
         }
-    T.xch = (2 * most + 15) & ~15;
+    }
+    T.xch = (used + 15) & ~15;
     if (T.xch + kZero > 0x7FFF || lds_bytes(T) > 160 * 1024)
         return fail(HUBBARD_ERR_ARG, "sector gate pairs do not fit the workgroup's LDS");
     std::vector<uint16_t> codes;
@@ -882,29 +941,20 @@ hubbard_status build_tables(const Model &m, Tables &T)
         const int R = rpt_of(T.n[s]);
         auto entry = [&](int r) { return (size_t)code_index(R, r % kT, r / kT); };
         for (int k = 0; k < m.nb; ++k) {
-            const int i = std::min(m.bi[k], m.bj[k]), j = std::max(m.bi[k], m.bj[k]);
-            const uint32_t between = ((1u << j) - 1u) & ~((2u << i) - 1u);
+            const Gate &G = gates[s][k];
             T.tab[s][k] = (int)codes.size();
             const size_t at = codes.size();
             codes.resize(at + (size_t)kT * rp_of(R), (uint16_t)T.xch);
-            std::vector<int> slot((size_t)R * kT, -1);   // per element (rank): pair slot
-            uint32_t pairs = 0;
-            for (int r = 0; r < T.n[s]; ++r) {
-                int r2 = 0;
-                if (active(s, k, r, &r2) && r2 > r) {
-                    const uint32_t sg = (uint32_t)(popc(pat[s][r] & between) & 1) << 15;
-                    slot[r] = (int)(2 * pairs);
-                    slot[r2] = (int)(2 * pairs + 1);
-                    codes[at + entry(r)] = (uint16_t)(slot[r] | sg);
-                    codes[at + entry(r2)] = (uint16_t)(slot[r2] | sg);
-                    ++pairs;
+            std::vector<int> slot((size_t)R * kT, -1);   // per element (rank)
+            for (size_t q = 0; q < G.prs.size(); ++q)
+                for (int h = 0; h < 2; ++h) {
+                    slot[G.prs[q][h]] = G.slot[2 * q + h];
+                    codes[at + entry(G.prs[q][h])] = (uint16_t)(G.slot[2 * q + h] | G.sgn[q]);
                 }
-            }
-            // per group of 16 threads and register (the lanes of one 16-byte
-            // LDS access that share the banks): the zero slot its inactive
-            // elements read, one per half of the group, in a bank group that
-            // the group's active reads leave free (slot mod 16, and slot mod 8
-            // within the half: 64 banks serve 16 lanes at a time, 32 banks 8)
+            // per group of 16 threads and register (the lanes one cycle of a
+            // 16-byte LDS read serves): the zero slot its inactive elements
+            // read, one per half of the group, in a bank group (slot mod 16)
+            // that the group's other reads leave free
             for (int e0 = 0; e0 < R * kT; e0 += 16) {
                 uint32_t taken = 0, u8[2] = {0, 0};
                 for (int e = e0; e < e0 + 16; ++e)
