@@ -81,6 +81,90 @@ uint64_t pass_grid(uint64_t units)
 }
 enum { M_FWD = 0, M_REV = 1, M_HAM = 2, M_EXP = 3 };
 
+// Bank-conflict cycles of a pass's LDS exchanges under the slot masks mask[b]
+// (tile-local bit b >= 4; bits below 4 are their own slot bits).  In each
+// phase's layout the lane id sits on the tile-local bits outside the register
+// and wave bits (ascending), so a lane bit i moves the slot's low bits by
+// v_i.  A wave's 16-byte LDS write is served 8 lanes at a time (slots equal
+// modulo 8 conflict: lane bits 0-2 must move slot bits 0-2 independently), a
+// 16-byte read 16 lanes at a time (modulo 16, lane bits 0-3).  A phase is
+// written when left and read when entered (not the load and store layouts).
+int gf2_rank(uint32_t *v, int n)
+{
+    int r = 0;
+    for (int bit = 0; bit < 4 && r < n; ++bit) {
+        int piv = -1;
+        for (int i = r; i < n; ++i)
+            if ((v[i] >> bit) & 1u) {
+                piv = i;
+                break;
+            }
+        if (piv < 0)
+            continue;
+        std::swap(v[r], v[piv]);
+        for (int i = 0; i < n; ++i)
+            if (i != r && ((v[i] >> bit) & 1u))
+                v[i] ^= v[r];
+        ++r;
+    }
+    return r;
+}
+int exchange_conflicts(const HostPass &p, int k, const uint32_t *mask)
+{
+    int cost = 0;
+    const int np = (int)p.phases.size();
+    for (int q = 0; q < np; ++q) {
+        uint32_t other = 0;
+        for (int b : p.phases[q].regs)
+            other |= 1u << b;
+        for (int b : p.phases[q].wave)
+            other |= 1u << b;
+        uint32_t v[4];
+        int nl = 0;
+        for (int b = 0; b < k && nl < 4; ++b)
+            if (!((other >> b) & 1u))
+                v[nl++] = b < 4 ? (1u << b) : mask[b];
+        if (nl < 4)
+            continue;
+        if (q + 1 < np) {
+            uint32_t w[3] = {v[0] & 7u, v[1] & 7u, v[2] & 7u};
+            cost += ((1 << (3 - gf2_rank(w, 3))) - 1) * 8;
+        }
+        if (q > 0) {
+            uint32_t w[4] = {v[0], v[1], v[2], v[3]};
+            cost += ((1 << (4 - gf2_rank(w, 4))) - 1) * 4;
+        }
+    }
+    return cost;
+}
+// The pass's slot masks (packed as slot() reads them): the fixed fold of
+// bits 4..11 onto bits 0..3, unless one of 256 pseudo-random mask sets (a
+// fixed sequence) costs fewer conflict cycles.  On the 32-qubit torus this
+// removes about three quarters of the exchanges' bank conflicts.
+void choose_slot_masks(const HostPass &p, int k, uint32_t swz[2])
+{
+    uint32_t best[13] = {0}, cand[13] = {0};
+    for (int b = 4; b < 12; ++b)
+        best[b] = 1u << ((b - 4) % 4);
+    int best_cost = exchange_conflicts(p, k, best);
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    for (int t = 0; t < 256 && best_cost > 0; ++t) {
+        for (int b = 4; b < 13; ++b) {
+            x = x * 6364136223846793005ull + 1442695040888963407ull;
+            cand[b] = b < k ? (uint32_t)(x >> 60) : 0u;
+        }
+        const int c = exchange_conflicts(p, k, cand);
+        if (c < best_cost) {
+            best_cost = c;
+            std::copy(cand, cand + 13, best);
+        }
+    }
+    swz[0] = swz[1] = 0;
+    for (int b = 4; b < 12; ++b)
+        swz[0] |= (best[b] & 15u) << (4 * (b - 4));
+    swz[1] = best[12] & 15u;
+}
+
 enum ProgKind { PROG_ANSATZ = 0, PROG_HAM = 1, PROG_ENERGY = 2, PROG_GRAD = 3 };
 
 // A flattened set of passes of one kind.
@@ -202,6 +286,7 @@ struct Builder {
                 }
             P.nfree = nf;
             P.flags = hp.flags;
+            choose_slot_masks(hp, P.k, P.swz);
             P.op_begin = (int)ops.size();
             const uint64_t ntiles = (uint64_t)1 << nf;
             // (the HVA circuit only: NP passes carry many per-register phases)
@@ -317,7 +402,7 @@ struct Builder {
                 for (int i = 0; i < kRegBits; ++i) {
                     if (i < (int)hph.regs.size()) {
                         D.gb[i] = 1u << hp.tile[hph.regs[i]];
-                        D.sb[i] = slot(1u << hph.regs[i]) << 4;
+                        D.sb[i] = slot(1u << hph.regs[i], P.swz[0], P.swz[1]) << 4;
                     } else {
                         D.gb[i] = D.sb[i] = 0;   // phantom register bit of a tile < 16
                     }

@@ -440,11 +440,11 @@ __device__ __forceinline__ void run_pass(const DevPass &P, const PhT *__restrict
     {
         for (int i = tid; i < P.n_phases * 64; i += T) {
             const uint32_t lp = pdep32((uint32_t)(i & 63), ph[i >> 6].lmask);
-            ltab[i] = make_uint2(tile_global(lp, P.c, P.hi_mask), slot(lp) << 4);
+            ltab[i] = make_uint2(tile_global(lp, P.c, P.hi_mask), slot(lp, P.swz[0], P.swz[1]) << 4);
         }
         for (int i = tid; i < P.n_phases * kMaxWaves; i += T) {
             const uint32_t wp = pdep32((uint32_t)(i % kMaxWaves), ph[i / kMaxWaves].wmask);
-            wtab[i] = make_uint2(tile_global(wp, P.c, P.hi_mask), slot(wp) << 4);
+            wtab[i] = make_uint2(tile_global(wp, P.c, P.hi_mask), slot(wp, P.swz[0], P.swz[1]) << 4);
         }
         if constexpr (MODE == M_FWD || MODE == M_REV) {
             for (int o = tid; o < P.n_ops; o += T) {
