@@ -82,7 +82,7 @@ uint64_t pass_grid(uint64_t units)
 enum { M_FWD = 0, M_REV = 1, M_HAM = 2, M_EXP = 3 };
 
 // Bank-conflict cycles of a pass's LDS exchanges under the slot masks mask[b]
-// (tile-local bit b >= 4; bits below 4 are their own slot bits).  In each
+// (the low four slot bits that tile-local bit b moves).  In each
 // phase's layout the lane id sits on the tile-local bits outside the register
 // and wave bits (ascending), so a lane bit i moves the slot's low bits by
 // v_i.  A wave's 16-byte LDS write is served 8 lanes at a time (slots equal
@@ -123,7 +123,7 @@ int exchange_conflicts(const HostPass &p, int k, const uint32_t *mask)
         int nl = 0;
         for (int b = 0; b < k && nl < 4; ++b)
             if (!((other >> b) & 1u))
-                v[nl++] = b < 4 ? (1u << b) : mask[b];
+                v[nl++] = mask[b];
         if (nl < 4)
             continue;
         if (q + 1 < np) {
@@ -137,32 +137,42 @@ int exchange_conflicts(const HostPass &p, int k, const uint32_t *mask)
     }
     return cost;
 }
-// The pass's slot masks (packed as slot() reads them): the fixed fold of
-// bits 4..11 onto bits 0..3, unless one of 256 pseudo-random mask sets (a
-// fixed sequence) costs fewer conflict cycles.  On the 32-qubit torus this
-// removes about three quarters of the exchanges' bank conflicts.
+// The pass's slot masks (packed as slot() reads them): the identity on bits
+// 0..3 with the fixed fold of bits 4..11 onto them, unless one of 256
+// pseudo-random mask sets (a fixed sequence; bits 0..3 an invertible
+// matrix) costs fewer conflict cycles.  On the 32-qubit torus every pass
+// gets a conflict-free set.
 void choose_slot_masks(const HostPass &p, int k, uint32_t swz[2])
 {
     uint32_t best[13] = {0}, cand[13] = {0};
-    for (int b = 4; b < 12; ++b)
-        best[b] = 1u << ((b - 4) % 4);
+    for (int b = 0; b < 12; ++b)
+        best[b] = 1u << (b % 4);
     int best_cost = exchange_conflicts(p, k, best);
     uint64_t x = 0x9E3779B97F4A7C15ull;
+    auto next4 = [&x]() {
+        x = x * 6364136223846793005ull + 1442695040888963407ull;
+        return (uint32_t)(x >> 60);
+    };
     for (int t = 0; t < 256 && best_cost > 0; ++t) {
-        for (int b = 4; b < 13; ++b) {
-            x = x * 6364136223846793005ull + 1442695040888963407ull;
-            cand[b] = b < k ? (uint32_t)(x >> 60) : 0u;
-        }
+        uint32_t low[4];
+        do {
+            for (int b = 0; b < 4; ++b)
+                cand[b] = low[b] = next4();
+        } while (gf2_rank(low, 4) < 4);
+        for (int b = 4; b < 13; ++b)
+            cand[b] = b < k ? next4() : 0u;
         const int c = exchange_conflicts(p, k, cand);
         if (c < best_cost) {
             best_cost = c;
             std::copy(cand, cand + 13, best);
         }
     }
-    swz[0] = swz[1] = 0;
+    swz[0] = 0;
     for (int b = 4; b < 12; ++b)
         swz[0] |= (best[b] & 15u) << (4 * (b - 4));
     swz[1] = best[12] & 15u;
+    for (int b = 0; b < 4; ++b)
+        swz[1] |= (best[b] & 15u) << (4 + 4 * b);
 }
 
 enum ProgKind { PROG_ANSATZ = 0, PROG_HAM = 1, PROG_ENERGY = 2, PROG_GRAD = 3 };

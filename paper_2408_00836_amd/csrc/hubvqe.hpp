@@ -66,19 +66,25 @@ struct DevOp {
 };
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
 
-// LDS slot of tile-local index l in the exchange buffer: the low four bits
-// are XORed with a 4-bit mask per set bit 4..12 of l (nibble b - 4 of s0 for
-// bits 4..11, s1 for bit 12), chosen per pass so that the 16-byte slots a
-// wave touches in one access spread over the banks.  Linear over GF(2),
-// hence a bijection on [0, 2^k), and slot(a ^ b) = slot(a) ^ slot(b).
+// LDS slot of tile-local index l in the exchange buffer: the high bits are
+// l's, the low four bits are A (l & 15) XOR a 4-bit mask per set bit 4..12
+// of l, with A an invertible 4 x 4 matrix over GF(2) (its columns in bits
+// 4..19 of s1) and the masks in nibble b - 4 of s0 (bits 4..11) and bits
+// 0..3 of s1 (bit 12), chosen per pass so that the 16-byte slots a wave
+// touches in one access spread over the banks.  Linear over GF(2), hence a
+// bijection on [0, 2^k), and slot(a ^ b) = slot(a) ^ slot(b).
 __host__ __device__ inline uint32_t slot(uint32_t l, uint32_t s0, uint32_t s1)
 {
     uint32_t f = ((l >> 12) & 1u) ? (s1 & 15u) : 0u;
 #pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if ((l >> b) & 1u)
+            f ^= (s1 >> (4 + 4 * b)) & 15u;
+#pragma unroll
     for (int b = 4; b < 12; ++b)
         if ((l >> b) & 1u)
             f ^= (s0 >> (4 * (b - 4))) & 15u;
-    return l ^ f;
+    return (l & ~15u) | f;
 }
 
 // Register layout of one phase of a pass (64 bytes).  Each thread holds 16
@@ -131,7 +137,7 @@ struct DevPass {
     int32_t tbits;         // thread-id bits: a workgroup has 2^tbits threads
     uint32_t hi_mask;      // global bits of tile bits c..k-1 (tile bits 0..c-1 = global 0..c-1)
     uint32_t free_mask;    // global bits not in the tile (the tile id is deposited here)
-    uint32_t swz[2];       // slot() masks of the tile-local bits 4..12 (bank spreading)
+    uint32_t swz[2];       // slot() masks of the tile-local bits 0..12 (bank spreading)
 };
 
 // One instance of a batched energy+gradient evaluation: its model tables,
