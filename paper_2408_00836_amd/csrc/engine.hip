@@ -882,13 +882,14 @@ size_t vec_bytes(const hubbard_model *h) { return ((size_t)1 << h->m.nq) * 16u; 
 
 // energy_grad's psi and lambda (2^n amplitudes each) share the first
 // 2 * 2^n amplitudes of the workspace for n > kBlockBits: blocks of
-// 2^kBlockBits amplitudes (16 MiB) of psi and lambda alternate.  A
+// 2^kBlockBits amplitudes (1 MiB) of psi and lambda alternate.  A
 // one-vector pass then streams over the whole 2 * 2^n region.  On MI355X
-// at 32 qubits this took the forward passes from 2.86 s to 2.62 s per
-// evaluation (one-vector streaming over a single contiguous 64 GiB range
+// at 32 qubits the interleave took the forward passes from 2.86 s to 2.62 s
+// per evaluation (one-vector streaming over a single contiguous 64 GiB range
 // ran at 5.1 TB/s in a probe, over both 64 GiB halves of a 128 GiB region
-// at 6.1 TB/s).
-constexpr int kBlockBits = 20;
+// at 6.1 TB/s); 1 MiB blocks beat 16 MiB ones by about 1 % per evaluation
+// (the reverse passes; 64 KiB to 8 MiB blocks measured).
+constexpr int kBlockBits = 16;
 VecLayout grad_layout(const hubbard_model *h)
 {
     VecLayout vl;
